@@ -70,6 +70,7 @@ def dev():
     if _dev is None:
         if not os.path.exists(_DEV_SO):
             raise RuntimeError("libgen_dev.so is not built; run __graft_entry__.build()")
+        import torch  # noqa: F401  (bind to torch's HIP runtime: one runtime per process)
         L = ctypes.CDLL(_DEV_SO)
         u64, vp = ctypes.c_uint64, ctypes.c_void_p
         L.gen_dev_uniform_u32.argtypes = [u64, vp, u64, u64, vp]

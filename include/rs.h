@@ -1,0 +1,160 @@
+/*
+ * rs.h -- C ABI of librs, an MI355X (gfx950) integer-sorting library for the
+ * hot path of Gerbessiotis, "Integer sorting on multicores: some (experiments
+ * and) observations" (arXiv 1708.09495).
+ *
+ * The paper states the problem as sorting n integer keys with radix-r
+ * count-sort rounds (Section 3, Eq. Ts and Eq. Tp) or with the block
+ * networks BTN and OET on p sorted runs (Section 2, Section 3 Eq. To and
+ * Eq. Tb).  This library sorts unsigned 32- or 64-bit keys ascending.
+ *
+ * Conventions for every entry point:
+ *   - All array pointers are DEVICE pointers owned by the caller.  The
+ *     library never allocates, frees or retains them.  Scratch memory comes
+ *     only from the caller's workspace `ws` of `ws_bytes` bytes, which must be
+ *     at least rs_workspace_bytes(...) for the same arguments and 256-byte
+ *     aligned.  The workspace must not be shared by calls that may overlap.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Work is enqueued
+ *     on it and the call returns without waiting: results are valid once the
+ *     stream has been synchronised.
+ *   - Argument errors are detected on the host before anything is enqueued
+ *     and returned synchronously; nothing is written in that case.  A HIP
+ *     launch failure returns RS_ERR_HIP.  Device faults surface at the
+ *     caller's next synchronisation, as for any HIP work.
+ *   - `in == out` (and vals_in == vals_out) is allowed: the sort is then in
+ *     place.  Other overlaps are not allowed.
+ *   - n = 0 is valid and enqueues nothing.
+ *   - The library never aborts the process.
+ */
+#ifndef RS_H
+#define RS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    RS_OK = 0,
+    RS_ERR_INVALID = 1,      /* bad argument (NULL pointer, bad width, ...)   */
+    RS_ERR_UNSUPPORTED = 2,  /* valid request this build cannot serve         */
+    RS_ERR_WORKSPACE = 3,    /* workspace NULL, too small or misaligned       */
+    RS_ERR_HIP = 4           /* a HIP runtime call failed                     */
+} rs_status;
+
+typedef enum {
+    RS_ALGO_AUTO = 0,       /* tuned choice for the size                     */
+    RS_ALGO_LSD = 1,        /* radix-2^b count-sort rounds (Section 3)       */
+    RS_ALGO_BTN = 2,        /* block bitonic on p runs (Section 2, Eq. Tb)   */
+    RS_ALGO_OET = 3,        /* block odd-even transposition (Sec. 2, Eq. To) */
+    RS_ALGO_LEARNED = 4,    /* learned-CDF buckets, LSD fallback             */
+    RS_ALGO_LDS_RADIX = 5   /* one workgroup's LDS radix sort (small n)      */
+} rs_algo;
+
+typedef enum {
+    RS_OP_SORT = 0,       /* rs_sort_u32 / rs_sort_u64                 */
+    RS_OP_SORT_KV = 1,    /* rs_sort_kv                                */
+    RS_OP_BATCH = 2,      /* rs_sort_batch_u32                         */
+    RS_OP_SEGMENTED = 3   /* rs_sort_segmented                         */
+} rs_op;
+
+/* Facts about the most recent call made on the calling host thread. */
+typedef struct {
+    int32_t algo;               /* rs_algo actually run                        */
+    int32_t radix_bits;         /* b of the count-sort rounds (0 if none)      */
+    int32_t passes;             /* count-sort rounds run: ceil(w/b)            */
+    int32_t runs_p;             /* p of BTN/OET (runs per instance)            */
+    int64_t network_stages;     /* BTN: lg p (lg p+1)/2; OET: p                */
+    int32_t tile_keys;          /* keys per workgroup tile of the LSD rounds   */
+    int32_t fallback;           /* learned path: 1 if plain LSD was used       */
+    int64_t buckets_overflowed; /* learned path: buckets over LDS capacity     */
+    int64_t keys_overflowed;    /* learned path: keys in those buckets         */
+    double  train_loss;         /* learned path: final training loss           */
+    uint32_t device_error;      /* bit 0: a bounded wait gave up; bit 1: a computed
+                                   destination was out of range (not written)    */
+    int32_t hip_error;          /* hipError_t of the failing call when RS_ERR_HIP */
+} rs_stats;
+
+/* Sort n uint32 keys ascending.  Follows Section 3: ceil(32/b) stable
+ * count-sort rounds at radix 2^b from the least significant digit, each a
+ * per-tile digit histogram, a device-wide exclusive scan and a stable
+ * rank-and-scatter.  radix_bits in [1, 16]; 0 = default (8).  algo: AUTO, LSD,
+ * or BTN/OET/LDS_RADIX for n <= rs_small_capacity(4) (one workgroup).
+ * Layout: `in` and `out` are dense arrays of n keys. */
+rs_status rs_sort_u32(const uint32_t* in, uint32_t* out, size_t n, int radix_bits,
+                      rs_algo algo, void* ws, size_t ws_bytes, void* stream);
+
+/* As rs_sort_u32 for uint64 keys: ceil(64/b) rounds.  algo LEARNED sorts
+ * with learned-CDF buckets (keys only). */
+rs_status rs_sort_u64(const uint64_t* in, uint64_t* out, size_t n, int radix_bits,
+                      rs_algo algo, void* ws, size_t ws_bytes, void* stream);
+
+/* Stable key-value sort: keys of key_bytes (4 or 8), values of val_bytes
+ * (4 or 8) move with their key; equal keys keep their input order.
+ * algo: AUTO, LSD or LEARNED (LEARNED needs key_bytes = 8). */
+rs_status rs_sort_kv(const void* keys_in, const void* vals_in, void* keys_out, void* vals_out,
+                     size_t n, int key_bytes, int val_bytes, int radix_bits, rs_algo algo,
+                     void* ws, size_t ws_bytes, void* stream);
+
+/* Sort `count` independent uint32 arrays of n keys each, stored back to back
+ * (array i at in + i*n), one workgroup per array, in one launch.  algo BTN
+ * or OET: the block networks of Section 2 on p runs of n_pad/p keys, where
+ * n_pad is the next power of two >= n and the tail is padded with
+ * UINT32_MAX; p = 0 picks the tuned p.  algo LDS_RADIX: radix-2^8 rounds in
+ * LDS.  AUTO: the tuned fastest.  Requires n <= rs_small_capacity(4). */
+rs_status rs_sort_batch_u32(const uint32_t* in, uint32_t* out, size_t n, size_t count,
+                            rs_algo algo, int p, void* ws, size_t ws_bytes, void* stream);
+
+/* Batched segmented sort: segment s is [offsets[s], offsets[s+1]) of `in`
+ * (offsets: DEVICE array of num_segments+1 non-decreasing int64,
+ * offsets[0] = 0, offsets[num_segments] = total_n; empty segments allowed;
+ * no segment may exceed 2^32 - 1 keys).  Each segment is sorted
+ * independently, all in one persistent launch; segments that fit one
+ * workgroup's LDS are sorted there (BTN/OET/LDS radix per the tuning
+ * table), larger ones by radix-2^b rounds.  algo: AUTO (tuned), BTN, OET or
+ * LDS_RADIX forces the small-segment algorithm.  `in == out` is allowed. */
+rs_status rs_sort_segmented(const uint32_t* in, uint32_t* out, const int64_t* offsets,
+                            size_t num_segments, int64_t total_n, rs_algo algo, void* ws,
+                            size_t ws_bytes, void* stream);
+
+/* Bytes of workspace the call (op, n, ...) needs.  For RS_OP_BATCH, n is
+ * the array length and num_segments the count; for RS_OP_SEGMENTED, n is
+ * total_n.  Returns 0 for arguments no call would accept. */
+size_t rs_workspace_bytes(int op, size_t n, int key_bytes, int val_bytes, int radix_bits,
+                          rs_algo algo, size_t num_segments);
+
+/* Largest n one workgroup can sort in LDS for keys of key_bytes bytes. */
+size_t rs_small_capacity(int key_bytes);
+
+/* Static description of a status code. */
+const char* rs_status_string(rs_status s);
+
+/* Copies the calling thread's stats of its most recent call.  If that call
+ * enqueued device work whose outcome the stats report (device_error, the
+ * learned path's overflow counts), this synchronises that call's stream. */
+rs_status rs_get_stats(rs_stats* out);
+
+/* ---- kernel timing (benchmarks) ---------------------------------------- */
+
+typedef struct {
+    char name[32];     /* kernel name                                          */
+    int64_t launches;  /* launches recorded since the last read                */
+    double total_ms;   /* summed duration between the bracketing HIP events    */
+} rs_kernel_time;
+
+/* on = 1: from now on every kernel launch of this library is bracketed by a
+ * pair of HIP events recorded on the launch's own stream (process-wide).
+ * on = 0 stops recording.  Recording adds two event records per launch. */
+rs_status rs_profile_enable(int on);
+
+/* Waits for every recorded event, writes at most `max` per-kernel totals to
+ * `out` (host array) and clears the record.  Returns the number of entries
+ * written, or -1 on a HIP error. */
+int rs_profile_read(rs_kernel_time* out, int max);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -23,15 +23,34 @@ NPARAM = 32 + 32 + 32 * 32 + 32 + 32 + 1
 H = 32
 
 
+_STAMP = _SO + ".cpu"
+
+
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def build(force: bool = False) -> str:
     """Compile ``oracle.c`` into ``liboracle.so`` with gcc -O2 -march=native
-    (the paper's flags, Section 4)."""
+    (the paper's flags, Section 4).  -march=native ties the library to the
+    host CPU, so it is rebuilt when loaded on a different CPU model."""
     src = os.path.join(_HERE, "oracle.c")
-    if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(src):
+    stale = (not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(src)
+             or not os.path.exists(_STAMP) or open(_STAMP).read() != _cpu_model())
+    if force or stale:
         tmp = _SO + ".tmp%d" % os.getpid()
         subprocess.check_call(["gcc", "-O2", "-march=native", "-std=c99", "-fPIC", "-shared",
                                "-Wall", "-Wextra", "-o", tmp, src, "-lm"])
         os.replace(tmp, _SO)
+        with open(_STAMP, "w") as f:
+            f.write(_cpu_model())
     return _SO
 
 
@@ -43,8 +62,7 @@ class Counters(ctypes.Structure):
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_SO):
-            build()
+        build()
         L = ctypes.CDLL(_SO)
         vp, sz, i, i64 = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int, ctypes.c_int64
         cp = ctypes.POINTER(Counters)

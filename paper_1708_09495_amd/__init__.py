@@ -1,0 +1,227 @@
+"""Python binding of librs (include/rs.h): argument marshalling only.
+
+Every function has the name of the C entry point it calls and forwards
+device pointers, sizes and the HIP stream.  PyTorch supplies device memory
+(tensors) and streams; every step of every sort runs in librs's HIP kernels.
+If librs.so is missing the binding raises: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librs.so")
+
+RS_OK, RS_ERR_INVALID, RS_ERR_UNSUPPORTED, RS_ERR_WORKSPACE, RS_ERR_HIP = range(5)
+RS_ALGO_AUTO, RS_ALGO_LSD, RS_ALGO_BTN, RS_ALGO_OET, RS_ALGO_LEARNED, RS_ALGO_LDS_RADIX = range(6)
+RS_OP_SORT, RS_OP_SORT_KV, RS_OP_BATCH, RS_OP_SEGMENTED = range(4)
+
+EXPORTS = ["rs_sort_u32", "rs_sort_u64", "rs_sort_kv", "rs_sort_batch_u32", "rs_sort_segmented",
+           "rs_workspace_bytes", "rs_small_capacity", "rs_status_string", "rs_get_stats",
+           "rs_profile_enable", "rs_profile_read"]
+
+
+class RsError(RuntimeError):
+    def __init__(self, code, where):
+        msg = "%s failed: %s (%d)" % (where, rs_status_string(code), code)
+        if code == RS_ERR_HIP:
+            try:
+                msg += ", hipError %d" % rs_get_stats().hip_error
+            except Exception:
+                pass
+        super().__init__(msg)
+        self.code = code
+
+
+class rs_stats(ctypes.Structure):
+    _fields_ = [("algo", ctypes.c_int32), ("radix_bits", ctypes.c_int32),
+                ("passes", ctypes.c_int32), ("runs_p", ctypes.c_int32),
+                ("network_stages", ctypes.c_int64), ("tile_keys", ctypes.c_int32),
+                ("fallback", ctypes.c_int32), ("buckets_overflowed", ctypes.c_int64),
+                ("keys_overflowed", ctypes.c_int64), ("train_loss", ctypes.c_double),
+                ("device_error", ctypes.c_uint32), ("hip_error", ctypes.c_int32)]
+
+
+class rs_kernel_time(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_int64),
+                ("total_ms", ctypes.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded librs (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("librs.so is not built (%s); run __graft_entry__.build()" % LIB_PATH)
+        # PyTorch ships its own libamdhip64 with the same soname as the
+        # system one librs links.  Loading torch first makes librs bind to
+        # that already-loaded runtime, so the process has one HIP runtime
+        # (two copies cannot share the device).
+        _torch()
+        L = ctypes.CDLL(LIB_PATH)
+        vp, sz, i = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int
+        L.rs_sort_u32.argtypes = [vp, vp, sz, i, i, vp, sz, vp]
+        L.rs_sort_u64.argtypes = [vp, vp, sz, i, i, vp, sz, vp]
+        L.rs_sort_kv.argtypes = [vp, vp, vp, vp, sz, i, i, i, i, vp, sz, vp]
+        L.rs_sort_batch_u32.argtypes = [vp, vp, sz, sz, i, i, vp, sz, vp]
+        L.rs_sort_segmented.argtypes = [vp, vp, vp, sz, ctypes.c_int64, i, vp, sz, vp]
+        L.rs_workspace_bytes.argtypes = [i, sz, i, i, i, i, sz]
+        L.rs_workspace_bytes.restype = sz
+        L.rs_small_capacity.argtypes = [i]
+        L.rs_small_capacity.restype = sz
+        L.rs_status_string.argtypes = [i]
+        L.rs_status_string.restype = ctypes.c_char_p
+        L.rs_get_stats.argtypes = [ctypes.POINTER(rs_stats)]
+        L.rs_profile_enable.argtypes = [i]
+        L.rs_profile_read.argtypes = [ctypes.POINTER(rs_kernel_time), i]
+        L.rs_profile_read.restype = i
+        for f in ("rs_profile_enable", "rs_sort_u32", "rs_sort_u64", "rs_sort_kv", "rs_sort_batch_u32",
+                  "rs_sort_segmented", "rs_get_stats"):
+            getattr(L, f).restype = i
+        _lib = L
+    return _lib
+
+
+# ---- marshalling helpers -------------------------------------------------
+
+def _torch():
+    import torch
+    return torch
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream(stream):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _check_dev(t, bytes_, what):
+    if not t.is_cuda or not t.is_contiguous() or t.element_size() != bytes_:
+        raise ValueError("%s must be a contiguous CUDA tensor of %d-byte elements" % (what, bytes_))
+
+
+def _workspace(need, ws, device):
+    if ws is None:
+        ws = _torch().empty(max(int(need), 1), dtype=_torch().uint8, device=device)
+    return ws
+
+
+def _call(rc, where):
+    if rc != RS_OK:
+        raise RsError(rc, where)
+
+
+# ---- the C entry points --------------------------------------------------
+
+def rs_workspace_bytes(op, n, key_bytes=4, val_bytes=0, radix_bits=0, algo=RS_ALGO_AUTO,
+                       num_segments=0):
+    return lib().rs_workspace_bytes(op, n, key_bytes, val_bytes, radix_bits, algo, num_segments)
+
+
+def rs_small_capacity(key_bytes=4):
+    return lib().rs_small_capacity(key_bytes)
+
+
+def rs_status_string(code):
+    return lib().rs_status_string(code).decode()
+
+
+def rs_get_stats():
+    s = rs_stats()
+    _call(lib().rs_get_stats(ctypes.byref(s)), "rs_get_stats")
+    return s
+
+
+def rs_profile_enable(on=True):
+    _call(lib().rs_profile_enable(1 if on else 0), "rs_profile_enable")
+
+
+def rs_profile_read():
+    """{kernel name: (launches, total ms)} since the last read (waits on the
+    recorded events)."""
+    buf = (rs_kernel_time * 32)()
+    k = lib().rs_profile_read(buf, 32)
+    if k < 0:
+        raise RsError(RS_ERR_HIP, "rs_profile_read")
+    return {buf[i].name.decode(): (int(buf[i].launches), float(buf[i].total_ms)) for i in range(k)}
+
+
+def rs_sort_u32(keys_in, keys_out=None, radix_bits=0, algo=RS_ALGO_AUTO, ws=None, stream=None):
+    """Sort a CUDA tensor of 4-byte keys (read as uint32) ascending."""
+    _check_dev(keys_in, 4, "keys_in")
+    keys_out = keys_in.new_empty(keys_in.shape) if keys_out is None else keys_out
+    _check_dev(keys_out, 4, "keys_out")
+    n = keys_in.numel()
+    ws = _workspace(rs_workspace_bytes(RS_OP_SORT, n, 4, 0, radix_bits, algo), ws, keys_in.device)
+    _call(lib().rs_sort_u32(_ptr(keys_in), _ptr(keys_out), n, radix_bits, algo, _ptr(ws),
+                            ws.numel(), _stream(stream)), "rs_sort_u32")
+    return keys_out
+
+
+def rs_sort_u64(keys_in, keys_out=None, radix_bits=0, algo=RS_ALGO_AUTO, ws=None, stream=None):
+    """Sort a CUDA tensor of 8-byte keys (read as uint64) ascending."""
+    _check_dev(keys_in, 8, "keys_in")
+    keys_out = keys_in.new_empty(keys_in.shape) if keys_out is None else keys_out
+    _check_dev(keys_out, 8, "keys_out")
+    n = keys_in.numel()
+    ws = _workspace(rs_workspace_bytes(RS_OP_SORT, n, 8, 0, radix_bits, algo), ws, keys_in.device)
+    _call(lib().rs_sort_u64(_ptr(keys_in), _ptr(keys_out), n, radix_bits, algo, _ptr(ws),
+                            ws.numel(), _stream(stream)), "rs_sort_u64")
+    return keys_out
+
+
+def rs_sort_kv(keys_in, vals_in, keys_out=None, vals_out=None, radix_bits=0, algo=RS_ALGO_AUTO,
+               ws=None, stream=None):
+    """Stable key-value sort; keys and values of 4 or 8 bytes."""
+    kb, vb = keys_in.element_size(), vals_in.element_size()
+    _check_dev(keys_in, kb, "keys_in")
+    _check_dev(vals_in, vb, "vals_in")
+    keys_out = keys_in.new_empty(keys_in.shape) if keys_out is None else keys_out
+    vals_out = vals_in.new_empty(vals_in.shape) if vals_out is None else vals_out
+    _check_dev(keys_out, kb, "keys_out")
+    _check_dev(vals_out, vb, "vals_out")
+    n = keys_in.numel()
+    if vals_in.numel() != n:
+        raise ValueError("keys and values differ in length")
+    ws = _workspace(rs_workspace_bytes(RS_OP_SORT_KV, n, kb, vb, radix_bits, algo), ws,
+                    keys_in.device)
+    _call(lib().rs_sort_kv(_ptr(keys_in), _ptr(vals_in), _ptr(keys_out), _ptr(vals_out), n, kb, vb,
+                           radix_bits, algo, _ptr(ws), ws.numel(), _stream(stream)), "rs_sort_kv")
+    return keys_out, vals_out
+
+
+def rs_sort_batch_u32(keys_in, n, count, keys_out=None, algo=RS_ALGO_AUTO, p=0, ws=None,
+                      stream=None):
+    """Sort `count` back-to-back arrays of n uint32 keys each."""
+    _check_dev(keys_in, 4, "keys_in")
+    if keys_in.numel() != n * count:
+        raise ValueError("keys_in must hold n * count keys")
+    keys_out = keys_in.new_empty(keys_in.shape) if keys_out is None else keys_out
+    _check_dev(keys_out, 4, "keys_out")
+    ws = _workspace(rs_workspace_bytes(RS_OP_BATCH, n, 4, 0, 0, algo, count), ws, keys_in.device)
+    _call(lib().rs_sort_batch_u32(_ptr(keys_in), _ptr(keys_out), n, count, algo, p, _ptr(ws),
+                                  ws.numel(), _stream(stream)), "rs_sort_batch_u32")
+    return keys_out
+
+
+def rs_sort_segmented(keys_in, offsets, keys_out=None, algo=RS_ALGO_AUTO, ws=None, stream=None):
+    """Sort each segment [offsets[s], offsets[s+1]) of a uint32 tensor."""
+    _check_dev(keys_in, 4, "keys_in")
+    _check_dev(offsets, 8, "offsets")
+    keys_out = keys_in.new_empty(keys_in.shape) if keys_out is None else keys_out
+    _check_dev(keys_out, 4, "keys_out")
+    S = offsets.numel() - 1
+    total = keys_in.numel()
+    ws = _workspace(rs_workspace_bytes(RS_OP_SEGMENTED, total, 4, 0, 0, algo, S), ws,
+                    keys_in.device)
+    _call(lib().rs_sort_segmented(_ptr(keys_in), _ptr(keys_out), _ptr(offsets), S, total, algo,
+                                  _ptr(ws), ws.numel(), _stream(stream)), "rs_sort_segmented")
+    return keys_out

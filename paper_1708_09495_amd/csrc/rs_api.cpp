@@ -1,0 +1,254 @@
+// rs_api.cpp -- the extern "C" entry points of librs (declared in
+// include/rs.h): argument checks, planning, workspace checks and dispatch to
+// the kernels' launchers.  Nothing here waits on the device except
+// rs_get_stats.
+#include <string.h>
+
+#include "rs_internal.hpp"
+
+namespace rs {
+namespace {
+
+struct CallState {
+    rs_stats stats{};
+    hipStream_t stream = nullptr;
+    const uint32_t* status = nullptr;   // device status word of the last call
+    bool pending = false;               // stats still need the device's word
+};
+thread_local CallState g_call;
+
+void begin_call(int algo) {
+    (void)hipGetLastError();  // drop an error left by an earlier, unrelated call
+    memset(&g_call.stats, 0, sizeof(g_call.stats));
+    g_call.stats.algo = algo;
+    g_call.stream = nullptr;
+    g_call.status = nullptr;
+    g_call.pending = false;
+}
+
+rs_status check_ws(const void* ws, size_t ws_bytes, size_t need) {
+    if (need == 0) return RS_OK;
+    if (!ws || ws_bytes < need || (reinterpret_cast<uintptr_t>(ws) % ALIGN) != 0)
+        return RS_ERR_WORKSPACE;
+    return RS_OK;
+}
+
+int default_bits(int bits) { return bits == 0 ? 8 : bits; }
+
+// Keys (and optionally values) through the LSD rounds.
+rs_status sort_lsd(const void* kin, void* kout, const void* vin, void* vout, size_t n, int kb,
+                   int vb, int bits, void* ws, size_t ws_bytes, hipStream_t st) {
+    LsdPlan p;
+    if (!lsd_plan(n, kb, vb, bits, &p)) return RS_ERR_UNSUPPORTED;
+    begin_call(RS_ALGO_LSD);
+    g_call.stats.radix_bits = bits;
+    g_call.stats.passes = p.passes;
+    g_call.stats.tile_keys = p.tile;
+    if (n == 0) return RS_OK;
+    rs_status rc = check_ws(ws, ws_bytes, p.total);
+    if (rc != RS_OK) return rc;
+    rc = lsd_run(p, kin, kout, vin, vout, ws, st);
+    if (rc == RS_OK) {
+        g_call.stream = st;
+        g_call.status = reinterpret_cast<const uint32_t*>(static_cast<unsigned char*>(ws) + p.off_status);
+        g_call.pending = true;
+    }
+    return rc;
+}
+
+bool overlaps(const void* a, size_t abytes, const void* b, size_t bbytes) {
+    const uintptr_t x = reinterpret_cast<uintptr_t>(a), y = reinterpret_cast<uintptr_t>(b);
+    return x < y + bbytes && y < x + abytes;
+}
+
+rs_status sort_keys_common(const void* kin, void* kout, const void* vin, void* vout, size_t n,
+                           int kb, int vb, int bits, rs_algo algo, void* ws, size_t ws_bytes,
+                           void* stream) {
+    if (kb != 4 && kb != 8) return RS_ERR_INVALID;
+    if (vb != 0 && vb != 4 && vb != 8) return RS_ERR_INVALID;
+    if (bits < 0 || bits > 16) return RS_ERR_INVALID;
+    if (n > 0 && (!kin || !kout)) return RS_ERR_INVALID;
+    if (vb && n > 0 && (!vin || !vout)) return RS_ERR_INVALID;
+    if (n > 0 && kin != kout && overlaps(kin, n * kb, kout, n * kb)) return RS_ERR_INVALID;
+    if (vb && n > 0 && vin != vout && overlaps(vin, n * vb, vout, n * vb)) return RS_ERR_INVALID;
+    if ((uint64_t)n >= (1ull << 40)) return RS_ERR_UNSUPPORTED;
+    bits = default_bits(bits);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    switch (algo) {
+        case RS_ALGO_AUTO:
+        case RS_ALGO_LSD:
+            return sort_lsd(kin, kout, vin, vout, n, kb, vb, bits, ws, ws_bytes, st);
+        default:
+            return RS_ERR_UNSUPPORTED;
+    }
+}
+
+}  // namespace
+
+rs_status hip_fail(hipError_t e) {
+    g_call.stats.hip_error = (int32_t)e;
+    return RS_ERR_HIP;
+}
+
+}  // namespace rs
+
+using namespace rs;
+
+extern "C" {
+
+rs_status rs_sort_u32(const uint32_t* in, uint32_t* out, size_t n, int radix_bits, rs_algo algo,
+                      void* ws, size_t ws_bytes, void* stream) {
+    return sort_keys_common(in, out, nullptr, nullptr, n, 4, 0, radix_bits, algo, ws, ws_bytes,
+                            stream);
+}
+
+rs_status rs_sort_u64(const uint64_t* in, uint64_t* out, size_t n, int radix_bits, rs_algo algo,
+                      void* ws, size_t ws_bytes, void* stream) {
+    return sort_keys_common(in, out, nullptr, nullptr, n, 8, 0, radix_bits, algo, ws, ws_bytes,
+                            stream);
+}
+
+rs_status rs_sort_kv(const void* keys_in, const void* vals_in, void* keys_out, void* vals_out,
+                     size_t n, int key_bytes, int val_bytes, int radix_bits, rs_algo algo,
+                     void* ws, size_t ws_bytes, void* stream) {
+    if (val_bytes != 4 && val_bytes != 8) return RS_ERR_INVALID;
+    return sort_keys_common(keys_in, keys_out, vals_in, vals_out, n, key_bytes, val_bytes,
+                            radix_bits, algo, ws, ws_bytes, stream);
+}
+
+rs_status rs_sort_batch_u32(const uint32_t*, uint32_t*, size_t, size_t, rs_algo, int, void*,
+                            size_t, void*) {
+    return RS_ERR_UNSUPPORTED;
+}
+
+rs_status rs_sort_segmented(const uint32_t*, uint32_t*, const int64_t*, size_t, int64_t, rs_algo,
+                            void*, size_t, void*) {
+    return RS_ERR_UNSUPPORTED;
+}
+
+size_t rs_workspace_bytes(int op, size_t n, int key_bytes, int val_bytes, int radix_bits,
+                          rs_algo algo, size_t num_segments) {
+    (void)algo;
+    (void)num_segments;
+    radix_bits = default_bits(radix_bits);
+    if (op == RS_OP_SORT || op == RS_OP_SORT_KV) {
+        LsdPlan p;
+        if (!lsd_plan(n, key_bytes, op == RS_OP_SORT ? 0 : val_bytes, radix_bits, &p)) return 0;
+        return p.total;
+    }
+    return 0;
+}
+
+size_t rs_small_capacity(int key_bytes) {
+    return key_bytes == 4 ? 16384 : (key_bytes == 8 ? 8192 : 0);
+}
+
+const char* rs_status_string(rs_status s) {
+    switch (s) {
+        case RS_OK: return "ok";
+        case RS_ERR_INVALID: return "invalid argument";
+        case RS_ERR_UNSUPPORTED: return "unsupported request";
+        case RS_ERR_WORKSPACE: return "workspace missing, too small or misaligned";
+        case RS_ERR_HIP: return "HIP runtime error";
+    }
+    return "unknown status";
+}
+
+rs_status rs_get_stats(rs_stats* out) {
+    if (!out) return RS_ERR_INVALID;
+    if (g_call.pending) {
+        uint32_t word = 0;
+        hipError_t e = hipStreamSynchronize(g_call.stream);
+        if (e == hipSuccess) e = hipMemcpy(&word, g_call.status, sizeof(word), hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return hip_fail(e);
+        g_call.stats.device_error = word;
+        g_call.pending = false;
+    }
+    *out = g_call.stats;
+    return RS_OK;
+}
+
+}  // extern "C"
+
+// ---- kernel timing --------------------------------------------------------
+#include <mutex>
+#include <vector>
+
+namespace rs {
+bool g_prof_on = false;
+namespace {
+const char* const KNAMES[KID_COUNT_] = {
+    "fill", "hist", "onesweep", "copy", "batch", "seg_plan", "seg",
+    "learn_sample", "learn_train", "learn_split", "learn_assign", "learn_bucket", "learn_check"};
+struct Mark {
+    int kid;
+    hipEvent_t b, e;
+};
+std::mutex g_prof_mu;
+std::vector<Mark> g_marks;
+std::vector<hipEvent_t> g_free_events;
+hipEvent_t take_event() {
+    if (!g_free_events.empty()) {
+        hipEvent_t e = g_free_events.back();
+        g_free_events.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+}  // namespace
+
+void prof_record(hipStream_t st, int kid, int phase) {
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    if (phase == 0) {
+        Mark m{kid, take_event(), nullptr};
+        if (m.b) hipEventRecord(m.b, st);
+        g_marks.push_back(m);
+    } else {
+        for (auto it = g_marks.rbegin(); it != g_marks.rend(); ++it) {
+            if (it->kid == kid && it->e == nullptr) {
+                it->e = take_event();
+                if (it->e) hipEventRecord(it->e, st);
+                break;
+            }
+        }
+    }
+}
+}  // namespace rs
+
+extern "C" rs_status rs_profile_enable(int on) {
+    rs::g_prof_on = on != 0;
+    return RS_OK;
+}
+
+extern "C" int rs_profile_read(rs_kernel_time* out, int max) {
+    using namespace rs;
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    double tot[KID_COUNT_] = {0};
+    int64_t cnt[KID_COUNT_] = {0};
+    int rc = 0;
+    for (auto& m : g_marks) {
+        if (m.b && m.e) {
+            if (hipEventSynchronize(m.e) != hipSuccess) rc = -1;
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, m.b, m.e) != hipSuccess) rc = -1;
+            tot[m.kid] += ms;
+            cnt[m.kid] += 1;
+        }
+        if (m.b) g_free_events.push_back(m.b);
+        if (m.e) g_free_events.push_back(m.e);
+    }
+    g_marks.clear();
+    if (rc) return -1;
+    int k = 0;
+    for (int i = 0; i < KID_COUNT_ && k < max; ++i) {
+        if (!cnt[i]) continue;
+        memset(out[k].name, 0, sizeof(out[k].name));
+        strncpy(out[k].name, KNAMES[i], sizeof(out[k].name) - 1);
+        out[k].launches = cnt[i];
+        out[k].total_ms = tot[i];
+        ++k;
+    }
+    return k;
+}

@@ -1,0 +1,83 @@
+// rs_internal.hpp -- host-side plans and launchers shared by the librs
+// translation units.  Not part of the C ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/rs.h"
+
+namespace rs {
+
+constexpr size_t ALIGN = 256;
+inline size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
+
+// Bounded waits: a look-back that polls this many times without progress
+// records an error in the workspace status word and gives up, so every
+// kernel always terminates.
+constexpr uint32_t SPIN_LIMIT = 1u << 20;
+constexpr uint32_t STATUS_SPIN = 1u;   // a bounded wait gave up
+constexpr uint32_t STATUS_RANGE = 2u;  // a computed destination was out of range (not written)
+
+// ---- kernel timing: every launch site brackets its launch with
+//      prof(st, id, 0) ... prof(st, id, 1); a no-op unless enabled.
+enum KernelId {
+    KID_FILL = 0,
+    KID_HIST,
+    KID_ONESWEEP,
+    KID_COPY,
+    KID_BATCH,
+    KID_SEG_PLAN,
+    KID_SEG,
+    KID_LEARN_SAMPLE,
+    KID_LEARN_TRAIN,
+    KID_LEARN_SPLIT,
+    KID_LEARN_ASSIGN,
+    KID_LEARN_BUCKET,
+    KID_LEARN_CHECK,
+    KID_COUNT_
+};
+extern bool g_prof_on;
+void prof_record(hipStream_t st, int kid, int phase);
+inline void prof(hipStream_t st, int kid, int phase) {
+    if (g_prof_on) prof_record(st, kid, phase);
+}
+
+// ---- LSD radix sort (count-sort rounds, Section 3) -----------------------
+struct LsdPlan {
+    size_t n = 0;
+    int kb = 4, vb = 0;      // key / value bytes
+    int bits = 8;            // radix bits b
+    int passes = 0;          // ceil(8*kb / b)
+    int R = 256;             // 2^b
+    int tile = 0;            // keys per workgroup tile
+    size_t tiles = 0;
+    bool lb64 = false;       // 64-bit look-back words (n >= 2^30)
+    size_t lb_words = 0;     // look-back words per pass (tiles * R)
+    // workspace layout (byte offsets)
+    size_t off_status = 0, off_ctr = 0, off_hist = 0, off_lb = 0, off_tk = 0, off_tv = 0;
+    size_t zero_bytes = 0;   // bytes from off_status that must be zeroed (status, ctr, hist)
+    size_t total = 0;
+};
+
+// Plans an LSD sort; returns false when (kb, vb, bits) is not supported.
+bool lsd_plan(size_t n, int kb, int vb, int bits, LsdPlan* p);
+
+// Enqueues the whole LSD sort on `st`.  `ws` holds at least p.total bytes.
+rs_status lsd_run(const LsdPlan& p, const void* kin, void* kout, const void* vin, void* vout,
+                  void* ws, hipStream_t st);
+
+// Records the HIP error of a failed launch or runtime call for rs_get_stats
+// and returns RS_ERR_HIP.
+rs_status hip_fail(hipError_t e);
+// hipGetLastError after a launch, mapped to a status.
+inline rs_status launch_status() {
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? RS_OK : hip_fail(e);
+}
+
+// Zero-fill of device memory by a kernel (no hipMemsetAsync, so callers may
+// capture the stream into a graph).
+rs_status fill_u32(void* p, size_t words, uint32_t v, hipStream_t st);
+
+}  // namespace rs

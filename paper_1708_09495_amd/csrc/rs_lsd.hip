@@ -1,0 +1,455 @@
+// rs_lsd.hip -- the count-sort rounds of LSD radix sort on gfx950.
+//
+// Section 3 of the paper prices one count-sort round as a first read of the
+// keys to count digits, a prefix over the count array, and a second read plus
+// a write that places every key in input order (3Ng + 2NG), and the parallel
+// form adds the exchange of the p count arrays (2prg).  On one MI355X the
+// rounds are organised as:
+//
+//   k_fill      zero the status word, tile counters and global histograms;
+//   k_hist      ONE read of the keys that counts the digits of every round at
+//               once (the global digit histogram does not depend on the order
+//               of the keys, so all rounds' counts come from the input) and
+//               zeroes the look-back words;
+//   k_onesweep  one launch per round: each workgroup takes the next tile id,
+//               ranks its keys stably by digit (wave64 ballot match plus
+//               per-wave LDS counters), publishes its per-digit counts,
+//               looks back over earlier tiles for their exclusive prefix
+//               (decoupled look-back, Merrill and Garland 2016, with flag and
+//               count packed in one word), reorders the tile by digit in LDS
+//               and writes each digit's run to HBM contiguously.
+//
+// The paper's count exchange (2prg) is the look-back table: R words per
+// tile.  Per round HBM traffic is one read and one write of the keys (and
+// values); the histogram read is paid once for all rounds.
+#include <type_traits>
+
+#include "rs_dev.h"
+#include "rs_internal.hpp"
+
+namespace rs {
+namespace {
+
+constexpr int NT = 512;          // threads per onesweep workgroup
+constexpr int NW = NT / WAVE;    // waves per workgroup
+constexpr int HIST_NT = 256;
+constexpr uint32_t FLAG_AGG = 1, FLAG_PRE = 2;
+
+template <typename LB> struct LBW;
+template <> struct LBW<uint32_t> {
+    static constexpr int SH = 30;
+    static constexpr uint32_t MASK = (1u << 30) - 1;
+};
+template <> struct LBW<uint64_t> {
+    static constexpr int SH = 62;
+    static constexpr uint64_t MASK = (1ull << 62) - 1;
+};
+
+template <int VB> struct ValT { using type = uint32_t; };
+template <> struct ValT<8> { using type = uint64_t; };
+
+__global__ void k_fill(uint32_t* __restrict__ p, uint64_t n, uint32_t v) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = v;
+}
+
+// Digit histograms of every round in one read of the keys.  LDS holds
+// passes * 2^bits counters; the zeroing of the look-back words (`zp`,
+// `zwords` 32-bit words) rides along on the same grid.
+template <typename K>
+__global__ __launch_bounds__(HIST_NT) void k_hist(const K* __restrict__ keys, uint64_t n, int bits,
+                                                   int passes, uint32_t* __restrict__ ghist,
+                                                   uint32_t* __restrict__ zp, uint64_t zwords) {
+    extern __shared__ uint32_t h[];
+    const int R = 1 << bits;
+    const uint32_t mask = (uint32_t)R - 1;
+    const int tot = passes * R;
+    for (int i = threadIdx.x; i < tot; i += HIST_NT) h[i] = 0;
+    __syncthreads();
+    const uint64_t stride = (uint64_t)gridDim.x * HIST_NT;
+    uint64_t i = (uint64_t)blockIdx.x * HIST_NT + threadIdx.x;
+    // four independent loads in flight per thread
+    for (; i + 3 * stride < n; i += 4 * stride) {
+        K k0 = keys[i], k1 = keys[i + stride], k2 = keys[i + 2 * stride], k3 = keys[i + 3 * stride];
+        for (int p = 0; p < passes; ++p) {
+            const int s = p * bits;
+            atomicAdd(&h[p * R + ((uint32_t)(k0 >> s) & mask)], 1u);
+            atomicAdd(&h[p * R + ((uint32_t)(k1 >> s) & mask)], 1u);
+            atomicAdd(&h[p * R + ((uint32_t)(k2 >> s) & mask)], 1u);
+            atomicAdd(&h[p * R + ((uint32_t)(k3 >> s) & mask)], 1u);
+        }
+    }
+    for (; i < n; i += stride) {
+        K k0 = keys[i];
+        for (int p = 0; p < passes; ++p)
+            atomicAdd(&h[p * R + ((uint32_t)(k0 >> (p * bits)) & mask)], 1u);
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j < tot; j += HIST_NT)
+        if (h[j]) atomicAdd(&ghist[j], h[j]);
+    const uint64_t gstride = (uint64_t)gridDim.x * HIST_NT;
+    for (uint64_t j = (uint64_t)blockIdx.x * HIST_NT + threadIdx.x; j < zwords; j += gstride) zp[j] = 0u;
+}
+
+// One stable count-sort round over tiles of NT*ITEMS keys.
+//   MAXB  : largest radix bits the LDS arrays are sized for (bits <= MAXB)
+//   VB    : value bytes (0 = keys only)
+//   LB    : look-back word type
+template <typename K, int VB, int MAXB, int ITEMS, typename LB>
+__global__ __launch_bounds__(NT) void k_onesweep(
+    const K* __restrict__ kin, K* __restrict__ kout, const void* __restrict__ vin_,
+    void* __restrict__ vout_, uint64_t n, int shift, int bits, uint32_t* __restrict__ tile_ctr,
+    LB* __restrict__ lb, const uint32_t* __restrict__ ghist, uint32_t* __restrict__ status) {
+    using V = typename ValT<VB>::type;
+    constexpr int RMAX = 1 << MAXB;
+    constexpr int T = NT * ITEMS;
+    constexpr int PER = (RMAX + NT - 1) / NT;  // digits per thread in the digit scans
+    constexpr size_t KEYB = (size_t)T * sizeof(K);
+    constexpr size_t VALB = VB ? (size_t)T * sizeof(V) : 0;
+    constexpr size_t CNTB = (size_t)NW * RMAX * sizeof(uint16_t);
+    constexpr size_t UB = KEYB > VALB ? (KEYB > CNTB ? KEYB : CNTB) : (VALB > CNTB ? VALB : CNTB);
+    static_assert(T < 65536, "wave counters are 16-bit");
+
+    __shared__ __align__(16) unsigned char u_raw[UB];
+    __shared__ int64_t goff[RMAX];    // global destination of slot 0 of each digit
+    __shared__ uint32_t tot[RMAX];    // this tile's count per digit
+    __shared__ uint32_t loc[RMAX];    // first LDS slot of each digit
+    __shared__ uint32_t wsum[NW + 1];
+    __shared__ uint32_t s_tile;
+
+    uint16_t* wcnt = reinterpret_cast<uint16_t*>(u_raw);
+    K* skeys = reinterpret_cast<K*>(u_raw);
+    V* svals = reinterpret_cast<V*>(u_raw);
+    const V* vin = reinterpret_cast<const V*>(vin_);
+    V* vout = reinterpret_cast<V*>(vout_);
+
+    const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int R = 1 << bits;
+    const uint32_t dmask = (uint32_t)R - 1;
+
+    if (tid == 0) s_tile = atomicAdd(tile_ctr, 1u);
+    for (int i = tid; i < NW * R; i += NT) wcnt[i] = 0;
+    __syncthreads();
+    const uint32_t tile = s_tile;
+    const uint64_t base = (uint64_t)tile * T;
+    const uint32_t nvalid = (uint32_t)((n - base) < (uint64_t)T ? (n - base) : (uint64_t)T);
+
+    // ---- load: wave w owns positions [w*64*ITEMS, (w+1)*64*ITEMS), item i
+    //      of lane l is position w*64*ITEMS + i*64 + l, so processing items
+    //      in order and lanes in order visits the tile in input order.
+    K k[ITEMS];
+    V v[VB ? ITEMS : 1];
+    const uint32_t wb = wave * (ITEMS * WAVE);
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+        const uint32_t j = wb + i * WAVE + lane;
+        k[i] = j < nvalid ? kin[base + j] : KeyMax<K>::v;
+    }
+    if constexpr (VB != 0) {
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+            const uint32_t j = wb + i * WAVE + lane;
+            v[i] = j < nvalid ? vin[base + j] : V(0);
+        }
+    }
+    // Slots past nvalid hold the largest key, whose digit is the largest
+    // that occurs in this round; they come last in input order, so they take
+    // the last LDS slots and never shift a real key.
+
+    // ---- rank: per-wave counters, one ballot match per item
+    uint32_t dr[ITEMS];  // digit | rank-in-wave << 16
+    uint16_t* wc = wcnt + wave * R;
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+        const uint32_t d = (uint32_t)(k[i] >> shift) & dmask;
+        const uint64_t m = match_digit<MAXB>(d, bits);
+        const uint32_t lt = mbcnt(m);
+        const uint32_t cnt = (uint32_t)__popcll(m);
+        const uint32_t c = wc[d];
+        if (lt + 1 == cnt) wc[d] = (uint16_t)(c + cnt);
+        dr[i] = d | ((c + lt) << 16);
+    }
+    __syncthreads();
+
+    // ---- per digit: exclusive prefix over waves, tile total
+    for (int d = tid; d < R; d += NT) {
+        uint32_t s = 0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+            const uint32_t c = wcnt[w * R + d];
+            wcnt[w * R + d] = (uint16_t)s;
+            s += c;
+        }
+        tot[d] = s;
+        if (tile != 0)
+            st_agent(&lb[(size_t)tile * R + d], (LB)(((LB)FLAG_AGG << LBW<LB>::SH) | (LB)s));
+    }
+    __syncthreads();
+
+    // ---- local exclusive scan over digits -> first LDS slot of each digit
+    {
+        uint32_t part[PER];
+        uint32_t s = 0;
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int d = tid * PER + q;
+            part[q] = d < R ? tot[d] : 0u;
+            s += part[q];
+        }
+        uint32_t total;
+        uint32_t ex = block_excl_scan<NT>(s, wsum, &total);
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int d = tid * PER + q;
+            if (d < R) loc[d] = ex;
+            ex += part[q];
+        }
+    }
+
+    // ---- global position of each digit's first key in this tile
+    if (tile == 0) {
+        // Tile 0 starts the chain: its exclusive prefix is the exclusive
+        // scan of the round's global histogram.
+        uint32_t part[PER];
+        uint32_t s = 0;
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int d = tid * PER + q;
+            part[q] = d < R ? ghist[d] : 0u;
+            s += part[q];
+        }
+        uint32_t total;
+        uint32_t ex = block_excl_scan<NT>(s, wsum, &total);
+        // (the block scan's barrier orders the loc[] writes above)
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int d = tid * PER + q;
+            if (d < R) {
+                st_agent(&lb[d], (LB)(((LB)FLAG_PRE << LBW<LB>::SH) | (LB)(ex + tot[d])));
+                goff[d] = (int64_t)ex - (int64_t)loc[d];
+            }
+            ex += part[q];
+        }
+    } else {
+        __syncthreads();  // loc[] complete
+        for (int d = tid; d < R; d += NT) {
+            LB excl = 0;
+            uint32_t j = tile - 1;
+            uint32_t spins = 0;
+            while (true) {
+                const LB w = ld_agent(&lb[(size_t)j * R + d]);
+                const uint32_t f = (uint32_t)(w >> LBW<LB>::SH);
+                if (f == 0) {
+                    if (++spins > SPIN_LIMIT) {
+                        atomicOr(status, STATUS_SPIN);
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+                    continue;
+                }
+                excl += w & LBW<LB>::MASK;
+                if (f == FLAG_PRE) break;
+                --j;
+            }
+            st_agent(&lb[(size_t)tile * R + d],
+                     (LB)(((LB)FLAG_PRE << LBW<LB>::SH) | (LB)(excl + tot[d])));
+            goff[d] = (int64_t)excl - (int64_t)loc[d];
+        }
+    }
+    __syncthreads();
+
+    // ---- LDS slot of every key, then the reorder
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+        const uint32_t d = dr[i] & 0xFFFFu;
+        dr[i] = loc[d] + wcnt[wave * R + d] + (dr[i] >> 16);
+    }
+    __syncthreads();  // the counters share LDS with the key buffer
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) skeys[dr[i]] = k[i];
+    __syncthreads();
+
+    // ---- write out: consecutive slots of one digit go to consecutive
+    //      addresses, so each digit's run is a coalesced burst.
+    int64_t dst[VB ? ITEMS : 1];
+#pragma unroll
+    for (int q = 0; q < ITEMS; ++q) {
+        const uint32_t j = q * NT + tid;
+        if (j < nvalid) {
+            const K key = skeys[j];
+            const uint32_t d = (uint32_t)(key >> shift) & dmask;
+            int64_t o = goff[d] + (int64_t)j;
+            // o is in [0, n) whenever the prefixes are right; the guard keeps
+            // a wrong prefix (or an abandoned look-back) from writing outside
+            // the array and reports it instead.
+            if ((uint64_t)o >= n) {
+                atomicOr(status, STATUS_RANGE);
+                o = -1;
+            } else {
+                kout[o] = key;
+            }
+            if constexpr (VB != 0) dst[q] = o;
+        }
+    }
+    if constexpr (VB != 0) {
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) svals[dr[i]] = v[i];
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < ITEMS; ++q) {
+            const uint32_t j = q * NT + tid;
+            if (j < nvalid && dst[q] >= 0) vout[dst[q]] = svals[j];
+        }
+    }
+}
+
+template <typename K, int VB, int MAXB, int ITEMS, typename LB>
+hipError_t launch_pass(const LsdPlan& p, const void* src, void* dst, const void* vsrc, void* vdst,
+                       int pass, unsigned char* ws, hipStream_t st) {
+    uint32_t* ctr = reinterpret_cast<uint32_t*>(ws + p.off_ctr) + pass;
+    LB* lb = reinterpret_cast<LB*>(ws + p.off_lb) + (size_t)pass * p.lb_words;
+    const uint32_t* gh = reinterpret_cast<const uint32_t*>(ws + p.off_hist) + (size_t)pass * p.R;
+    uint32_t* status = reinterpret_cast<uint32_t*>(ws + p.off_status);
+    prof(st, KID_ONESWEEP, 0);
+    hipLaunchKernelGGL((k_onesweep<K, VB, MAXB, ITEMS, LB>), dim3((unsigned)p.tiles), dim3(NT), 0, st,
+                       (const K*)src, (K*)dst, vsrc, vdst, (uint64_t)p.n, pass * p.bits, p.bits, ctr,
+                       lb, gh, status);
+    prof(st, KID_ONESWEEP, 1);
+    return hipGetLastError();
+}
+
+template <typename K, int VB, int MAXB, int ITEMS>
+hipError_t launch_pass_lb(const LsdPlan& p, const void* src, void* dst, const void* vsrc,
+                          void* vdst, int pass, unsigned char* ws, hipStream_t st) {
+    return p.lb64 ? launch_pass<K, VB, MAXB, ITEMS, uint64_t>(p, src, dst, vsrc, vdst, pass, ws, st)
+                  : launch_pass<K, VB, MAXB, ITEMS, uint32_t>(p, src, dst, vsrc, vdst, pass, ws, st);
+}
+
+template <typename K, int VB>
+hipError_t launch_pass_k(const LsdPlan& p, const void* src, void* dst, const void* vsrc,
+                         void* vdst, int pass, unsigned char* ws, hipStream_t st) {
+    constexpr int ITEMS = sizeof(K) == 4 ? 16 : 8;
+    if (p.bits <= 8) return launch_pass_lb<K, VB, 8, ITEMS>(p, src, dst, vsrc, vdst, pass, ws, st);
+    return launch_pass_lb<K, VB, 11, ITEMS>(p, src, dst, vsrc, vdst, pass, ws, st);
+}
+
+hipError_t launch_pass_any(const LsdPlan& p, const void* src, void* dst, const void* vsrc,
+                           void* vdst, int pass, unsigned char* ws, hipStream_t st) {
+    if (p.kb == 4) {
+        if (p.vb == 0) return launch_pass_k<uint32_t, 0>(p, src, dst, vsrc, vdst, pass, ws, st);
+        if (p.vb == 4) return launch_pass_k<uint32_t, 4>(p, src, dst, vsrc, vdst, pass, ws, st);
+        return launch_pass_k<uint32_t, 8>(p, src, dst, vsrc, vdst, pass, ws, st);
+    }
+    if (p.vb == 0) return launch_pass_k<uint64_t, 0>(p, src, dst, vsrc, vdst, pass, ws, st);
+    if (p.vb == 4) return launch_pass_k<uint64_t, 4>(p, src, dst, vsrc, vdst, pass, ws, st);
+    return launch_pass_k<uint64_t, 8>(p, src, dst, vsrc, vdst, pass, ws, st);
+}
+
+}  // namespace
+
+rs_status fill_u32(void* p, size_t words, uint32_t v, hipStream_t st) {
+    if (!words) return RS_OK;
+    size_t g = (words + 255) / 256;
+    if (g > 4096) g = 4096;
+    prof(st, KID_FILL, 0);
+    hipLaunchKernelGGL(k_fill, dim3((unsigned)g), dim3(256), 0, st, (uint32_t*)p, (uint64_t)words, v);
+    prof(st, KID_FILL, 1);
+    return launch_status();
+}
+
+bool lsd_plan(size_t n, int kb, int vb, int bits, LsdPlan* p) {
+    if ((kb != 4 && kb != 8) || (vb != 0 && vb != 4 && vb != 8) || bits < 1 || bits > 11) return false;
+    LsdPlan q;
+    q.n = n;
+    q.kb = kb;
+    q.vb = vb;
+    q.bits = bits;
+    q.passes = (8 * kb + bits - 1) / bits;
+    q.R = 1 << bits;
+    q.tile = NT * (kb == 4 ? 16 : 8);
+    q.tiles = n ? (n + q.tile - 1) / q.tile : 0;
+    q.lb64 = n >= (1ull << 30);
+    q.lb_words = q.tiles * (size_t)q.R;
+    size_t off = 0;
+    q.off_status = off;
+    off += ALIGN;
+    q.off_ctr = off;
+    off += align_up(sizeof(uint32_t) * q.passes);
+    q.off_hist = off;
+    off += align_up(sizeof(uint32_t) * (size_t)q.passes * q.R);
+    q.zero_bytes = off - q.off_status;
+    q.off_lb = off;
+    off += align_up((q.lb64 ? 8 : 4) * q.lb_words * q.passes);
+    q.off_tk = off;
+    off += align_up((size_t)kb * n);
+    q.off_tv = off;
+    off += align_up((size_t)vb * n);
+    q.total = off;
+    *p = q;
+    return true;
+}
+
+rs_status lsd_run(const LsdPlan& p, const void* kin, void* kout, const void* vin, void* vout,
+                  void* ws_, hipStream_t st) {
+    if (p.n == 0) return RS_OK;
+    unsigned char* ws = static_cast<unsigned char*>(ws_);
+    rs_status rc = fill_u32(ws + p.off_status, p.zero_bytes / 4, 0u, st);
+    if (rc != RS_OK) return rc;
+    // one read of the keys for every round's histogram (+ look-back zeroing)
+    {
+        const size_t lb_u32 = (p.lb64 ? 2 : 1) * p.lb_words * p.passes;
+        size_t g = (p.n + HIST_NT * 16 - 1) / (HIST_NT * 16);
+        size_t gz = (lb_u32 + HIST_NT * 16 - 1) / (HIST_NT * 16);
+        if (gz > g) g = gz;
+        if (g > 2048) g = 2048;
+        if (g < 1) g = 1;
+        const size_t shm = sizeof(uint32_t) * (size_t)p.passes * p.R;
+        uint32_t* gh = reinterpret_cast<uint32_t*>(ws + p.off_hist);
+        uint32_t* zp = reinterpret_cast<uint32_t*>(ws + p.off_lb);
+        prof(st, KID_HIST, 0);
+        if (p.kb == 4)
+            hipLaunchKernelGGL(k_hist<uint32_t>, dim3((unsigned)g), dim3(HIST_NT), shm, st,
+                               (const uint32_t*)kin, (uint64_t)p.n, p.bits, p.passes, gh, zp,
+                               (uint64_t)lb_u32);
+        else
+            hipLaunchKernelGGL(k_hist<uint64_t>, dim3((unsigned)g), dim3(HIST_NT), shm, st,
+                               (const uint64_t*)kin, (uint64_t)p.n, p.bits, p.passes, gh, zp,
+                               (uint64_t)lb_u32);
+        prof(st, KID_HIST, 1);
+        if ((rc = launch_status()) != RS_OK) return rc;
+    }
+    // Buffers: the rounds alternate between `out` and the workspace copy so
+    // that the last round writes `out`.  For an in-place sort with an odd
+    // round count the first round cannot write `out` (it is being read), so
+    // the rounds end in the workspace and one copy follows.
+    void* tk = ws + p.off_tk;
+    void* tv = ws + p.off_tv;
+    const int P = p.passes;
+    const bool inplace = kin == kout;
+    const bool copy_back = inplace && (P % 2 == 1);
+    const void* src = kin;
+    const void* vsrc = vin;
+    for (int j = 0; j < P; ++j) {
+        const int left = P - 1 - j;  // rounds after this one
+        bool to_out = (left % 2 == 0);
+        if (copy_back) to_out = !to_out;
+        void* dst = to_out ? kout : tk;
+        void* vdst = to_out ? vout : tv;
+        hipError_t e = launch_pass_any(p, src, dst, vsrc, vdst, j, ws, st);
+        if (e != hipSuccess) return hip_fail(e);
+        src = dst;
+        vsrc = vdst;
+    }
+    if (copy_back) {
+        prof(st, KID_COPY, 0);
+        hipError_t e = hipMemcpyAsync(kout, tk, p.n * p.kb, hipMemcpyDeviceToDevice, st);
+        if (e == hipSuccess && p.vb)
+            e = hipMemcpyAsync(vout, tv, p.n * p.vb, hipMemcpyDeviceToDevice, st);
+        if (e != hipSuccess) return hip_fail(e);
+        prof(st, KID_COPY, 1);
+    }
+    return RS_OK;
+}
+
+}  // namespace rs

@@ -1,0 +1,135 @@
+"""GPU parity of the LSD radix sort (count-sort rounds of Section 3) through
+the C ABI: every output is compared bit for bit with the oracle on the same
+seeded input, including the order of equal keys in key-value sorts."""
+import numpy as np
+import pytest
+
+from gpu_util import first_mismatch, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+SIZES = [0, 1, 2, 63, 64, 65, 4095, 4096, 4097, 8191, 8192, 8193, 100_000, 1 << 20,
+         (1 << 20) + 12_345]
+
+
+@pytest.fixture(scope="module")
+def rs():
+    import paper_1708_09495_amd as rs
+    rs.lib()
+    return rs
+
+
+def _u32(seed, n):
+    import gen
+    return gen.uniform_u32(seed, n)
+
+
+def _check(out, ref, what):
+    i = first_mismatch(out, ref)
+    assert i is None, "%s: first mismatch at %d: got %d want %d" % (what, i, out[i], ref[i])
+
+
+@pytest.mark.parametrize("bits", [8, 11, 4, 1])
+def test_u32_uniform(rs, orc, bits):
+    import gen
+    sizes = SIZES if bits >= 4 else [0, 1, 65, 8193, 100_000]
+    for n in sizes:
+        print("case u32 n=%d bits=%d" % (n, bits), flush=True)
+        a = _u32(gen.S0 + 1 + n, n)
+        out = to_host(rs.rs_sort_u32(to_dev(a), radix_bits=bits, algo=rs.RS_ALGO_LSD), np.uint32)
+        _check(out, orc.lsd(a, bits), "u32 n=%d b=%d" % (n, bits))
+        assert rs.rs_get_stats().device_error == 0
+        assert rs.rs_get_stats().passes == -(-32 // bits)
+
+
+@pytest.mark.parametrize("case", ["equal", "sorted", "reverse", "high", "low", "max", "few"])
+@pytest.mark.parametrize("bits", [8, 11])
+def test_u32_structured(rs, orc, case, bits):
+    rng = np.random.default_rng(7)
+    n = 300_001
+    a = {
+        "equal": np.full(n, 0xDEADBEEF, np.uint32),
+        "sorted": np.sort(rng.integers(0, 2**32, n, dtype=np.uint64)).astype(np.uint32),
+        "reverse": np.sort(rng.integers(0, 2**32, n, dtype=np.uint64))[::-1].astype(np.uint32),
+        "high": (rng.integers(0, 256, n).astype(np.uint32) << np.uint32(24)),
+        "low": rng.integers(0, 256, n).astype(np.uint32),
+        "max": np.where(rng.random(n) < 0.5, 2**32 - 1, rng.integers(0, 2**32, n)).astype(np.uint32),
+        "few": rng.choice(np.array([3, 2**31, 77, 2**32 - 1], np.uint32), n),
+    }[case]
+    out = to_host(rs.rs_sort_u32(to_dev(a), radix_bits=bits, algo=rs.RS_ALGO_LSD), np.uint32)
+    _check(out, orc.lsd(a, bits), case)
+
+
+@pytest.mark.parametrize("bits", [8, 11])
+def test_u64_uniform(rs, orc, bits):
+    import gen
+    for n in [1, 65, 4097, 100_000, (1 << 20) + 3]:
+        a = gen.uniform_u64(gen.S0 + 2 + n, n)
+        out = to_host(rs.rs_sort_u64(to_dev(a), radix_bits=bits, algo=rs.RS_ALGO_LSD), np.uint64)
+        _check(out, orc.lsd(a, bits), "u64 n=%d" % n)
+
+
+@pytest.mark.parametrize("kdt,vdt", [(np.uint32, np.uint32), (np.uint32, np.uint64),
+                                     (np.uint64, np.uint32), (np.uint64, np.uint64)])
+@pytest.mark.parametrize("bits", [8, 11])
+def test_kv_stable(rs, orc, kdt, vdt, bits):
+    rng = np.random.default_rng(11)
+    for n in [1, 1000, 8193, 250_000]:
+        keys = rng.integers(0, 1000, n).astype(kdt)            # many ties
+        keys[::7] = rng.integers(0, np.iinfo(kdt).max, keys[::7].size, dtype=kdt)
+        vals = np.arange(n, dtype=vdt)
+        ko, vo = rs.rs_sort_kv(to_dev(keys), to_dev(vals), radix_bits=bits, algo=rs.RS_ALGO_LSD)
+        ko, vo = to_host(ko, kdt), to_host(vo, vdt)
+        rk, rv = orc.lsd(keys, bits, vals=vals)
+        _check(ko, rk, "kv keys n=%d" % n)
+        _check(vo, rv, "kv vals n=%d" % n)
+        assert orc.check_stable_kv(keys, ko, vo) == 0
+
+
+@pytest.mark.parametrize("bits", [8, 11])
+def test_in_place(rs, orc, bits):
+    import gen
+    n = 200_003
+    a = _u32(gen.S0 + 9, n)
+    t = to_dev(a)
+    rs.rs_sort_u32(t, t, radix_bits=bits, algo=rs.RS_ALGO_LSD)
+    _check(to_host(t, np.uint32), orc.lsd(a, bits), "in place")
+    keys = np.random.default_rng(3).integers(0, 50, n).astype(np.uint32)
+    vals = np.arange(n, dtype=np.uint32)
+    kt, vt = to_dev(keys), to_dev(vals)
+    rs.rs_sort_kv(kt, vt, kt, vt, radix_bits=bits, algo=rs.RS_ALGO_LSD)
+    rk, rv = orc.lsd(keys, bits, vals=vals)
+    _check(to_host(kt, np.uint32), rk, "kv in place keys")
+    _check(to_host(vt, np.uint32), rv, "kv in place vals")
+
+
+def test_repeat_runs_identical(rs):
+    import gen
+    import torch
+    a = to_dev(_u32(gen.S0 + 10, 1 << 20))
+    ref = rs.rs_sort_u32(a, radix_bits=8, algo=rs.RS_ALGO_LSD)
+    ws = torch.empty(rs.rs_workspace_bytes(rs.RS_OP_SORT, a.numel(), 4, 0, 8), dtype=torch.uint8,
+                     device="cuda")
+    out = torch.empty_like(a)
+    for _ in range(30):
+        rs.rs_sort_u32(a, out, radix_bits=8, algo=rs.RS_ALGO_LSD, ws=ws)
+        assert torch.equal(out, ref)
+    assert rs.rs_get_stats().device_error == 0
+
+
+def test_argument_errors(rs):
+    import ctypes
+    import torch
+    L = rs.lib()
+    a = torch.zeros(100, dtype=torch.int32, device="cuda")
+    ws = torch.empty(rs.rs_workspace_bytes(rs.RS_OP_SORT, 100, 4, 0, 8), dtype=torch.uint8,
+                     device="cuda")
+    p = ctypes.c_void_p
+    s = p(torch.cuda.current_stream().cuda_stream)
+    assert L.rs_sort_u32(None, p(a.data_ptr()), 100, 8, 1, p(ws.data_ptr()), ws.numel(), s) == rs.RS_ERR_INVALID
+    assert L.rs_sort_u32(p(a.data_ptr()), p(a.data_ptr() + 4), 100, 8, 1, p(ws.data_ptr()), ws.numel(), s) == rs.RS_ERR_INVALID
+    assert L.rs_sort_u32(p(a.data_ptr()), p(a.data_ptr()), 100, 17, 1, p(ws.data_ptr()), ws.numel(), s) == rs.RS_ERR_INVALID
+    assert L.rs_sort_u32(p(a.data_ptr()), p(a.data_ptr()), 100, 8, 1, p(ws.data_ptr()), 16, s) == rs.RS_ERR_WORKSPACE
+    assert L.rs_sort_u32(p(a.data_ptr()), p(a.data_ptr()), 100, 8, 1, None, 0, s) == rs.RS_ERR_WORKSPACE
+    assert L.rs_sort_kv(p(a.data_ptr()), None, p(a.data_ptr()), None, 100, 4, 3, 8, 1, p(ws.data_ptr()), ws.numel(), s) == rs.RS_ERR_INVALID
+    assert L.rs_sort_u32(None, None, 0, 8, 1, None, 0, s) == rs.RS_OK
