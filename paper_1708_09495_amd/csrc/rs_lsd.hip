@@ -34,6 +34,7 @@ constexpr int NT = 512;          // threads per onesweep workgroup
 constexpr int NW = NT / WAVE;    // waves per workgroup
 constexpr int HIST_NT = 256;
 constexpr uint32_t FLAG_AGG = 1, FLAG_PRE = 2;
+constexpr int LBWIN = 4;         // predecessors read per look-back step
 
 template <typename LB> struct LBW;
 template <> struct LBW<uint32_t> {
@@ -44,6 +45,9 @@ template <> struct LBW<uint64_t> {
     static constexpr int SH = 62;
     static constexpr uint64_t MASK = (1ull << 62) - 1;
 };
+
+// keys per thread of a onesweep tile
+constexpr int lsd_items(int kb, int vb) { return kb == 4 ? (vb == 0 ? 24 : 16) : 8; }
 
 template <int VB> struct ValT { using type = uint32_t; };
 template <> struct ValT<8> { using type = uint64_t; };
@@ -94,30 +98,47 @@ __global__ __launch_bounds__(HIST_NT) void k_hist(const K* __restrict__ keys, ui
 // One stable count-sort round over tiles of NT*ITEMS keys.
 //   MAXB  : largest radix bits the LDS arrays are sized for (bits <= MAXB)
 //   VB    : value bytes (0 = keys only)
-//   LB    : look-back word type
-template <typename K, int VB, int MAXB, int ITEMS, typename LB>
+//   LB    : look-back word type (32-bit while n < 2^30)
+//   OFF   : int32_t destinations while n < 2^31, else int64_t
+//
+// Ranking.  Keys are visited in input order: item i of lane l of wave w is
+// tile position w*64*ITEMS + i*64 + l.  For each item the lanes holding the
+// same digit are found with an LDS match: every lane ORs its lane bit into
+// its wave's slot for the low 8 digit bits, then reads the slot back; OR is
+// order-independent, so the mask is exact and the ranking stable whatever
+// order the LDS serves the atomics in.  Digit bits above the low 8 (b > 8)
+// are matched with one ballot each.  A key's rank among equal digits of its
+// wave is the wave's running count for the digit plus the number of peer
+// lanes below it; the highest peer lane advances the running count and
+// clears the slot.
+template <typename K, int VB, int MAXB, int ITEMS, typename LB, typename OFF>
 __global__ __launch_bounds__(NT) void k_onesweep(
     const K* __restrict__ kin, K* __restrict__ kout, const void* __restrict__ vin_,
     void* __restrict__ vout_, uint64_t n, int shift, int bits, uint32_t* __restrict__ tile_ctr,
     LB* __restrict__ lb, const uint32_t* __restrict__ ghist, uint32_t* __restrict__ status) {
     using V = typename ValT<VB>::type;
     constexpr int RMAX = 1 << MAXB;
+    constexpr int RLO = RMAX < 256 ? RMAX : 256;      // slots of the LDS match
     constexpr int T = NT * ITEMS;
     constexpr int PER = (RMAX + NT - 1) / NT;  // digits per thread in the digit scans
     constexpr size_t KEYB = (size_t)T * sizeof(K);
     constexpr size_t VALB = VB ? (size_t)T * sizeof(V) : 0;
     constexpr size_t CNTB = (size_t)NW * RMAX * sizeof(uint16_t);
-    constexpr size_t UB = KEYB > VALB ? (KEYB > CNTB ? KEYB : CNTB) : (VALB > CNTB ? VALB : CNTB);
+    constexpr size_t MSKB = (size_t)NW * RLO * sizeof(uint64_t);
+    constexpr size_t RANKB = CNTB + MSKB;
+    constexpr size_t UB1 = KEYB > VALB ? KEYB : VALB;
+    constexpr size_t UB = UB1 > RANKB ? UB1 : RANKB;
     static_assert(T < 65536, "wave counters are 16-bit");
 
     __shared__ __align__(16) unsigned char u_raw[UB];
-    __shared__ int64_t goff[RMAX];    // global destination of slot 0 of each digit
+    __shared__ OFF goff[RMAX];        // global destination of slot 0 of each digit
     __shared__ uint32_t tot[RMAX];    // this tile's count per digit
     __shared__ uint32_t loc[RMAX];    // first LDS slot of each digit
     __shared__ uint32_t wsum[NW + 1];
     __shared__ uint32_t s_tile;
 
-    uint16_t* wcnt = reinterpret_cast<uint16_t*>(u_raw);
+    uint64_t* wmask = reinterpret_cast<uint64_t*>(u_raw);          // [NW][RLO]
+    uint16_t* wcnt = reinterpret_cast<uint16_t*>(u_raw + MSKB);    // [NW][R]
     K* skeys = reinterpret_cast<K*>(u_raw);
     V* svals = reinterpret_cast<V*>(u_raw);
     const V* vin = reinterpret_cast<const V*>(vin_);
@@ -125,53 +146,72 @@ __global__ __launch_bounds__(NT) void k_onesweep(
 
     const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int R = 1 << bits;
+    const int lob = bits < 8 ? bits : 8;   // digit bits matched in LDS
     const uint32_t dmask = (uint32_t)R - 1;
+    const uint32_t lomask = (1u << lob) - 1;
 
     if (tid == 0) s_tile = atomicAdd(tile_ctr, 1u);
     for (int i = tid; i < NW * R; i += NT) wcnt[i] = 0;
+    for (int i = tid; i < NW * RLO; i += NT) wmask[i] = 0;
     __syncthreads();
     const uint32_t tile = s_tile;
     const uint64_t base = (uint64_t)tile * T;
     const uint32_t nvalid = (uint32_t)((n - base) < (uint64_t)T ? (n - base) : (uint64_t)T);
+    const bool full = nvalid == (uint32_t)T;
+    const K* __restrict__ tin = kin + base;
 
-    // ---- load: wave w owns positions [w*64*ITEMS, (w+1)*64*ITEMS), item i
-    //      of lane l is position w*64*ITEMS + i*64 + l, so processing items
-    //      in order and lanes in order visits the tile in input order.
+    // ---- load (slots past nvalid hold the largest key: its digit is the
+    //      largest of the round and it comes last in input order, so it takes
+    //      the last LDS slots and never shifts a real key)
     K k[ITEMS];
     V v[VB ? ITEMS : 1];
-    const uint32_t wb = wave * (ITEMS * WAVE);
+    const uint32_t wb = wave * (ITEMS * WAVE) + lane;
+    if (full) {
 #pragma unroll
-    for (int i = 0; i < ITEMS; ++i) {
-        const uint32_t j = wb + i * WAVE + lane;
-        k[i] = j < nvalid ? kin[base + j] : KeyMax<K>::v;
-    }
-    if constexpr (VB != 0) {
+        for (int i = 0; i < ITEMS; ++i) k[i] = tin[wb + i * WAVE];
+    } else {
 #pragma unroll
         for (int i = 0; i < ITEMS; ++i) {
-            const uint32_t j = wb + i * WAVE + lane;
-            v[i] = j < nvalid ? vin[base + j] : V(0);
+            const uint32_t j = wb + i * WAVE;
+            k[i] = j < nvalid ? tin[j] : KeyMax<K>::v;
         }
     }
-    // Slots past nvalid hold the largest key, whose digit is the largest
-    // that occurs in this round; they come last in input order, so they take
-    // the last LDS slots and never shift a real key.
-
-    // ---- rank: per-wave counters, one ballot match per item
-    uint32_t dr[ITEMS];  // digit | rank-in-wave << 16
-    uint16_t* wc = wcnt + wave * R;
+    if constexpr (VB != 0) {
+        const V* __restrict__ vtin = vin + base;
 #pragma unroll
-    for (int i = 0; i < ITEMS; ++i) {
-        const uint32_t d = (uint32_t)(k[i] >> shift) & dmask;
-        const uint64_t m = match_digit<MAXB>(d, bits);
-        const uint32_t lt = mbcnt(m);
-        const uint32_t cnt = (uint32_t)__popcll(m);
-        const uint32_t c = wc[d];
-        if (lt + 1 == cnt) wc[d] = (uint16_t)(c + cnt);
-        dr[i] = d | ((c + lt) << 16);
+        for (int i = 0; i < ITEMS; ++i) {
+            const uint32_t j = wb + i * WAVE;
+            v[i] = (full || j < nvalid) ? vtin[j] : V(0);
+        }
+    }
+
+    // ---- rank
+    uint32_t dr[ITEMS];  // digit | rank-in-wave << 16
+    {
+        uint16_t* wc = wcnt + wave * R;
+        uint64_t* wm = wmask + wave * RLO;
+        const uint64_t mybit = 1ull << lane;
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+            const uint32_t d = (uint32_t)(k[i] >> shift) & dmask;
+            uint64_t* slot = wm + (d & lomask);
+            atomicOr((unsigned long long*)slot, (unsigned long long)mybit);
+            uint64_t m = __hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (MAXB > 8 && bits > 8) m &= match_digit<(MAXB > 8 ? MAXB - 8 : 1)>(d >> 8, bits - 8);
+            const uint32_t lt = mbcnt(m);
+            const uint32_t cnt = (uint32_t)__popcll(m);
+            const uint32_t c = wc[d];
+            if (lt + 1 == cnt) {
+                wc[d] = (uint16_t)(c + cnt);
+                __hip_atomic_store(slot, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            }
+            dr[i] = d | ((c + lt) << 16);
+        }
     }
     __syncthreads();
 
-    // ---- per digit: exclusive prefix over waves, tile total
+    // ---- per digit: exclusive prefix over waves, tile total, published at
+    //      once for the tiles that follow
     for (int d = tid; d < R; d += NT) {
         uint32_t s = 0;
 #pragma unroll
@@ -226,34 +266,51 @@ __global__ __launch_bounds__(NT) void k_onesweep(
             const int d = tid * PER + q;
             if (d < R) {
                 st_agent(&lb[d], (LB)(((LB)FLAG_PRE << LBW<LB>::SH) | (LB)(ex + tot[d])));
-                goff[d] = (int64_t)ex - (int64_t)loc[d];
+                goff[d] = (OFF)((int64_t)ex - (int64_t)loc[d]);
             }
             ex += part[q];
         }
     } else {
         __syncthreads();  // loc[] complete
+        // Windowed look-back: each step reads the words of up to LBWIN
+        // predecessors at once (independent loads, one memory round trip),
+        // then consumes them nearest first, stopping at the first inclusive
+        // prefix.  A predecessor that has not published yet (flag 0) is
+        // waited for and re-read; no tile is ever skipped.
         for (int d = tid; d < R; d += NT) {
             LB excl = 0;
-            uint32_t j = tile - 1;
+            int64_t j = (int64_t)tile - 1;  // nearest predecessor not yet consumed
             uint32_t spins = 0;
             while (true) {
-                const LB w = ld_agent(&lb[(size_t)j * R + d]);
-                const uint32_t f = (uint32_t)(w >> LBW<LB>::SH);
-                if (f == 0) {
+                LB w[LBWIN];
+#pragma unroll
+                for (int q = 0; q < LBWIN; ++q)
+                    w[q] = (j - q >= 0) ? ld_agent(&lb[(size_t)(j - q) * R + d])
+                                        : (LB)((LB)FLAG_PRE << LBW<LB>::SH);
+                bool done = false;
+                int used = 0;
+#pragma unroll
+                for (int q = 0; q < LBWIN; ++q) {
+                    if (done || used < q) continue;
+                    const uint32_t f = (uint32_t)(w[q] >> LBW<LB>::SH);
+                    if (f == 0) continue;  // not published yet: stop consuming here
+                    excl += w[q] & LBW<LB>::MASK;
+                    used = q + 1;
+                    if (f == FLAG_PRE) done = true;
+                }
+                if (done) break;
+                j -= used;
+                if (used == 0) {
                     if (++spins > SPIN_LIMIT) {
                         atomicOr(status, STATUS_SPIN);
                         break;
                     }
                     __builtin_amdgcn_s_sleep(1);
-                    continue;
                 }
-                excl += w & LBW<LB>::MASK;
-                if (f == FLAG_PRE) break;
-                --j;
             }
             st_agent(&lb[(size_t)tile * R + d],
                      (LB)(((LB)FLAG_PRE << LBW<LB>::SH) | (LB)(excl + tot[d])));
-            goff[d] = (int64_t)excl - (int64_t)loc[d];
+            goff[d] = (OFF)((int64_t)excl - (int64_t)loc[d]);
         }
     }
     __syncthreads();
@@ -270,23 +327,24 @@ __global__ __launch_bounds__(NT) void k_onesweep(
     __syncthreads();
 
     // ---- write out: consecutive slots of one digit go to consecutive
-    //      addresses, so each digit's run is a coalesced burst.
-    int64_t dst[VB ? ITEMS : 1];
+    //      addresses, so each digit's run is a coalesced burst.  The
+    //      destination is in [0, n) whenever the prefixes are right; the
+    //      check keeps a wrong prefix (or an abandoned look-back) from writing
+    //      outside the array and reports it instead.
+    using UOFF = typename std::make_unsigned<OFF>::type;
+    OFF dst[VB ? ITEMS : 1];
 #pragma unroll
     for (int q = 0; q < ITEMS; ++q) {
         const uint32_t j = q * NT + tid;
-        if (j < nvalid) {
+        if (full || j < nvalid) {
             const K key = skeys[j];
             const uint32_t d = (uint32_t)(key >> shift) & dmask;
-            int64_t o = goff[d] + (int64_t)j;
-            // o is in [0, n) whenever the prefixes are right; the guard keeps
-            // a wrong prefix (or an abandoned look-back) from writing outside
-            // the array and reports it instead.
-            if ((uint64_t)o >= n) {
+            OFF o = goff[d] + (OFF)j;
+            if ((uint64_t)(UOFF)o >= n) {
                 atomicOr(status, STATUS_RANGE);
                 o = -1;
             } else {
-                kout[o] = key;
+                kout[(UOFF)o] = key;
             }
             if constexpr (VB != 0) dst[q] = o;
         }
@@ -299,12 +357,12 @@ __global__ __launch_bounds__(NT) void k_onesweep(
 #pragma unroll
         for (int q = 0; q < ITEMS; ++q) {
             const uint32_t j = q * NT + tid;
-            if (j < nvalid && dst[q] >= 0) vout[dst[q]] = svals[j];
+            if ((full || j < nvalid) && dst[q] >= 0) vout[(UOFF)dst[q]] = svals[j];
         }
     }
 }
 
-template <typename K, int VB, int MAXB, int ITEMS, typename LB>
+template <typename K, int VB, int MAXB, int ITEMS, typename LB, typename OFF>
 hipError_t launch_pass(const LsdPlan& p, const void* src, void* dst, const void* vsrc, void* vdst,
                        int pass, unsigned char* ws, hipStream_t st) {
     uint32_t* ctr = reinterpret_cast<uint32_t*>(ws + p.off_ctr) + pass;
@@ -312,7 +370,7 @@ hipError_t launch_pass(const LsdPlan& p, const void* src, void* dst, const void*
     const uint32_t* gh = reinterpret_cast<const uint32_t*>(ws + p.off_hist) + (size_t)pass * p.R;
     uint32_t* status = reinterpret_cast<uint32_t*>(ws + p.off_status);
     prof(st, KID_ONESWEEP, 0);
-    hipLaunchKernelGGL((k_onesweep<K, VB, MAXB, ITEMS, LB>), dim3((unsigned)p.tiles), dim3(NT), 0, st,
+    hipLaunchKernelGGL((k_onesweep<K, VB, MAXB, ITEMS, LB, OFF>), dim3((unsigned)p.tiles), dim3(NT), 0, st,
                        (const K*)src, (K*)dst, vsrc, vdst, (uint64_t)p.n, pass * p.bits, p.bits, ctr,
                        lb, gh, status);
     prof(st, KID_ONESWEEP, 1);
@@ -322,14 +380,17 @@ hipError_t launch_pass(const LsdPlan& p, const void* src, void* dst, const void*
 template <typename K, int VB, int MAXB, int ITEMS>
 hipError_t launch_pass_lb(const LsdPlan& p, const void* src, void* dst, const void* vsrc,
                           void* vdst, int pass, unsigned char* ws, hipStream_t st) {
-    return p.lb64 ? launch_pass<K, VB, MAXB, ITEMS, uint64_t>(p, src, dst, vsrc, vdst, pass, ws, st)
-                  : launch_pass<K, VB, MAXB, ITEMS, uint32_t>(p, src, dst, vsrc, vdst, pass, ws, st);
+    if (p.n >= (1ull << 31))
+        return launch_pass<K, VB, MAXB, ITEMS, uint64_t, int64_t>(p, src, dst, vsrc, vdst, pass, ws, st);
+    if (p.lb64)
+        return launch_pass<K, VB, MAXB, ITEMS, uint64_t, int32_t>(p, src, dst, vsrc, vdst, pass, ws, st);
+    return launch_pass<K, VB, MAXB, ITEMS, uint32_t, int32_t>(p, src, dst, vsrc, vdst, pass, ws, st);
 }
 
 template <typename K, int VB>
 hipError_t launch_pass_k(const LsdPlan& p, const void* src, void* dst, const void* vsrc,
                          void* vdst, int pass, unsigned char* ws, hipStream_t st) {
-    constexpr int ITEMS = sizeof(K) == 4 ? 16 : 8;
+    constexpr int ITEMS = lsd_items(sizeof(K), VB);
     if (p.bits <= 8) return launch_pass_lb<K, VB, 8, ITEMS>(p, src, dst, vsrc, vdst, pass, ws, st);
     return launch_pass_lb<K, VB, 11, ITEMS>(p, src, dst, vsrc, vdst, pass, ws, st);
 }
@@ -367,7 +428,7 @@ bool lsd_plan(size_t n, int kb, int vb, int bits, LsdPlan* p) {
     q.bits = bits;
     q.passes = (8 * kb + bits - 1) / bits;
     q.R = 1 << bits;
-    q.tile = NT * (kb == 4 ? 16 : 8);
+    q.tile = NT * lsd_items(kb, vb);
     q.tiles = n ? (n + q.tile - 1) / q.tile : 0;
     q.lb64 = n >= (1ull << 30);
     q.lb_words = q.tiles * (size_t)q.R;
