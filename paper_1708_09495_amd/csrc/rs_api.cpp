@@ -61,6 +61,35 @@ bool overlaps(const void* a, size_t abytes, const void* b, size_t bbytes) {
     return x < y + bbytes && y < x + abytes;
 }
 
+int64_t network_stages(int algo, int p) {
+    int lg = 0;
+    while ((1 << lg) < p) ++lg;
+    return algo == RS_ALGO_BTN ? (int64_t)lg * (lg + 1) / 2 : (algo == RS_ALGO_OET ? p : 0);
+}
+
+// `count` small arrays through BTN / OET / LDS radix.
+rs_status sort_small(const uint32_t* in, uint32_t* out, size_t n, size_t count, int algo, int p,
+                     hipStream_t st) {
+    if (n > SMALL_CAP_U32) return RS_ERR_UNSUPPORTED;
+    if (algo == RS_ALGO_AUTO) algo = RS_ALGO_BTN;
+    if (algo == RS_ALGO_BTN || algo == RS_ALGO_OET) {
+        if (p == 0) p = small_default_p(algo, (uint32_t)n);
+        if (!small_valid_p((uint32_t)n, p)) return RS_ERR_INVALID;
+    } else if (algo == RS_ALGO_LDS_RADIX) {
+        p = 0;
+    } else {
+        return RS_ERR_UNSUPPORTED;
+    }
+    begin_call(algo);
+    g_call.stats.runs_p = p;
+    g_call.stats.network_stages = network_stages(algo, p);
+    if (algo == RS_ALGO_LDS_RADIX) {
+        g_call.stats.radix_bits = 8;
+        g_call.stats.passes = 4;
+    }
+    return small_run(algo, in, out, (uint32_t)n, count, p, st);
+}
+
 rs_status sort_keys_common(const void* kin, void* kout, const void* vin, void* vout, size_t n,
                            int kb, int vb, int bits, rs_algo algo, void* ws, size_t ws_bytes,
                            void* stream) {
@@ -78,6 +107,12 @@ rs_status sort_keys_common(const void* kin, void* kout, const void* vin, void* v
         case RS_ALGO_AUTO:
         case RS_ALGO_LSD:
             return sort_lsd(kin, kout, vin, vout, n, kb, vb, bits, ws, ws_bytes, st);
+        case RS_ALGO_BTN:
+        case RS_ALGO_OET:
+        case RS_ALGO_LDS_RADIX:
+            if (kb != 4 || vb != 0) return RS_ERR_UNSUPPORTED;
+            return sort_small(static_cast<const uint32_t*>(kin), static_cast<uint32_t*>(kout), n, 1,
+                              algo, 0, st);
         default:
             return RS_ERR_UNSUPPORTED;
     }
@@ -116,9 +151,16 @@ rs_status rs_sort_kv(const void* keys_in, const void* vals_in, void* keys_out, v
                             radix_bits, algo, ws, ws_bytes, stream);
 }
 
-rs_status rs_sort_batch_u32(const uint32_t*, uint32_t*, size_t, size_t, rs_algo, int, void*,
-                            size_t, void*) {
-    return RS_ERR_UNSUPPORTED;
+rs_status rs_sort_batch_u32(const uint32_t* in, uint32_t* out, size_t n, size_t count, rs_algo algo,
+                            int p, void* ws, size_t ws_bytes, void* stream) {
+    (void)ws;
+    (void)ws_bytes;
+    if (n > 0 && count > 0 && (!in || !out)) return RS_ERR_INVALID;
+    if (count > 0x7FFFFFFFu) return RS_ERR_UNSUPPORTED;
+    if (n > 0 && count > 0 && in != out && overlaps(in, n * count * 4, out, n * count * 4))
+        return RS_ERR_INVALID;
+    if (p < 0) return RS_ERR_INVALID;
+    return sort_small(in, out, n, count, algo, p, static_cast<hipStream_t>(stream));
 }
 
 rs_status rs_sort_segmented(const uint32_t*, uint32_t*, const int64_t*, size_t, int64_t, rs_algo,

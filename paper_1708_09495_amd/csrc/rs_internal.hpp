@@ -76,6 +76,15 @@ inline rs_status launch_status() {
     return e == hipSuccess ? RS_OK : hip_fail(e);
 }
 
+// ---- one workgroup per small array (BTN, OET, LDS radix) -----------------
+constexpr uint32_t SMALL_CAP_U32 = 16384;          // keys one workgroup holds
+uint32_t small_npad(uint32_t n);                   // next power of two >= n
+bool small_valid_p(uint32_t n, int p);             // p a power of two, n_pad/p <= 64
+int small_default_p(int algo, uint32_t n);
+// `count` arrays of n keys back to back, one workgroup each.
+rs_status small_run(int algo, const uint32_t* in, uint32_t* out, uint32_t n, size_t count, int p,
+                    hipStream_t st);
+
 // Zero-fill of device memory by a kernel (no hipMemsetAsync, so callers may
 // capture the stream into a graph).
 rs_status fill_u32(void* p, size_t words, uint32_t v, hipStream_t st);
