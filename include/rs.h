@@ -136,6 +136,28 @@ const char* rs_status_string(rs_status s);
  * learned path's overflow counts), this synchronises that call's stream. */
 rs_status rs_get_stats(rs_stats* out);
 
+/* ---- tuning table --------------------------------------------------------- */
+
+/* The small-array choice for length class size_log2 = k (arrays of length
+ * in (2^(k-1), 2^k], k = 0..14): algo is RS_ALGO_BTN, RS_ALGO_OET or
+ * RS_ALGO_LDS_RADIX, p the runs of BTN/OET.  Used by RS_ALGO_AUTO for small
+ * single arrays and batches, and for the small segments of
+ * rs_sort_segmented. */
+typedef struct {
+    int32_t size_log2;
+    int32_t algo;
+    int32_t p;
+} rs_tune_entry;
+
+/* Replaces the entries for the classes listed (process-wide, not
+ * thread-safe against concurrent sorts).  RS_ERR_INVALID for a bad class,
+ * algorithm, or p (p must be a power of two with 2^k / p <= 64). */
+rs_status rs_tune_set(const rs_tune_entry* entries, int count);
+
+/* Copies the current table (classes 0..14) to `out` (host); returns the
+ * number of entries written. */
+int rs_tune_get(rs_tune_entry* out, int max);
+
 /* ---- kernel timing (benchmarks) ---------------------------------------- */
 
 typedef struct {

@@ -19,7 +19,7 @@ RS_OP_SORT, RS_OP_SORT_KV, RS_OP_BATCH, RS_OP_SEGMENTED = range(4)
 
 EXPORTS = ["rs_sort_u32", "rs_sort_u64", "rs_sort_kv", "rs_sort_batch_u32", "rs_sort_segmented",
            "rs_workspace_bytes", "rs_small_capacity", "rs_status_string", "rs_get_stats",
-           "rs_profile_enable", "rs_profile_read"]
+           "rs_tune_set", "rs_tune_get", "rs_profile_enable", "rs_profile_read"]
 
 
 class RsError(RuntimeError):
@@ -41,6 +41,10 @@ class rs_stats(ctypes.Structure):
                 ("fallback", ctypes.c_int32), ("buckets_overflowed", ctypes.c_int64),
                 ("keys_overflowed", ctypes.c_int64), ("train_loss", ctypes.c_double),
                 ("device_error", ctypes.c_uint32), ("hip_error", ctypes.c_int32)]
+
+
+class rs_tune_entry(ctypes.Structure):
+    _fields_ = [("size_log2", ctypes.c_int32), ("algo", ctypes.c_int32), ("p", ctypes.c_int32)]
 
 
 class rs_kernel_time(ctypes.Structure):
@@ -76,6 +80,10 @@ def lib():
         L.rs_status_string.argtypes = [i]
         L.rs_status_string.restype = ctypes.c_char_p
         L.rs_get_stats.argtypes = [ctypes.POINTER(rs_stats)]
+        L.rs_tune_set.argtypes = [ctypes.POINTER(rs_tune_entry), i]
+        L.rs_tune_set.restype = i
+        L.rs_tune_get.argtypes = [ctypes.POINTER(rs_tune_entry), i]
+        L.rs_tune_get.restype = i
         L.rs_profile_enable.argtypes = [i]
         L.rs_profile_read.argtypes = [ctypes.POINTER(rs_kernel_time), i]
         L.rs_profile_read.restype = i
@@ -138,6 +146,21 @@ def rs_get_stats():
     s = rs_stats()
     _call(lib().rs_get_stats(ctypes.byref(s)), "rs_get_stats")
     return s
+
+
+def rs_tune_set(entries):
+    """entries: iterable of (size_log2, algo, p)."""
+    entries = list(entries)
+    arr = (rs_tune_entry * max(1, len(entries)))()
+    for k, (c, a, p) in enumerate(entries):
+        arr[k].size_log2, arr[k].algo, arr[k].p = c, a, p
+    _call(lib().rs_tune_set(arr, len(entries)), "rs_tune_set")
+
+
+def rs_tune_get():
+    arr = (rs_tune_entry * 16)()
+    k = lib().rs_tune_get(arr, 16)
+    return [(arr[i].size_log2, arr[i].algo, arr[i].p) for i in range(k)]
 
 
 def rs_profile_enable(on=True):

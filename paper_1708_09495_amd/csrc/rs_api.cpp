@@ -71,7 +71,13 @@ int64_t network_stages(int algo, int p) {
 rs_status sort_small(const uint32_t* in, uint32_t* out, size_t n, size_t count, int algo, int p,
                      hipStream_t st) {
     if (n > SMALL_CAP_U32) return RS_ERR_UNSUPPORTED;
-    if (algo == RS_ALGO_AUTO) algo = RS_ALGO_BTN;
+    if (algo == RS_ALGO_AUTO) {
+        int c = 0;
+        while ((1u << c) < n) ++c;
+        algo = tune_table().algo[c];
+        if (p == 0 && algo != RS_ALGO_LDS_RADIX) p = tune_table().p[c];
+        if (algo != RS_ALGO_LDS_RADIX && !small_valid_p((uint32_t)n, p)) p = 0;
+    }
     if (algo == RS_ALGO_BTN || algo == RS_ALGO_OET) {
         if (p == 0) p = small_default_p(algo, (uint32_t)n);
         if (!small_valid_p((uint32_t)n, p)) return RS_ERR_INVALID;
@@ -163,9 +169,40 @@ rs_status rs_sort_batch_u32(const uint32_t* in, uint32_t* out, size_t n, size_t 
     return sort_small(in, out, n, count, algo, p, static_cast<hipStream_t>(stream));
 }
 
-rs_status rs_sort_segmented(const uint32_t*, uint32_t*, const int64_t*, size_t, int64_t, rs_algo,
-                            void*, size_t, void*) {
-    return RS_ERR_UNSUPPORTED;
+rs_status rs_sort_segmented(const uint32_t* in, uint32_t* out, const int64_t* offsets,
+                            size_t num_segments, int64_t total_n, rs_algo algo, void* ws,
+                            size_t ws_bytes, void* stream) {
+    if (total_n < 0) return RS_ERR_INVALID;
+    if (num_segments > 0 && !offsets) return RS_ERR_INVALID;
+    if (total_n > 0 && (!in || !out)) return RS_ERR_INVALID;
+    if (total_n > 0 && in != out && overlaps(in, (size_t)total_n * 4, out, (size_t)total_n * 4))
+        return RS_ERR_INVALID;
+    if (algo != RS_ALGO_AUTO && algo != RS_ALGO_BTN && algo != RS_ALGO_OET &&
+        algo != RS_ALGO_LDS_RADIX)
+        return RS_ERR_UNSUPPORTED;
+    SegPlan p;
+    if (!seg_plan(num_segments, total_n, &p)) return RS_ERR_UNSUPPORTED;
+    begin_call(algo);
+    g_call.stats.radix_bits = 8;
+    g_call.stats.passes = 4;
+    if (num_segments == 0) return RS_OK;
+    rs_status rc = check_ws(ws, ws_bytes, p.total);
+    if (rc != RS_OK) return rc;
+    SegTable t = tune_table();
+    if (algo != RS_ALGO_AUTO)
+        for (int c = 0; c < 64; ++c) {
+            t.algo[c] = (int8_t)algo;
+            const int npad = c < 15 ? (1 << c) : 16384;
+            t.p[c] = (int16_t)small_default_p(algo, (uint32_t)npad);
+        }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    rc = seg_run(p, in, out, offsets, num_segments, total_n, t, ws, st);
+    if (rc == RS_OK) {
+        g_call.stream = st;
+        g_call.status = reinterpret_cast<const uint32_t*>(static_cast<unsigned char*>(ws) + p.off_status);
+        g_call.pending = true;
+    }
+    return rc;
 }
 
 size_t rs_workspace_bytes(int op, size_t n, int key_bytes, int val_bytes, int radix_bits,
@@ -174,8 +211,15 @@ size_t rs_workspace_bytes(int op, size_t n, int key_bytes, int val_bytes, int ra
     (void)num_segments;
     radix_bits = default_bits(radix_bits);
     if (op == RS_OP_SORT || op == RS_OP_SORT_KV) {
+        if (algo == RS_ALGO_BTN || algo == RS_ALGO_OET || algo == RS_ALGO_LDS_RADIX) return ALIGN;
         LsdPlan p;
         if (!lsd_plan(n, key_bytes, op == RS_OP_SORT ? 0 : val_bytes, radix_bits, &p)) return 0;
+        return p.total;
+    }
+    if (op == RS_OP_BATCH) return ALIGN;
+    if (op == RS_OP_SEGMENTED) {
+        SegPlan p;
+        if ((int64_t)n < 0 || !seg_plan(num_segments, (int64_t)n, &p)) return 0;
         return p.total;
     }
     return 0;
@@ -211,6 +255,52 @@ rs_status rs_get_stats(rs_stats* out) {
 }
 
 }  // extern "C"
+
+// ---- tuning table -----------------------------------------------------------
+
+namespace rs {
+SegTable& tune_table() {
+    static SegTable t = [] {
+        SegTable d{};
+        for (int c = 0; c < 64; ++c) {
+            const uint32_t npad = c < 15 ? (1u << c) : 16384u;
+            d.algo[c] = (int8_t)RS_ALGO_BTN;
+            d.p[c] = (int16_t)small_default_p(RS_ALGO_BTN, npad);
+        }
+        return d;
+    }();
+    return t;
+}
+}  // namespace rs
+
+extern "C" rs_status rs_tune_set(const rs_tune_entry* e, int count) {
+    if (count < 0 || (count > 0 && !e)) return RS_ERR_INVALID;
+    for (int i = 0; i < count; ++i) {
+        const int c = e[i].size_log2;
+        if (c < 0 || c > 14) return RS_ERR_INVALID;
+        if (e[i].algo != RS_ALGO_BTN && e[i].algo != RS_ALGO_OET && e[i].algo != RS_ALGO_LDS_RADIX)
+            return RS_ERR_INVALID;
+        if (e[i].algo != RS_ALGO_LDS_RADIX && !rs::small_valid_p(1u << c, e[i].p)) return RS_ERR_INVALID;
+    }
+    rs::SegTable& t = rs::tune_table();
+    for (int i = 0; i < count; ++i) {
+        t.algo[e[i].size_log2] = (int8_t)e[i].algo;
+        t.p[e[i].size_log2] = (int16_t)e[i].p;
+    }
+    return RS_OK;
+}
+
+extern "C" int rs_tune_get(rs_tune_entry* out, int max) {
+    if (!out || max <= 0) return 0;
+    const rs::SegTable& t = rs::tune_table();
+    int k = 0;
+    for (int c = 0; c <= 14 && k < max; ++c, ++k) {
+        out[k].size_log2 = c;
+        out[k].algo = t.algo[c];
+        out[k].p = t.p[c];
+    }
+    return k;
+}
 
 // ---- kernel timing --------------------------------------------------------
 #include <mutex>

@@ -85,6 +85,24 @@ int small_default_p(int algo, uint32_t n);
 rs_status small_run(int algo, const uint32_t* in, uint32_t* out, uint32_t n, size_t count, int p,
                     hipStream_t st);
 
+// ---- segmented sort ---------------------------------------------------------
+constexpr uint32_t SEG_SMALL_MAX = 16384;        // longest segment sorted in LDS
+// Small-array choice per length class c (length in (2^(c-1), 2^c]).
+struct SegTable {
+    int8_t algo[64];    // RS_ALGO_BTN, RS_ALGO_OET or RS_ALGO_LDS_RADIX
+    int16_t p[64];      // runs for BTN/OET
+};
+struct SegPlan {
+    size_t off_status = 0, off_cnt = 0, off_order = 0, off_tmp = 0;
+    size_t zero_bytes = 0, total = 0;
+};
+bool seg_plan(uint64_t S, int64_t total, SegPlan* p);
+rs_status seg_run(const SegPlan& p, const uint32_t* in, uint32_t* out, const int64_t* offsets,
+                  uint64_t S, int64_t total, const SegTable& table, void* ws, hipStream_t st);
+
+// The process-wide tuning table (defaults until rs_tune_set / rs_tune_run).
+SegTable& tune_table();
+
 // Zero-fill of device memory by a kernel (no hipMemsetAsync, so callers may
 // capture the stream into a graph).
 rs_status fill_u32(void* p, size_t words, uint32_t v, hipStream_t st);

@@ -1,0 +1,325 @@
+// rs_seg.hip -- batched segmented sort in one persistent launch (an
+// extension beyond the paper: many independent arrays of uneven length).
+//
+// Plan (three small kernels, all on the device):
+//   classify  each segment's length class = bit length of its length;
+//   scan      class cursors, largest class first;
+//   scatter   segment ids into a queue ordered by decreasing class, so the
+//             longest segments start first (longest-processing-time order).
+// Sort (one persistent kernel): every workgroup pops the next queue entry
+// until the queue is empty and sorts that segment by itself:
+//   length <= 16384  in LDS, with BTN, OET or the LDS radix sort as the
+//                    tuning table says for the length class;
+//   longer           the radix-2^8 count-sort rounds of Section 3 run by the
+//                    one workgroup: one read counts all four rounds' digits,
+//                    then each round walks the segment's tiles IN ORDER,
+//                    ranking each tile stably in LDS and writing each digit's
+//                    run at that digit's running offset -- the running
+//                    offsets stay in LDS, so no tile waits on another
+//                    workgroup.
+// Segments are independent, so workgroups never wait on each other and every
+// workgroup leaves once the queue is exhausted.
+#include "rs_internal.hpp"
+#include "rs_small_dev.h"
+
+namespace rs {
+namespace {
+
+constexpr int SG_NT = 512;
+constexpr int SG_NW = SG_NT / WAVE;
+constexpr int SG_ITEMS = 16;
+constexpr int SG_T = SG_NT * SG_ITEMS;        // keys per tile of the large path
+constexpr int SG_R = 256;                     // radix 2^8
+constexpr int SG_P = 4;                       // rounds for 32-bit keys
+constexpr int NCLASS = 64;
+constexpr int SMEM = 16896 * 4;               // BTN/OET: p*(N+1) words for n_pad <= 16384
+
+__device__ __forceinline__ int len_class(int64_t L) {
+    return L <= 0 ? 0 : 64 - __clzll((unsigned long long)L);
+}
+
+__global__ void k_seg_classify(const int64_t* __restrict__ off, uint64_t S, int64_t total,
+                               uint32_t* __restrict__ cnt, uint32_t* __restrict__ status) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; s < S; s += stride) {
+        const int64_t b = off[s], e = off[s + 1];
+        if (b < 0 || e < b || e > total || (s == 0 && b != 0)) atomicOr(status, STATUS_RANGE);
+        const int c = (b < 0 || e < b || e > total) ? 0 : len_class(e - b);
+        atomicAdd(&cnt[c], 1u);
+    }
+}
+
+// One workgroup of NCLASS threads: cursor[c] = number of segments in classes
+// above c (the queue lists the largest class first).
+__global__ void k_seg_scan(const uint32_t* __restrict__ cnt, uint32_t* __restrict__ cursor) {
+    if (threadIdx.x == 0) {
+        uint32_t s = 0;
+        for (int c = NCLASS - 1; c >= 0; --c) {
+            cursor[c] = s;
+            s += cnt[c];
+        }
+    }
+}
+
+__global__ void k_seg_scatter(const int64_t* __restrict__ off, uint64_t S, int64_t total,
+                              uint32_t* __restrict__ cursor, uint32_t* __restrict__ order) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; s < S; s += stride) {
+        const int64_t b = off[s], e = off[s + 1];
+        const int c = (b < 0 || e < b || e > total) ? 0 : len_class(e - b);
+        const uint32_t pos = atomicAdd(&cursor[c], 1u);
+        if (pos < S) order[pos] = (uint32_t)s;
+    }
+}
+
+// ---- large segments: radix-2^8 rounds by one workgroup ------------------------
+
+__device__ void seg_large(const uint32_t* __restrict__ in, uint32_t* __restrict__ out,
+                          uint32_t* __restrict__ tmp, uint32_t L, unsigned char* smem,
+                          uint32_t* status) {
+    uint64_t* wmask = reinterpret_cast<uint64_t*>(smem);              // NW*R
+    uint16_t* wcnt = reinterpret_cast<uint16_t*>(smem + 16384);       // NW*R
+    uint32_t* skeys = reinterpret_cast<uint32_t*>(smem + 20480);      // T
+    uint32_t* hist = reinterpret_cast<uint32_t*>(smem + 53248);       // P*R
+    uint32_t* run = hist + SG_P * SG_R;                               // R
+    uint32_t* loc = run + SG_R;                                       // R
+    uint32_t* tot = loc + SG_R;                                       // R
+    uint32_t* wsum = tot + SG_R;                                      // NW+1
+    const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+
+    for (int i = tid; i < SG_NW * SG_R; i += SG_NT) {
+        wmask[i] = 0;
+        wcnt[i] = 0;
+    }
+    for (int i = tid; i < SG_P * SG_R; i += SG_NT) hist[i] = 0;
+    __syncthreads();
+    // one read counts the digits of all four rounds
+    for (uint32_t q = tid; q < L; q += SG_NT) {
+        const uint32_t k = in[q];
+#pragma unroll
+        for (int p = 0; p < SG_P; ++p) atomicAdd(&hist[p * SG_R + ((k >> (8 * p)) & 255u)], 1u);
+    }
+    const uint64_t mybit = 1ull << lane;
+    const uint32_t* src = in;
+    for (int p = 0; p < SG_P; ++p) {
+        // four rounds: in -> tmp -> out -> tmp -> out
+        uint32_t* dst = (p & 1) ? out : tmp;
+        const int shift = 8 * p;
+        __syncthreads();
+        {
+            const uint32_t v = tid < (uint32_t)SG_R ? hist[p * SG_R + tid] : 0u;
+            uint32_t total;
+            const uint32_t ex = block_excl_scan<SG_NT>(v, wsum, &total);
+            if (tid < (uint32_t)SG_R) run[tid] = ex;
+        }
+        for (uint32_t base = 0; base < L; base += SG_T) {
+            const uint32_t nvalid = (L - base) < (uint32_t)SG_T ? (L - base) : (uint32_t)SG_T;
+            const uint32_t wb = wave * (SG_ITEMS * WAVE) + lane;
+            uint32_t k[SG_ITEMS];
+#pragma unroll
+            for (int i = 0; i < SG_ITEMS; ++i) {
+                const uint32_t j = wb + i * WAVE;
+                k[i] = j < nvalid ? src[base + j] : 0xFFFFFFFFu;
+            }
+            __syncthreads();  // run[] set; previous tile finished with wcnt/skeys
+            uint32_t dr[SG_ITEMS];
+            {
+                uint16_t* wc = wcnt + wave * SG_R;
+                uint64_t* wm = wmask + wave * SG_R;
+#pragma unroll
+                for (int i = 0; i < SG_ITEMS; ++i) {
+                    const uint32_t d = (k[i] >> shift) & 255u;
+                    atomicOr((unsigned long long*)&wm[d], (unsigned long long)mybit);
+                    const uint64_t m =
+                        __hip_atomic_load(&wm[d], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    const uint32_t lt = mbcnt(m);
+                    const uint32_t cnt = (uint32_t)__popcll(m);
+                    const uint32_t c = wc[d];
+                    if (lt + 1 == cnt) {
+                        wc[d] = (uint16_t)(c + cnt);
+                        __hip_atomic_store(&wm[d], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    }
+                    dr[i] = d | ((c + lt) << 16);
+                }
+            }
+            __syncthreads();
+            uint32_t t = 0;
+            if (tid < (uint32_t)SG_R) {
+                uint32_t s = 0;
+#pragma unroll
+                for (int w = 0; w < SG_NW; ++w) {
+                    const uint32_t c = wcnt[w * SG_R + tid];
+                    wcnt[w * SG_R + tid] = (uint16_t)s;
+                    s += c;
+                }
+                t = s;
+                tot[tid] = s;
+            }
+            {
+                uint32_t total;
+                const uint32_t ex = block_excl_scan<SG_NT>(t, wsum, &total);
+                if (tid < (uint32_t)SG_R) loc[tid] = ex;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int i = 0; i < SG_ITEMS; ++i) {
+                const uint32_t d = dr[i] & 0xFFFFu;
+                skeys[loc[d] + wcnt[wave * SG_R + d] + (dr[i] >> 16)] = k[i];
+            }
+            __syncthreads();
+            // each digit's run of this tile lands at the digit's running offset
+#pragma unroll
+            for (int q = 0; q < SG_ITEMS; ++q) {
+                const uint32_t j = q * SG_NT + tid;
+                if (j < nvalid) {
+                    const uint32_t key = skeys[j];
+                    const uint32_t d = (key >> shift) & 255u;
+                    const uint32_t o = run[d] - loc[d] + j;
+                    if (o < L) dst[o] = key;
+                    else atomicOr(status, STATUS_RANGE);
+                }
+            }
+            __syncthreads();
+            if (tid < (uint32_t)SG_R) run[tid] += tot[tid];
+            for (int i = tid; i < SG_NW * SG_R; i += SG_NT) wcnt[i] = 0;
+        }
+        src = dst;
+    }
+}
+
+// ---- small segments in LDS -------------------------------------------------------
+
+__device__ void seg_small(const uint32_t* __restrict__ in, uint32_t* __restrict__ out, uint32_t L,
+                          int algo, int p, unsigned char* smem) {
+    uint32_t* sh = reinterpret_cast<uint32_t*>(smem);
+    if (algo == RS_ALGO_LDS_RADIX && L <= (uint32_t)SG_NT * 16) {
+        uint64_t* wmask = reinterpret_cast<uint64_t*>(smem);
+        uint32_t* sk = reinterpret_cast<uint32_t*>(smem);            // aliases the masks
+        uint16_t* wcnt = reinterpret_cast<uint16_t*>(smem + 32768);
+        uint32_t* loc = reinterpret_cast<uint32_t*>(smem + 36864);
+        uint32_t* wsum = loc + 256;
+        const uint32_t items = (L + SG_NT - 1) / SG_NT;
+        if (items <= 1) lds_radix_sort<1, SG_NT>(in, out, L, wmask, wcnt, loc, wsum, sk);
+        else if (items <= 2) lds_radix_sort<2, SG_NT>(in, out, L, wmask, wcnt, loc, wsum, sk);
+        else if (items <= 4) lds_radix_sort<4, SG_NT>(in, out, L, wmask, wcnt, loc, wsum, sk);
+        else if (items <= 8) lds_radix_sort<8, SG_NT>(in, out, L, wmask, wcnt, loc, wsum, sk);
+        else lds_radix_sort<16, SG_NT>(in, out, L, wmask, wcnt, loc, wsum, sk);
+        return;
+    }
+    uint32_t npad = 1;
+    while (npad < L) npad <<= 1;
+    // p within what a SG_NT-thread workgroup holds: p <= SG_NT, N <= 32
+    if (p < 1) p = 1;
+    if (p > SG_NT) p = SG_NT;
+    if ((uint32_t)p > npad) p = (int)npad;
+    while (npad / (uint32_t)p > 32u) p <<= 1;
+    const uint32_t N = npad / (uint32_t)p;
+    const bool oet = algo == RS_ALGO_OET;
+    switch (N) {
+        case 1: oet ? oet_sort<1>(in, out, L, p, sh) : btn_sort<1>(in, out, L, p, sh); break;
+        case 2: oet ? oet_sort<2>(in, out, L, p, sh) : btn_sort<2>(in, out, L, p, sh); break;
+        case 4: oet ? oet_sort<4>(in, out, L, p, sh) : btn_sort<4>(in, out, L, p, sh); break;
+        case 8: oet ? oet_sort<8>(in, out, L, p, sh) : btn_sort<8>(in, out, L, p, sh); break;
+        case 16: oet ? oet_sort<16>(in, out, L, p, sh) : btn_sort<16>(in, out, L, p, sh); break;
+        default: oet ? oet_sort<32>(in, out, L, p, sh) : btn_sort<32>(in, out, L, p, sh); break;
+    }
+}
+
+__attribute__((amdgpu_waves_per_eu(4))) __global__ __launch_bounds__(SG_NT) void k_seg_sort(const uint32_t* __restrict__ in,
+                                                    uint32_t* __restrict__ out,
+                                                    uint32_t* __restrict__ tmp,
+                                                    const int64_t* __restrict__ off, uint64_t S,
+                                                    int64_t total, const uint32_t* __restrict__ order,
+                                                    uint32_t* __restrict__ qctr, SegTable table,
+                                                    uint32_t* __restrict__ status) {
+    __shared__ __align__(16) unsigned char smem[SMEM];
+    __shared__ uint32_t s_item;
+    while (true) {
+        __syncthreads();  // the previous segment is done with LDS
+        if (threadIdx.x == 0) s_item = atomicAdd(qctr, 1u);
+        __syncthreads();
+        const uint64_t item = s_item;
+        if (item >= S) break;  // the queue is finite: every workgroup leaves
+        const uint32_t seg = order[item];
+        const int64_t b = off[seg], e = off[seg + 1];
+        if (b < 0 || e <= b || e > total) continue;  // empty (or reported invalid)
+        const uint64_t L = (uint64_t)(e - b);
+        if (L > 0xFFFFFFFFull) {
+            if (threadIdx.x == 0) atomicOr(status, STATUS_RANGE);
+            continue;
+        }
+        if (L == 1) {
+            if (threadIdx.x == 0) out[b] = in[b];
+            continue;
+        }
+        if (L <= SEG_SMALL_MAX) {
+            const int c = len_class((int64_t)L);
+            seg_small(in + b, out + b, (uint32_t)L, table.algo[c], table.p[c], smem);
+        } else {
+            seg_large(in + b, out + b, tmp + b, (uint32_t)L, smem, status);
+        }
+    }
+}
+
+}  // namespace
+
+// ---- host side -------------------------------------------------------------------
+
+bool seg_plan(uint64_t S, int64_t total, SegPlan* p) {
+    if (total < 0 || S > 0x7FFFFFFFull) return false;
+    SegPlan q;
+    size_t off = 0;
+    q.off_status = off;
+    off += ALIGN;
+    q.off_cnt = off;
+    off += align_up(sizeof(uint32_t) * (2 * NCLASS + 1));
+    q.zero_bytes = off - q.off_status;
+    q.off_order = off;
+    off += align_up(sizeof(uint32_t) * (S ? S : 1));
+    q.off_tmp = off;
+    off += align_up(sizeof(uint32_t) * (size_t)(total ? total : 1));
+    q.total = off;
+    *p = q;
+    return true;
+}
+
+static int g_seg_grid = 0;
+
+rs_status seg_run(const SegPlan& p, const uint32_t* in, uint32_t* out, const int64_t* offsets,
+                  uint64_t S, int64_t total, const SegTable& table, void* ws_, hipStream_t st) {
+    if (S == 0) return RS_OK;
+    unsigned char* ws = static_cast<unsigned char*>(ws_);
+    uint32_t* status = reinterpret_cast<uint32_t*>(ws + p.off_status);
+    uint32_t* cnt = reinterpret_cast<uint32_t*>(ws + p.off_cnt);
+    uint32_t* cursor = cnt + NCLASS;
+    uint32_t* qctr = cursor + NCLASS;
+    uint32_t* order = reinterpret_cast<uint32_t*>(ws + p.off_order);
+    uint32_t* tmp = reinterpret_cast<uint32_t*>(ws + p.off_tmp);
+    rs_status rc = fill_u32(ws + p.off_status, p.zero_bytes / 4, 0u, st);
+    if (rc != RS_OK) return rc;
+    unsigned g = (unsigned)((S + 255) / 256);
+    if (g > 4096) g = 4096;
+    prof(st, KID_SEG_PLAN, 0);
+    hipLaunchKernelGGL(k_seg_classify, dim3(g), dim3(256), 0, st, offsets, S, total, cnt, status);
+    hipLaunchKernelGGL(k_seg_scan, dim3(1), dim3(64), 0, st, cnt, cursor);
+    hipLaunchKernelGGL(k_seg_scatter, dim3(g), dim3(256), 0, st, offsets, S, total, cursor, order);
+    prof(st, KID_SEG_PLAN, 1);
+    if ((rc = launch_status()) != RS_OK) return rc;
+    if (g_seg_grid == 0) {
+        int dev = 0, cus = 0, per = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_seg_sort, SG_NT, 0) != hipSuccess)
+            return hip_fail(hipGetLastError());
+        g_seg_grid = cus * (per > 0 ? per : 1);
+    }
+    uint64_t grid = (uint64_t)g_seg_grid;
+    if (grid > S) grid = S;
+    prof(st, KID_SEG, 0);
+    hipLaunchKernelGGL(k_seg_sort, dim3((unsigned)grid), dim3(SG_NT), 0, st, in, out, tmp, offsets, S,
+                       total, order, qctr, table, status);
+    prof(st, KID_SEG, 1);
+    return launch_status();
+}
+
+}  // namespace rs
