@@ -57,7 +57,8 @@ typedef enum {
     RS_OP_SORT = 0,       /* rs_sort_u32 / rs_sort_u64                 */
     RS_OP_SORT_KV = 1,    /* rs_sort_kv                                */
     RS_OP_BATCH = 2,      /* rs_sort_batch_u32                         */
-    RS_OP_SEGMENTED = 3   /* rs_sort_segmented                         */
+    RS_OP_SEGMENTED = 3,  /* rs_sort_segmented                         */
+    RS_OP_TUNE = 4        /* rs_tune_run (n = instances)               */
 } rs_op;
 
 /* Facts about the most recent call made on the calling host thread. */
@@ -157,6 +158,27 @@ rs_status rs_tune_set(const rs_tune_entry* entries, int count);
 /* Copies the current table (classes 0..14) to `out` (host); returns the
  * number of entries written. */
 int rs_tune_get(rs_tune_entry* out, int max);
+
+/* One timing of the autotuner. */
+typedef struct {
+    int32_t size_log2;     /* arrays of 2^size_log2 keys                        */
+    int32_t algo;          /* RS_ALGO_BTN / _OET / _LDS_RADIX, or RS_ALGO_LSD:  */
+                           /* the device-wide radix sort, one array per call    */
+    int32_t p;             /* runs of BTN/OET                                   */
+    int32_t chosen;        /* 1 if installed in the tuning table                */
+    double us_per_array;   /* batch of `instances` arrays in one launch, per array */
+    double us_single;      /* one array alone: launch latency included           */
+} rs_tune_result;
+
+/* Autotuner: on the current device, for every class k = 1..14, times BTN and
+ * OET at every valid p and the LDS radix sort on `instances` arrays of 2^k
+ * keys in one launch (and one array alone), installs the fastest in the
+ * tuning table, and times the device-wide LSD sort of one array.  Writes at
+ * most `max` results to `out` (host) and returns how many, or minus an
+ * rs_status.  Synchronises `stream`.  The workspace (device, at least
+ * rs_workspace_bytes(RS_OP_TUNE, instances, ...)) holds the inputs. */
+int rs_tune_run(void* ws, size_t ws_bytes, int instances, void* stream, rs_tune_result* out,
+                int max);
 
 /* ---- kernel timing (benchmarks) ---------------------------------------- */
 

@@ -15,11 +15,11 @@ LIB_PATH = os.path.join(_HERE, "librs.so")
 
 RS_OK, RS_ERR_INVALID, RS_ERR_UNSUPPORTED, RS_ERR_WORKSPACE, RS_ERR_HIP = range(5)
 RS_ALGO_AUTO, RS_ALGO_LSD, RS_ALGO_BTN, RS_ALGO_OET, RS_ALGO_LEARNED, RS_ALGO_LDS_RADIX = range(6)
-RS_OP_SORT, RS_OP_SORT_KV, RS_OP_BATCH, RS_OP_SEGMENTED = range(4)
+RS_OP_SORT, RS_OP_SORT_KV, RS_OP_BATCH, RS_OP_SEGMENTED, RS_OP_TUNE = range(5)
 
 EXPORTS = ["rs_sort_u32", "rs_sort_u64", "rs_sort_kv", "rs_sort_batch_u32", "rs_sort_segmented",
            "rs_workspace_bytes", "rs_small_capacity", "rs_status_string", "rs_get_stats",
-           "rs_tune_set", "rs_tune_get", "rs_profile_enable", "rs_profile_read"]
+           "rs_tune_set", "rs_tune_get", "rs_tune_run", "rs_profile_enable", "rs_profile_read"]
 
 
 class RsError(RuntimeError):
@@ -45,6 +45,12 @@ class rs_stats(ctypes.Structure):
 
 class rs_tune_entry(ctypes.Structure):
     _fields_ = [("size_log2", ctypes.c_int32), ("algo", ctypes.c_int32), ("p", ctypes.c_int32)]
+
+
+class rs_tune_result(ctypes.Structure):
+    _fields_ = [("size_log2", ctypes.c_int32), ("algo", ctypes.c_int32), ("p", ctypes.c_int32),
+                ("chosen", ctypes.c_int32), ("us_per_array", ctypes.c_double),
+                ("us_single", ctypes.c_double)]
 
 
 class rs_kernel_time(ctypes.Structure):
@@ -84,6 +90,8 @@ def lib():
         L.rs_tune_set.restype = i
         L.rs_tune_get.argtypes = [ctypes.POINTER(rs_tune_entry), i]
         L.rs_tune_get.restype = i
+        L.rs_tune_run.argtypes = [vp, sz, i, vp, ctypes.POINTER(rs_tune_result), i]
+        L.rs_tune_run.restype = i
         L.rs_profile_enable.argtypes = [i]
         L.rs_profile_read.argtypes = [ctypes.POINTER(rs_kernel_time), i]
         L.rs_profile_read.restype = i
@@ -161,6 +169,19 @@ def rs_tune_get():
     arr = (rs_tune_entry * 16)()
     k = lib().rs_tune_get(arr, 16)
     return [(arr[i].size_log2, arr[i].algo, arr[i].p) for i in range(k)]
+
+
+def rs_tune_run(instances=1024, ws=None, stream=None):
+    """Runs the autotuner on the current device; returns a list of dicts
+    (size_log2, algo, p, chosen, us_per_array, us_single)."""
+    torch = _torch()
+    need = rs_workspace_bytes(RS_OP_TUNE, instances)
+    ws = _workspace(need, ws, torch.device("cuda", torch.cuda.current_device()))
+    buf = (rs_tune_result * 512)()
+    k = lib().rs_tune_run(_ptr(ws), ws.numel(), instances, _stream(stream), buf, 512)
+    if k < 0:
+        raise RsError(-k, "rs_tune_run")
+    return [{f: getattr(buf[i], f) for f, _ in rs_tune_result._fields_} for i in range(k)]
 
 
 def rs_profile_enable(on=True):

@@ -217,6 +217,7 @@ size_t rs_workspace_bytes(int op, size_t n, int key_bytes, int val_bytes, int ra
         return p.total;
     }
     if (op == RS_OP_BATCH) return ALIGN;
+    if (op == RS_OP_TUNE) return (n >= 1 && n <= 65536) ? tune_ws_bytes((int)n) : 0;
     if (op == RS_OP_SEGMENTED) {
         SegPlan p;
         if ((int64_t)n < 0 || !seg_plan(num_segments, (int64_t)n, &p)) return 0;

@@ -100,6 +100,8 @@ bool seg_plan(uint64_t S, int64_t total, SegPlan* p);
 rs_status seg_run(const SegPlan& p, const uint32_t* in, uint32_t* out, const int64_t* offsets,
                   uint64_t S, int64_t total, const SegTable& table, void* ws, hipStream_t st);
 
+size_t tune_ws_bytes(int instances);
+
 // The process-wide tuning table (defaults until rs_tune_set / rs_tune_run).
 SegTable& tune_table();
 

@@ -137,3 +137,31 @@ def test_small_errors(rs):
     with pytest.raises(rs.RsError) as e:
         rs.rs_sort_batch_u32(b, 1000, 1, algo=rs.RS_ALGO_BTN, p=4)     # runs of 256 > 64
     assert e.value.code == rs.RS_ERR_INVALID
+
+
+def test_autotuner_installs_fastest_and_stays_correct(rs, orc):
+    import json
+    import os
+    old = rs.rs_tune_get()
+    try:
+        res = rs.rs_tune_run(instances=256)
+        os.makedirs("gpurun_out", exist_ok=True)
+        with open("gpurun_out/tune_results.json", "w") as f:
+            json.dump(res, f)
+        table = {c: (a, p) for c, a, p in rs.rs_tune_get()}
+        for c in range(1, 15):
+            rows = [r for r in res if r["size_log2"] == c and r["algo"] != rs.RS_ALGO_LSD]
+            assert rows and all(r["us_per_array"] > 0 for r in rows)
+            best = min(rows, key=lambda r: r["us_per_array"])
+            assert best["chosen"] == 1
+            assert table[c][0] == best["algo"]
+            assert any(r["algo"] == rs.RS_ALGO_LSD for r in res if r["size_log2"] == c)
+        # the tuned AUTO path still sorts exactly
+        rng = np.random.default_rng(1)
+        for n in (3, 100, 5000, 16384):
+            a = rng.integers(0, 2**32, (4, n), dtype=np.uint64).astype(np.uint32)
+            out = to_host(rs.rs_sort_batch_u32(to_dev(a.ravel()), n, 4), np.uint32).reshape(4, n)
+            for i in range(4):
+                assert first_mismatch(out[i], orc.lsd(a[i], 8)) is None
+    finally:
+        rs.rs_tune_set(old)
