@@ -1,0 +1,57 @@
+/*
+ * rs_learned.h -- options of the learned-CDF bucket path of librs and the
+ * entry points that expose its network for gradient checks.  The network
+ * is the library's own extension (the paper has none): a monotone MLP
+ * 1 -> 32 -> 32 -> 1 with weights softplus(v) >= 0, tanh hidden units and a
+ * sigmoid output, trained on (feature of a sampled key, mid-rank of that key
+ * in the sample) with Adam.
+ *
+ * Parameter vector layout (MLP_NPARAM = 1153 floats, device memory):
+ *   v1[32] b1[32] v2[32*32] (row-major [out][in]) b2[32] v3[32] b3[1]
+ *   h1 = tanh(softplus(v1) x + b1), h2 = tanh(softplus(v2) h1 + b2),
+ *   y = sigmoid(softplus(v3) . h2 + b3).
+ * All pointers below are device pointers unless stated; calls are
+ * asynchronous on `stream` (a hipStream_t) and return argument errors
+ * synchronously.
+ */
+#ifndef RS_LEARNED_H
+#define RS_LEARNED_H
+
+#include "rs.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+    int32_t train_steps;          /* Adam steps (default 256)                       */
+    float lr;                     /* Adam learning rate (default 1e-2)              */
+    int32_t use_network;          /* 0: buckets from the key's feature alone       */
+    int32_t bucket_cap;           /* pairs one bucket may hold in LDS (<= 6144)    */
+    int32_t feature_mode;         /* -1 automatic, 0 linear in the key, 1 log2     */
+    double fallback_frac;         /* overflowed-key share above which the whole    */
+                                  /* array is sorted by the LSD rounds instead     */
+    int32_t train_blocks;         /* workgroups of the training launch             */
+    int32_t max_fallback_buckets; /* more overflowed buckets: whole-array LSD      */
+} rs_learned_opts;
+
+/* Process-wide options of the LEARNED path (host structs). */
+rs_status rs_learned_set_opts(const rs_learned_opts* opts);
+rs_status rs_learned_get_opts(rs_learned_opts* opts);
+
+/* Number of network parameters (1153). */
+size_t rs_mlp_num_params(void);
+
+/* y[i] = f(x[i]) for i < m (float32, the forward pass the learned path uses). */
+rs_status rs_mlp_forward(const float* params, const float* x, float* y, size_t m, void* stream);
+
+/* grad[0..1152] = gradient of mean_i (f(x_i) - t_i)^2 over the m samples with
+ * respect to the raw parameters (through the softplus); grad[1153] = the
+ * summed squared error.  `grad` holds 1154 floats. */
+rs_status rs_mlp_loss_grad(const float* params, const float* x, const float* t, size_t m,
+                           float* grad, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -19,7 +19,9 @@ RS_OP_SORT, RS_OP_SORT_KV, RS_OP_BATCH, RS_OP_SEGMENTED, RS_OP_TUNE = range(5)
 
 EXPORTS = ["rs_sort_u32", "rs_sort_u64", "rs_sort_kv", "rs_sort_batch_u32", "rs_sort_segmented",
            "rs_workspace_bytes", "rs_small_capacity", "rs_status_string", "rs_get_stats",
-           "rs_tune_set", "rs_tune_get", "rs_tune_run", "rs_profile_enable", "rs_profile_read"]
+           "rs_tune_set", "rs_tune_get", "rs_tune_run", "rs_profile_enable", "rs_profile_read",
+           "rs_learned_set_opts", "rs_learned_get_opts", "rs_mlp_num_params", "rs_mlp_forward",
+           "rs_mlp_loss_grad"]
 
 
 class RsError(RuntimeError):
@@ -51,6 +53,13 @@ class rs_tune_result(ctypes.Structure):
     _fields_ = [("size_log2", ctypes.c_int32), ("algo", ctypes.c_int32), ("p", ctypes.c_int32),
                 ("chosen", ctypes.c_int32), ("us_per_array", ctypes.c_double),
                 ("us_single", ctypes.c_double)]
+
+
+class rs_learned_opts(ctypes.Structure):
+    _fields_ = [("train_steps", ctypes.c_int32), ("lr", ctypes.c_float), ("use_network", ctypes.c_int32),
+                ("bucket_cap", ctypes.c_int32), ("feature_mode", ctypes.c_int32),
+                ("fallback_frac", ctypes.c_double), ("train_blocks", ctypes.c_int32),
+                ("max_fallback_buckets", ctypes.c_int32)]
 
 
 class rs_kernel_time(ctypes.Structure):
@@ -92,6 +101,16 @@ def lib():
         L.rs_tune_get.restype = i
         L.rs_tune_run.argtypes = [vp, sz, i, vp, ctypes.POINTER(rs_tune_result), i]
         L.rs_tune_run.restype = i
+        L.rs_learned_set_opts.argtypes = [ctypes.POINTER(rs_learned_opts)]
+        L.rs_learned_set_opts.restype = i
+        L.rs_learned_get_opts.argtypes = [ctypes.POINTER(rs_learned_opts)]
+        L.rs_learned_get_opts.restype = i
+        L.rs_mlp_num_params.argtypes = []
+        L.rs_mlp_num_params.restype = sz
+        L.rs_mlp_forward.argtypes = [vp, vp, vp, sz, vp]
+        L.rs_mlp_forward.restype = i
+        L.rs_mlp_loss_grad.argtypes = [vp, vp, vp, sz, vp, vp]
+        L.rs_mlp_loss_grad.restype = i
         L.rs_profile_enable.argtypes = [i]
         L.rs_profile_read.argtypes = [ctypes.POINTER(rs_kernel_time), i]
         L.rs_profile_read.restype = i
@@ -182,6 +201,47 @@ def rs_tune_run(instances=1024, ws=None, stream=None):
     if k < 0:
         raise RsError(-k, "rs_tune_run")
     return [{f: getattr(buf[i], f) for f, _ in rs_tune_result._fields_} for i in range(k)]
+
+
+def rs_learned_get_opts():
+    o = rs_learned_opts()
+    _call(lib().rs_learned_get_opts(ctypes.byref(o)), "rs_learned_get_opts")
+    return {f: getattr(o, f) for f, _ in rs_learned_opts._fields_}
+
+
+def rs_learned_set_opts(**kw):
+    """Sets the named options (others keep their value); returns the old ones."""
+    old = rs_learned_get_opts()
+    new = dict(old)
+    new.update(kw)
+    o = rs_learned_opts(**new)
+    _call(lib().rs_learned_set_opts(ctypes.byref(o)), "rs_learned_set_opts")
+    return old
+
+
+def rs_mlp_num_params():
+    return lib().rs_mlp_num_params()
+
+
+def rs_mlp_forward(params, x, y=None, stream=None):
+    _check_dev(params, 4, "params")
+    _check_dev(x, 4, "x")
+    y = x.new_empty(x.shape) if y is None else y
+    _call(lib().rs_mlp_forward(_ptr(params), _ptr(x), _ptr(y), x.numel(), _stream(stream)),
+          "rs_mlp_forward")
+    return y
+
+
+def rs_mlp_loss_grad(params, x, t, grad=None, stream=None):
+    """Returns a float32 tensor of 1154: the gradient (1153) and the summed
+    squared error."""
+    _check_dev(params, 4, "params")
+    _check_dev(x, 4, "x")
+    _check_dev(t, 4, "t")
+    grad = params.new_empty(rs_mlp_num_params() + 1) if grad is None else grad
+    _call(lib().rs_mlp_loss_grad(_ptr(params), _ptr(x), _ptr(t), x.numel(), _ptr(grad),
+                                 _stream(stream)), "rs_mlp_loss_grad")
+    return grad
 
 
 def rs_profile_enable(on=True):

@@ -4,6 +4,7 @@
 // rs_get_stats.
 #include <string.h>
 
+#include "../../include/rs_learned.h"
 #include "rs_internal.hpp"
 
 namespace rs {
@@ -53,6 +54,33 @@ rs_status sort_lsd(const void* kin, void* kout, const void* vin, void* vout, siz
         g_call.status = reinterpret_cast<const uint32_t*>(static_cast<unsigned char*>(ws) + p.off_status);
         g_call.pending = true;
     }
+    return rc;
+}
+
+bool overlaps(const void* a, size_t abytes, const void* b, size_t bbytes);
+
+// uint64 keys (optional uint64 values) through learned-CDF buckets; small or
+// in-place sorts take the LSD rounds (the learned path needs the input
+// intact for its fallback).
+rs_status sort_learned(const void* kin, void* kout, const void* vin, void* vout, size_t n, int vb,
+                       void* ws, size_t ws_bytes, hipStream_t st) {
+    if (vb != 0 && vb != 8) return RS_ERR_UNSUPPORTED;
+    if (n < (1u << 16) || n >= (1ull << 32) || kin == kout || (vb && vin == vout)) {
+        rs_status rc = sort_lsd(kin, kout, vin, vout, n, 8, vb, 8, ws, ws_bytes, st);
+        g_call.stats.algo = RS_ALGO_LEARNED;
+        g_call.stats.fallback = 1;
+        return rc;
+    }
+    begin_call(RS_ALGO_LEARNED);
+    g_call.stats.radix_bits = 8;
+    LearnReport rep;
+    rs_status rc = learned_run(kin, kout, vin, vout, n, vb, ws, ws_bytes, st, &rep);
+    g_call.stats.fallback = rep.fallback;
+    g_call.stats.buckets_overflowed = rep.buckets_overflowed;
+    g_call.stats.keys_overflowed = rep.keys_overflowed;
+    g_call.stats.train_loss = rep.train_loss;
+    g_call.stats.device_error = rep.device_error;
+    g_call.stats.passes = rep.fallback ? 8 : 2;
     return rc;
 }
 
@@ -113,6 +141,9 @@ rs_status sort_keys_common(const void* kin, void* kout, const void* vin, void* v
         case RS_ALGO_AUTO:
         case RS_ALGO_LSD:
             return sort_lsd(kin, kout, vin, vout, n, kb, vb, bits, ws, ws_bytes, st);
+        case RS_ALGO_LEARNED:
+            if (kb != 8) return RS_ERR_UNSUPPORTED;
+            return sort_learned(kin, kout, vin, vout, n, vb, ws, ws_bytes, st);
         case RS_ALGO_BTN:
         case RS_ALGO_OET:
         case RS_ALGO_LDS_RADIX:
@@ -212,6 +243,13 @@ size_t rs_workspace_bytes(int op, size_t n, int key_bytes, int val_bytes, int ra
     radix_bits = default_bits(radix_bits);
     if (op == RS_OP_SORT || op == RS_OP_SORT_KV) {
         if (algo == RS_ALGO_BTN || algo == RS_ALGO_OET || algo == RS_ALGO_LDS_RADIX) return ALIGN;
+        if (algo == RS_ALGO_LEARNED && key_bytes == 8) {
+            const int vb = op == RS_OP_SORT ? 0 : val_bytes;
+            LsdPlan p;
+            if (!lsd_plan(n, 8, vb, 8, &p)) return 0;
+            const size_t l = (n >= (1u << 16) && n < (1ull << 32)) ? learned_ws_bytes(n, vb) : 0;
+            return l > p.total ? l : p.total;
+        }
         LsdPlan p;
         if (!lsd_plan(n, key_bytes, op == RS_OP_SORT ? 0 : val_bytes, radix_bits, &p)) return 0;
         return p.total;
@@ -256,6 +294,54 @@ rs_status rs_get_stats(rs_stats* out) {
 }
 
 }  // extern "C"
+
+// ---- learned path: options and network entry points --------------------------
+
+extern "C" rs_status rs_learned_set_opts(const rs_learned_opts* o) {
+    if (!o || o->train_steps < 0 || o->train_steps > 100000 || !(o->lr > 0.f) || o->bucket_cap < 2 ||
+        o->feature_mode < -1 || o->feature_mode > 1 || o->fallback_frac < 0.0 || o->train_blocks < 1 ||
+        o->train_blocks > 4096 || o->max_fallback_buckets < 0)
+        return RS_ERR_INVALID;
+    rs::LearnOpts& d = rs::learn_opts();
+    d.train_steps = o->train_steps;
+    d.lr = o->lr;
+    d.use_network = o->use_network ? 1 : 0;
+    d.bucket_cap = o->bucket_cap;
+    d.feature_mode = o->feature_mode;
+    d.fallback_frac = o->fallback_frac;
+    d.train_blocks = o->train_blocks;
+    d.max_fallback_buckets = o->max_fallback_buckets;
+    return RS_OK;
+}
+
+extern "C" rs_status rs_learned_get_opts(rs_learned_opts* o) {
+    if (!o) return RS_ERR_INVALID;
+    const rs::LearnOpts& d = rs::learn_opts();
+    o->train_steps = d.train_steps;
+    o->lr = d.lr;
+    o->use_network = d.use_network;
+    o->bucket_cap = d.bucket_cap;
+    o->feature_mode = d.feature_mode;
+    o->fallback_frac = d.fallback_frac;
+    o->train_blocks = d.train_blocks;
+    o->max_fallback_buckets = d.max_fallback_buckets;
+    return RS_OK;
+}
+
+extern "C" size_t rs_mlp_num_params(void) { return rs::MLP_NPARAM; }
+
+extern "C" rs_status rs_mlp_forward(const float* params, const float* x, float* y, size_t m, void* stream) {
+    if (m && (!params || !x || !y)) return RS_ERR_INVALID;
+    (void)hipGetLastError();
+    return rs::mlp_forward(params, x, y, m, static_cast<hipStream_t>(stream));
+}
+
+extern "C" rs_status rs_mlp_loss_grad(const float* params, const float* x, const float* t, size_t m,
+                                      float* grad, void* stream) {
+    if (!m || !params || !x || !t || !grad) return RS_ERR_INVALID;
+    (void)hipGetLastError();
+    return rs::mlp_loss_grad(params, x, t, m, grad, static_cast<hipStream_t>(stream));
+}
 
 // ---- tuning table -----------------------------------------------------------
 

@@ -8,6 +8,7 @@ namespace rs {
 constexpr int WAVE = 64;
 
 template <typename T> struct KeyMax;
+template <> struct KeyMax<uint16_t> { static constexpr uint16_t v = 0xFFFFu; };
 template <> struct KeyMax<uint32_t> { static constexpr uint32_t v = 0xFFFFFFFFu; };
 template <> struct KeyMax<uint64_t> { static constexpr uint64_t v = ~0ull; };
 

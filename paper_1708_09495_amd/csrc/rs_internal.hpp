@@ -46,7 +46,8 @@ inline void prof(hipStream_t st, int kid, int phase) {
 // ---- LSD radix sort (count-sort rounds, Section 3) -----------------------
 struct LsdPlan {
     size_t n = 0;
-    int kb = 4, vb = 0;      // key / value bytes
+    int kb = 4, vb = 0;      // key / value bytes (kb = 2: 16-bit digit keys)
+    int vb2 = 0;             // bytes of a second payload (16-bit keys only)
     int bits = 8;            // radix bits b
     int passes = 0;          // ceil(8*kb / b)
     int R = 256;             // 2^b
@@ -55,17 +56,17 @@ struct LsdPlan {
     bool lb64 = false;       // 64-bit look-back words (n >= 2^30)
     size_t lb_words = 0;     // look-back words per pass (tiles * R)
     // workspace layout (byte offsets)
-    size_t off_status = 0, off_ctr = 0, off_hist = 0, off_lb = 0, off_tk = 0, off_tv = 0;
+    size_t off_status = 0, off_ctr = 0, off_hist = 0, off_lb = 0, off_tk = 0, off_tv = 0, off_tv2 = 0;
     size_t zero_bytes = 0;   // bytes from off_status that must be zeroed (status, ctr, hist)
     size_t total = 0;
 };
 
-// Plans an LSD sort; returns false when (kb, vb, bits) is not supported.
-bool lsd_plan(size_t n, int kb, int vb, int bits, LsdPlan* p);
+// Plans an LSD sort; returns false when (kb, vb, bits, vb2) is not supported.
+bool lsd_plan(size_t n, int kb, int vb, int bits, LsdPlan* p, int vb2 = 0);
 
 // Enqueues the whole LSD sort on `st`.  `ws` holds at least p.total bytes.
 rs_status lsd_run(const LsdPlan& p, const void* kin, void* kout, const void* vin, void* vout,
-                  void* ws, hipStream_t st);
+                  void* ws, hipStream_t st, const void* vin2 = nullptr, void* vout2 = nullptr);
 
 // Records the HIP error of a failed launch or runtime call for rs_get_stats
 // and returns RS_ERR_HIP.
@@ -104,6 +105,34 @@ size_t tune_ws_bytes(int instances);
 
 // The process-wide tuning table (defaults until rs_tune_set / rs_tune_run).
 SegTable& tune_table();
+
+// ---- learned-CDF buckets -------------------------------------------------------
+struct LearnOpts {
+    int32_t train_steps;          // Adam steps
+    float lr;                     // Adam learning rate
+    int32_t use_network;          // 0: bucket by the feature alone (no network)
+    int32_t bucket_cap;           // LDS capacity of a bucket (<= 6144 pairs)
+    int32_t feature_mode;         // -1 automatic, 0 linear, 1 log-scaled
+    double fallback_frac;         // overflowed-key share that sends the whole array to LSD
+    int32_t train_blocks;         // workgroups of the training launch
+    int32_t max_fallback_buckets; // more overflowed buckets than this: whole-array LSD
+};
+struct LearnReport {
+    int32_t fallback;
+    int64_t buckets_overflowed, keys_overflowed;
+    double train_loss;
+    uint32_t device_error, unsorted;
+    int32_t feature_mode;
+};
+LearnOpts& learn_opts();
+size_t learned_ws_bytes(size_t n, int vb);
+// Synchronises `st` (it reads the overflow counts back).
+rs_status learned_run(const void* kin, void* kout, const void* vin, void* vout, size_t n, int vb, void* ws,
+                      size_t ws_bytes, hipStream_t st, LearnReport* rep);
+rs_status mlp_forward(const float* params, const float* x, float* y, size_t m, hipStream_t st);
+rs_status mlp_loss_grad(const float* params, const float* x, const float* t, size_t m, float* grad,
+                        hipStream_t st);
+constexpr int MLP_NPARAM = 1153;
 
 // Zero-fill of device memory by a kernel (no hipMemsetAsync, so callers may
 // capture the stream into a graph).

@@ -1,0 +1,1174 @@
+// rs_learned.hip -- learned-CDF bucket sort (an extension beyond the paper)
+// for uint64 keys with an optional uint64 payload, stable.
+//
+//   1. sample 2^16 keys (with replacement, seeded) and sort the sample with
+//      the LSD rounds; targets are mid-ranks (#{s < k} + #{s <= k}) / 2m;
+//   2. train a monotone MLP 1 -> 32 -> 32 -> 1 (weights = softplus of free
+//      parameters, tanh hidden units, sigmoid output) on (feature, target)
+//      with Adam, all steps in one cooperative launch;
+//   3. invert the network into 65535 key splitters: s_j = the least key whose
+//      bucket floor(f(x(key)) * 65536) is at least j (binary search over
+//      keys); a prefix max makes them non-decreasing, so bucket(key) =
+//      #{j : s_j <= key} is monotone in the key by construction;
+//   4. bucket id of every key by a two-level search of the splitters;
+//   5. two stable radix-2^8 rounds on the 16-bit bucket id carry each key
+//      and value into its bucket, in input order within the bucket;
+//   6. every bucket is sorted stably in LDS (on key - bucket minimum, only
+//      as many 8-bit rounds as the bucket's key range needs); a bucket whose
+//      keys are all equal is already in order; a bucket above the LDS
+//      capacity is recorded as overflowed;
+//   7. overflowed buckets are sorted by the LSD rounds in place; if too many
+//      keys overflowed, or a final check finds the output unsorted, the
+//      whole array is sorted by the LSD rounds from the untouched input.
+// Every path ends in the stable sort of the input, so the output does not
+// depend on how well the network fits; the fit only decides the speed.
+#include <math.h>
+#include <string.h>
+
+#include <vector>
+
+#include "rs_dev.h"
+#include "rs_internal.hpp"
+
+namespace rs {
+namespace {
+
+constexpr int H = 32;
+constexpr int NP = 4 * H + H * H + 1;  // 1153 free parameters
+constexpr int P_V1 = 0, P_B1 = H, P_V2 = 2 * H, P_B2 = 2 * H + H * H, P_V3 = P_B2 + H, P_B3 = P_V3 + H;
+constexpr uint32_t NB = 65536;         // buckets
+constexpr uint32_t M = 65536;          // sample size
+constexpr int TR_NT = 256;             // training threads per workgroup
+constexpr int BS_NT = 512;             // bucket-sort threads per workgroup
+constexpr int BS_ITEMS = 12;
+constexpr uint32_t BS_CAP = BS_NT * BS_ITEMS;  // 6144 pairs
+constexpr int AS_NT = 256;             // assignment threads per workgroup
+constexpr int AS_KEYS = 8;             // keys per assignment thread
+constexpr int TOP = 4096;              // splitter groups of 16 held in LDS
+constexpr int GBUF = NP + 1;           // gradient buffer: parameters + loss
+constexpr uint32_t MID_CAP = 1u << 20; // largest bucket sorted by one workgroup
+constexpr int KNOTS = 256;             // calibration intervals of the network output
+
+struct State {
+    uint64_t kmin, kmax;
+    double inv_span, inv_logspan;
+    int32_t mode;          // feature: 0 linear in the key, 1 linear in log2(key)
+    uint32_t reach;        // number of reachable splitters
+    float loss;            // last training loss (mean squared error)
+    uint32_t bar_count, bar_gen;
+    uint32_t ovf_buckets;          // buckets over the LDS capacity
+    unsigned long long ovf_keys;   // keys in them
+    uint32_t big_buckets;          // buckets too big for one workgroup (host fallback)
+    unsigned long long big_keys;
+    uint32_t unsorted;
+    uint32_t err;
+};
+
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+
+__device__ __forceinline__ float softplusf_(float v) { return v > 20.f ? v : log1pf(expf(v)); }
+__device__ __forceinline__ float sigmoidf_(float v) { return 1.f / (1.f + expf(-v)); }
+
+// Feature of a key: its position in [kmin, kmax], linear or log-scaled,
+// computed in double and rounded once to float.
+__device__ __forceinline__ float feat(uint64_t k, const State& s) {
+    const uint64_t d = k > s.kmin ? k - s.kmin : 0ull;
+    double x = s.mode ? log2((double)d + 1.0) * s.inv_logspan : (double)d * s.inv_span;
+    x = x < 0.0 ? 0.0 : (x > 1.0 ? 1.0 : x);
+    return (float)x;
+}
+
+// Network weights in LDS: softplus of the free parameters (and its
+// derivative, the logistic function, for the backward pass).
+struct Mlp {
+    float w1[H], b1[H], w2[H * H], b2[H], w3[H], b3;
+    float s1[H], s2[H * H], s3[H];
+};
+
+__device__ void mlp_derive(const float* raw, Mlp& W, bool with_sig) {
+    for (int p = threadIdx.x; p < NP; p += blockDim.x) {
+        const float v = raw[p];
+        if (p < P_B1) {
+            W.w1[p] = softplusf_(v);
+            if (with_sig) W.s1[p] = sigmoidf_(v);
+        } else if (p < P_V2) {
+            W.b1[p - P_B1] = v;
+        } else if (p < P_B2) {
+            W.w2[p - P_V2] = softplusf_(v);
+            if (with_sig) W.s2[p - P_V2] = sigmoidf_(v);
+        } else if (p < P_V3) {
+            W.b2[p - P_B2] = v;
+        } else if (p < P_B3) {
+            W.w3[p - P_V3] = softplusf_(v);
+            if (with_sig) W.s3[p - P_V3] = sigmoidf_(v);
+        } else {
+            W.b3 = v;
+        }
+    }
+}
+
+// Forward pass with a fixed order of operations (ascending input index,
+// one fused multiply-add per term).
+__device__ __forceinline__ float mlp_fwd(const Mlp& W, float x, float (&h1)[H], float (&h2)[H]) {
+#pragma unroll
+    for (int i = 0; i < H; ++i) h1[i] = tanhf(fmaf(W.w1[i], x, W.b1[i]));
+#pragma unroll 4
+    for (int o = 0; o < H; ++o) {
+        float s = W.b2[o];
+#pragma unroll
+        for (int i = 0; i < H; ++i) s = fmaf(W.w2[o * H + i], h1[i], s);
+        h2[o] = tanhf(s);
+    }
+    float z = W.b3;
+#pragma unroll
+    for (int o = 0; o < H; ++o) z = fmaf(W.w3[o], h2[o], z);
+    return 1.f / (1.f + expf(-z));
+}
+
+__device__ __forceinline__ float mlp_y(const Mlp& W, float x) {
+    float h1[H], h2[H];
+    return mlp_fwd(W, x, h1, h2);
+}
+
+// Calibration: knot[g] is the network output at the sample's g/KNOTS
+// quantile (non-decreasing), and u = (g + (y - knot[g]) / (knot[g+1] -
+// knot[g])) / KNOTS maps each interval between knots to an equal share of
+// (0, 1): the sample fixes how much of the key mass lies between knots, the
+// network how it spreads inside each interval.  The map stays monotone.
+__device__ __forceinline__ float calibrate(float y, const float* knot) {
+    if (y <= knot[0]) return 0.f;
+    if (y >= knot[KNOTS]) return 1.f;
+    int lo = 0, hi = KNOTS;  // knot[lo] <= y < knot[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (knot[mid] <= y) lo = mid;
+        else hi = mid;
+    }
+    const float d = knot[lo + 1] - knot[lo];
+    const float f = d > 0.f ? (y - knot[lo]) / d : 0.f;
+    return ((float)lo + fminf(fmaxf(f, 0.f), 1.f)) * (1.0f / (float)KNOTS);
+}
+
+__device__ __forceinline__ uint32_t bucket_of(const Mlp& W, const State& s, const float* knot, uint64_t k,
+                                              int use_net) {
+    const float x = feat(k, s);
+    const float y = use_net ? mlp_y(W, x) : x;
+    const float b = calibrate(y, knot) * (float)NB;
+    return b >= (float)(NB - 1) ? NB - 1 : (b <= 0.f ? 0u : (uint32_t)b);
+}
+
+// ---- 1. sample, setup, targets ----------------------------------------------
+
+__global__ void k_sample(const uint64_t* __restrict__ keys, uint64_t n, uint64_t seed,
+                         uint64_t* __restrict__ sample) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < M) sample[i] = keys[mix64(seed + (uint64_t)(i + 1) * 0x9E3779B97F4A7C15ULL) % n];
+}
+
+__global__ void k_setup(const uint64_t* __restrict__ s, State* st, int mode_req) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const uint64_t kmin = s[0], kmax = s[M - 1];
+    const uint64_t span = kmax - kmin;
+    st->kmin = kmin;
+    st->kmax = kmax;
+    st->inv_span = span ? 1.0 / (double)span : 0.0;
+    const double ls = log2((double)span + 1.0);
+    st->inv_logspan = span ? 1.0 / ls : 0.0;
+    // log features when the linear positions crowd near zero (the sample's
+    // median sits in the lowest thousandth of the key range)
+    const double xmed = (double)(s[M / 2] - kmin) * st->inv_span;
+    st->mode = mode_req >= 0 ? mode_req : (xmed < 1e-3 ? 1 : 0);
+}
+
+__global__ void k_targets(const uint64_t* __restrict__ s, const State* __restrict__ st,
+                          float* __restrict__ xs, float* __restrict__ ts) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= M) return;
+    const uint64_t k = s[i];
+    uint32_t lo = 0, hi = M;  // first index with s >= k
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (s[mid] < k) lo = mid + 1;
+        else hi = mid;
+    }
+    const uint32_t first = lo;
+    lo = first;
+    hi = M;  // first index with s > k
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (s[mid] <= k) lo = mid + 1;
+        else hi = mid;
+    }
+    xs[i] = feat(k, *st);
+    ts[i] = (float)(((double)first + (double)lo) / (2.0 * (double)M));
+}
+
+// ---- 2. training -------------------------------------------------------------------
+
+// Grid-wide barrier for a cooperative launch (every workgroup resident).
+// Bounded: a workgroup that waits SPIN_LIMIT polls records an error and
+// gives up, so the kernel always ends.
+__device__ bool grid_sync(State* st, uint32_t nblocks) {
+    __shared__ uint32_t s_ok;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        s_ok = 1;
+        const uint32_t g0 = __hip_atomic_load(&st->bar_gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __threadfence();
+        if (atomicAdd(&st->bar_count, 1u) == nblocks - 1) {
+            __hip_atomic_store(&st->bar_count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __threadfence();
+            atomicAdd(&st->bar_gen, 1u);
+        } else {
+            uint32_t spins = 0;
+            while (__hip_atomic_load(&st->bar_gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g0) {
+                if (++spins > SPIN_LIMIT) {
+                    atomicOr(&st->err, STATUS_SPIN);
+                    s_ok = 0;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(2);
+            }
+        }
+        __threadfence();
+    }
+    __syncthreads();
+    return s_ok != 0;
+}
+
+struct TrainCfg {
+    int steps;
+    float lr, beta1, beta2, eps;
+    uint32_t m;        // samples
+    int grad_only;     // 1: one gradient over all m samples into gbuf[0], no update
+};
+
+// Data-dependent initialisation from the sorted sample's features xs:
+// hidden unit i of layer 1 starts as a step centred in the i-th of 32
+// equal-mass slices of the sample, as steep as that slice is narrow, so the
+// units sit where the keys are; layer 2 starts near the identity (a unit
+// weight on the diagonal, about 3e-4 elsewhere) and the output layer sums the
+// units into (0, 1).  Training then refines every parameter.
+__device__ float inv_softplus(float w) { return w > 20.f ? w : logf(expm1f(w)); }
+
+__device__ float init_param(int p, const float* __restrict__ xs, uint32_t m) {
+    if (p < P_B2 && p >= P_V2) {
+        const int o = (p - P_V2) / H, i = (p - P_V2) % H;
+        return o == i ? inv_softplus(1.0f) : -8.0f;
+    }
+    if (p < P_V2) {
+        const int i = p < P_B1 ? p : p - P_B1;
+        const float lo = xs[(uint64_t)i * m / H];
+        const float hi = xs[(uint64_t)(i + 1) * m / H < m ? (uint64_t)(i + 1) * m / H : m - 1];
+        const float c = 0.5f * (lo + hi);
+        float w = 2.0f / fmaxf(hi - lo, 1e-6f);
+        w = fminf(w, 1e6f);
+        return p < P_B1 ? inv_softplus(w) : -w * c;
+    }
+    if (p < P_V3) return 0.0f;                       // b2
+    if (p < P_B3) return inv_softplus(4.0f / (H * 0.76f));  // w3: 32 units of +-0.76 span +-4
+    return 0.0f;                                     // b3
+}
+
+__global__ __launch_bounds__(TR_NT) void k_train(const float* __restrict__ xs, const float* __restrict__ ts,
+                                                 float* __restrict__ params, float* __restrict__ gbuf,
+                                                 State* __restrict__ st, TrainCfg cfg, int init) {
+    __shared__ float raw[NP], m1[NP], m2[NP], gl[GBUF];
+    __shared__ Mlp W;
+    __shared__ float A[TR_NT][H + 1], Hm[TR_NT][H + 1];
+    __shared__ float xsl[TR_NT], dzl[TR_NT], e2[TR_NT];
+    const int t = threadIdx.x;
+    const uint32_t G = gridDim.x, g = blockIdx.x;
+    for (int p = t; p < NP; p += TR_NT) {
+        raw[p] = init ? init_param(p, xs, cfg.m) : params[p];
+        m1[p] = 0.f;
+        m2[p] = 0.f;
+    }
+    __syncthreads();
+    mlp_derive(raw, W, true);
+    __syncthreads();
+    const uint32_t bsz = cfg.grad_only ? cfg.m : (uint32_t)G * TR_NT;
+    const int steps = cfg.grad_only ? 1 : cfg.steps;
+    const uint32_t slices = cfg.grad_only ? (cfg.m + TR_NT - 1) / TR_NT : 1;
+    bool ok = true;
+    for (int step = 0; step < steps && ok; ++step) {
+        float* cur = gbuf + (size_t)(cfg.grad_only ? 0 : step % 3) * GBUF;
+        if (!cfg.grad_only && g == 0) {
+            // zero the buffer the step after this one will fill; it was last
+            // read two steps ago, before every workgroup reached the previous
+            // barrier
+            float* nxt = gbuf + (size_t)((step + 1) % 3) * GBUF;
+            for (int p = t; p < GBUF; p += TR_NT) nxt[p] = 0.f;
+        }
+        for (int p = t; p < GBUF; p += TR_NT) gl[p] = 0.f;
+        // training: one slice of 256 samples per workgroup per step, cycling
+        // through the sample; gradient only: slices g, g+G, ... of all m
+        const uint32_t sl_first = cfg.grad_only ? g : 0u;
+        const uint32_t sl_end = cfg.grad_only ? slices : 1u;
+        const uint32_t sl_step = cfg.grad_only ? G : 1u;
+        for (uint32_t sl = sl_first; sl < sl_end; sl += sl_step) {
+            const uint32_t base = cfg.grad_only ? sl * TR_NT
+                                                : ((uint32_t)(step * G + g) * TR_NT) % cfg.m;
+            const uint32_t i = base + t;
+            const bool live = i < cfg.m;
+            const float x = live ? xs[i] : 0.f, tt = live ? ts[i] : 0.f;
+            float h1[H], h2[H];
+            const float y = mlp_fwd(W, x, h1, h2);
+            const float e = live ? (y - tt) : 0.f;
+            const float dz = (2.f * e / (float)bsz) * y * (1.f - y);
+            float da2[H];
+#pragma unroll
+            for (int o = 0; o < H; ++o) da2[o] = dz * W.w3[o] * (1.f - h2[o] * h2[o]);
+            __syncthreads();
+#pragma unroll
+            for (int o = 0; o < H; ++o) {
+                A[t][o] = da2[o];
+                Hm[t][o] = h1[o];
+            }
+            xsl[t] = x;
+            dzl[t] = dz;
+            e2[t] = e * e;
+            __syncthreads();
+            {   // dW2 (4 entries per thread) and db2
+                const int o = t >> 3, i0 = (t & 7) * 4;
+                float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f, acc3 = 0.f, asum = 0.f;
+                for (int s = 0; s < TR_NT; ++s) {
+                    const float a = A[s][o];
+                    acc0 = fmaf(a, Hm[s][i0 + 0], acc0);
+                    acc1 = fmaf(a, Hm[s][i0 + 1], acc1);
+                    acc2 = fmaf(a, Hm[s][i0 + 2], acc2);
+                    acc3 = fmaf(a, Hm[s][i0 + 3], acc3);
+                    asum += a;
+                }
+                gl[P_V2 + o * H + i0 + 0] += acc0 * W.s2[o * H + i0 + 0];
+                gl[P_V2 + o * H + i0 + 1] += acc1 * W.s2[o * H + i0 + 1];
+                gl[P_V2 + o * H + i0 + 2] += acc2 * W.s2[o * H + i0 + 2];
+                gl[P_V2 + o * H + i0 + 3] += acc3 * W.s2[o * H + i0 + 3];
+                if ((t & 7) == 0) gl[P_B2 + o] += asum;
+            }
+            // da1 = (W2^T da2) (1 - h1^2); dz * h2 for the output weights
+            float da1[H];
+#pragma unroll
+            for (int i = 0; i < H; ++i) da1[i] = 0.f;
+#pragma unroll 4
+            for (int o = 0; o < H; ++o) {
+#pragma unroll
+                for (int i = 0; i < H; ++i) da1[i] = fmaf(da2[o], W.w2[o * H + i], da1[i]);
+            }
+            __syncthreads();
+#pragma unroll
+            for (int i = 0; i < H; ++i) {
+                Hm[t][i] = da1[i] * (1.f - h1[i] * h1[i]);
+                A[t][i] = dz * h2[i];
+            }
+            __syncthreads();
+            if (t < H) {
+                float sb = 0.f, sv = 0.f;
+                for (int s = 0; s < TR_NT; ++s) {
+                    sb += Hm[s][t];
+                    sv = fmaf(Hm[s][t], xsl[s], sv);
+                }
+                gl[P_B1 + t] += sb;
+                gl[P_V1 + t] += sv * W.s1[t];
+            } else if (t < 2 * H) {
+                float sv = 0.f;
+                for (int s = 0; s < TR_NT; ++s) sv += A[s][t - H];
+                gl[P_V3 + t - H] += sv * W.s3[t - H];
+            } else if (t == 2 * H) {
+                float sb = 0.f;
+                for (int s = 0; s < TR_NT; ++s) sb += dzl[s];
+                gl[P_B3] += sb;
+            } else if (t == 2 * H + 1) {
+                float se = 0.f;
+                for (int s = 0; s < TR_NT; ++s) se += e2[s];
+                gl[NP] += se;
+            }
+            __syncthreads();
+        }
+        for (int p = t; p < GBUF; p += TR_NT) atomicAdd(&cur[p], gl[p]);
+        if (cfg.grad_only) break;
+        ok = grid_sync(st, G);
+        // every workgroup applies the same Adam step to its own copy
+        const float c1 = 1.f - powf(cfg.beta1, (float)(step + 1));
+        const float c2 = 1.f - powf(cfg.beta2, (float)(step + 1));
+        for (int p = t; p < NP; p += TR_NT) {
+            const float gr = __hip_atomic_load(&cur[p], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            m1[p] = cfg.beta1 * m1[p] + (1.f - cfg.beta1) * gr;
+            m2[p] = cfg.beta2 * m2[p] + (1.f - cfg.beta2) * gr * gr;
+            raw[p] -= cfg.lr * (m1[p] / c1) / (sqrtf(m2[p] / c2) + cfg.eps);
+        }
+        if (g == 0 && t == 0)
+            st->loss = __hip_atomic_load(&cur[NP], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) / (float)bsz;
+        __syncthreads();
+        mlp_derive(raw, W, true);
+        __syncthreads();
+    }
+    if (!cfg.grad_only && g == 0)
+        for (int p = t; p < NP; p += TR_NT) params[p] = raw[p];
+}
+
+// ---- 3a. calibration knots ------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_calibrate(const float* __restrict__ params,
+                                                   const float* __restrict__ xs, float* __restrict__ knot,
+                                                   int use_net) {
+    __shared__ Mlp W;
+    __shared__ float raw[NP];
+    __shared__ float kv[KNOTS + 1];
+    for (int p = threadIdx.x; p < NP; p += blockDim.x) raw[p] = params[p];
+    __syncthreads();
+    mlp_derive(raw, W, false);
+    __syncthreads();
+    for (int g = threadIdx.x; g <= KNOTS; g += blockDim.x) {
+        const uint32_t i = (uint64_t)g * M / KNOTS < M ? (uint32_t)((uint64_t)g * M / KNOTS) : M - 1;
+        const float x = xs[i];
+        kv[g] = use_net ? mlp_y(W, x) : x;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float m = kv[0];
+        for (int g = 0; g <= KNOTS; ++g) {
+            m = kv[g] > m ? kv[g] : m;
+            knot[g] = m;
+        }
+    }
+}
+
+// ---- 3. splitters ------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_splitters(const float* __restrict__ params, State* __restrict__ st,
+                                                   const float* __restrict__ knot_g, uint64_t* __restrict__ spl,
+                                                   int use_net) {
+    __shared__ Mlp W;
+    __shared__ float raw[NP];
+    __shared__ float knot[KNOTS + 1];
+    __shared__ State S;
+    for (int p = threadIdx.x; p < NP; p += blockDim.x) raw[p] = params[p];
+    for (int g = threadIdx.x; g <= KNOTS; g += blockDim.x) knot[g] = knot_g[g];
+    if (threadIdx.x == 0) S = *st;
+    __syncthreads();
+    mlp_derive(raw, W, false);
+    __syncthreads();
+    const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x + 1;  // 1 .. NB-1
+    if (j >= NB) {
+        if (j == NB) spl[NB - 1] = ~0ull;  // pad entry
+        return;
+    }
+    const uint32_t blo = bucket_of(W, S, knot, S.kmin, use_net);
+    const uint32_t bhi = bucket_of(W, S, knot, S.kmax, use_net);
+    uint64_t r;
+    if (j <= blo) r = 0;
+    else if (j > bhi) r = ~0ull;  // no key reaches bucket j
+    else {
+        uint64_t lo = S.kmin, hi = S.kmax;  // bucket(lo) < j <= bucket(hi)
+        while (hi - lo > 1) {
+            const uint64_t mid = lo + (hi - lo) / 2;
+            if (bucket_of(W, S, knot, mid, use_net) >= j) hi = mid;
+            else lo = mid;
+        }
+        r = hi;
+    }
+    spl[j - 1] = r;
+    if (j == 1) st->reach = bhi;
+}
+
+// Prefix maximum over the splitters (one workgroup of 1024 threads): makes
+// them non-decreasing even where float rounding bends the network.
+__global__ __launch_bounds__(1024) void k_split_fix(uint64_t* __restrict__ spl) {
+    __shared__ uint64_t part[1024];
+    const int t = threadIdx.x;
+    constexpr int PER = NB / 1024;
+    uint64_t m = 0;
+    for (int q = 0; q < PER; ++q) {
+        const uint64_t v = spl[t * PER + q];
+        m = v > m ? v : m;
+    }
+    part[t] = m;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+        const uint64_t v = t >= o ? part[t - o] : 0;
+        __syncthreads();
+        if (v > part[t]) part[t] = v;
+        __syncthreads();
+    }
+    uint64_t run = t ? part[t - 1] : 0;
+    for (int q = 0; q < PER; ++q) {
+        const uint64_t v = spl[t * PER + q];
+        run = v > run ? v : run;
+        spl[t * PER + q] = run;
+    }
+}
+
+// ---- 4. bucket ids --------------------------------------------------------------------
+
+__global__ __launch_bounds__(AS_NT) void k_assign(const uint64_t* __restrict__ keys, uint64_t n,
+                                                  const uint64_t* __restrict__ spl,
+                                                  const State* __restrict__ st, uint16_t* __restrict__ bid) {
+    __shared__ uint64_t top[TOP];  // top[b] = spl[16 b + 15]
+    for (int b = threadIdx.x; b < TOP; b += AS_NT) top[b] = spl[16 * b + 15];
+    const uint32_t reach = st->reach;
+    __syncthreads();
+    const uint64_t per_block = (uint64_t)AS_NT * AS_KEYS;
+    for (uint64_t base = (uint64_t)blockIdx.x * per_block; base < n; base += (uint64_t)gridDim.x * per_block) {
+        uint64_t k[AS_KEYS];
+        uint32_t lo[AS_KEYS];
+#pragma unroll
+        for (int q = 0; q < AS_KEYS; ++q) {
+            const uint64_t i = base + (uint64_t)q * AS_NT + threadIdx.x;
+            k[q] = i < n ? keys[i] : 0;
+            lo[q] = 0;
+        }
+        // number of groups whose last splitter is <= key (12 halvings)
+#pragma unroll
+        for (int step = TOP / 2; step >= 1; step >>= 1) {
+#pragma unroll
+            for (int q = 0; q < AS_KEYS; ++q)
+                if (top[lo[q] + step - 1] <= k[q]) lo[q] += step;
+        }
+#pragma unroll
+        for (int q = 0; q < AS_KEYS; ++q) {
+            const uint64_t i = base + (uint64_t)q * AS_NT + threadIdx.x;
+            uint32_t ub = 16u * lo[q];
+            if (top[TOP - 1] <= k[q]) ub = NB;
+            else {
+                // within the group: the last entry is > key, so 4 halvings
+                // over its first 15 entries find how many are <= key
+                const uint64_t* g = spl + 16u * lo[q];
+                uint32_t c = 0;
+#pragma unroll
+                for (int step = 8; step >= 1; step >>= 1)
+                    if (g[c + step - 1] <= k[q]) c += step;
+                ub += c;
+            }
+            const uint32_t b = ub < reach ? ub : reach;
+            if (i < n) bid[i] = (uint16_t)(b < NB ? b : NB - 1);
+        }
+    }
+}
+
+// ---- 6. buckets ----------------------------------------------------------------------
+
+__global__ void k_bucket_first(const uint16_t* __restrict__ bid, uint64_t n, uint32_t* __restrict__ start) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        if (i == 0 || bid[i] != bid[i - 1]) start[bid[i]] = (uint32_t)i;
+}
+
+// start[b] = min over b' >= b of start[b'] (empty buckets start where the
+// next non-empty one does); one workgroup of 1024 threads.
+__global__ __launch_bounds__(1024) void k_bucket_fix(uint32_t* __restrict__ start) {
+    __shared__ uint32_t part[1024];
+    const int t = threadIdx.x;
+    constexpr int PER = NB / 1024;
+    const int hi = NB - 1 - t * PER;  // this thread's chunk, walked downwards
+    uint32_t m = start[NB];
+    uint32_t loc = 0xFFFFFFFFu;
+    for (int q = 0; q < PER; ++q) {
+        const uint32_t v = start[hi - q];
+        loc = v < loc ? v : loc;
+    }
+    part[t] = loc;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+        const uint32_t v = t >= o ? part[t - o] : 0xFFFFFFFFu;
+        __syncthreads();
+        if (v < part[t]) part[t] = v;
+        __syncthreads();
+    }
+    uint32_t run = t ? part[t - 1] : 0xFFFFFFFFu;
+    run = m < run ? m : run;
+    for (int q = 0; q < PER; ++q) {
+        const uint32_t v = start[hi - q];
+        run = v < run ? v : run;
+        start[hi - q] = run;
+    }
+}
+
+// Mid-size bucket (above the LDS capacity): one workgroup runs stable
+// radix-2^8 rounds on key - mn over global memory, as many rounds as the
+// bucket's key range needs, walking its tiles in order with running digit
+// offsets in LDS (the tiles of one bucket never wait on another workgroup).
+// Data ping-pongs between the bucket's place and the same place in a
+// scratch array; values follow their keys by gathering from the tile.
+template <int VB>
+__device__ void bucket_global_lsd(uint64_t* __restrict__ ka, uint64_t* __restrict__ va,
+                                  uint64_t* __restrict__ kb, uint64_t* __restrict__ vb, uint32_t L,
+                                  uint64_t mn, uint64_t mx, uint64_t* sk, uint16_t* sidx, uint16_t* wcnt,
+                                  uint32_t* loc, uint32_t* wsum, uint32_t* tot, uint32_t* run) {
+    constexpr int NW = BS_NT / WAVE;
+    constexpr int R = 256;
+    uint64_t* wmask = sk;
+    const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int rounds = (64 - __clzll((unsigned long long)(mx - mn)) + 7) / 8;
+    const uint64_t mybit = 1ull << lane;
+    const uint32_t wb = wave * (BS_ITEMS * WAVE) + lane;
+    for (int r = 0; r < rounds; ++r) {
+        const int shift = 8 * r;
+        uint64_t* sk_src = (r & 1) ? kb : ka;
+        uint64_t* sv_src = (r & 1) ? vb : va;
+        uint64_t* dk = (r & 1) ? ka : kb;
+        uint64_t* dv = (r & 1) ? va : vb;
+        __syncthreads();
+        if (tid < (uint32_t)R) tot[tid] = 0;
+        __syncthreads();
+        for (uint32_t q = tid; q < L; q += BS_NT) atomicAdd(&tot[((sk_src[q] - mn) >> shift) & 255u], 1u);
+        __syncthreads();
+        {
+            const uint32_t v = tid < (uint32_t)R ? tot[tid] : 0u;
+            uint32_t total;
+            const uint32_t ex = block_excl_scan<BS_NT>(v, wsum, &total);
+            if (tid < (uint32_t)R) run[tid] = ex;
+        }
+        for (uint32_t base = 0; base < L; base += BS_CAP) {
+            const uint32_t nvalid = (L - base) < BS_CAP ? (L - base) : BS_CAP;
+            uint64_t k[BS_ITEMS];
+#pragma unroll
+            for (int i = 0; i < BS_ITEMS; ++i) {
+                const uint32_t j = wb + i * WAVE;
+                k[i] = j < nvalid ? sk_src[base + j] : ~0ull;
+            }
+            __syncthreads();
+            for (int i = tid; i < NW * R; i += BS_NT) {
+                wcnt[i] = 0;
+                wmask[i] = 0;
+            }
+            __syncthreads();
+            uint32_t dr[BS_ITEMS];
+            {
+                uint16_t* wc = wcnt + wave * R;
+                uint64_t* wm = wmask + wave * R;
+#pragma unroll
+                for (int i = 0; i < BS_ITEMS; ++i) {
+                    const uint32_t j = wb + i * WAVE;
+                    const uint32_t d = j >= nvalid ? 255u : (uint32_t)(((k[i] - mn) >> shift) & 255u);
+                    atomicOr((unsigned long long*)&wm[d], (unsigned long long)mybit);
+                    const uint64_t m =
+                        __hip_atomic_load(&wm[d], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    const uint32_t lt = mbcnt(m);
+                    const uint32_t cnt = (uint32_t)__popcll(m);
+                    const uint32_t c = wc[d];
+                    if (lt + 1 == cnt) {
+                        wc[d] = (uint16_t)(c + cnt);
+                        __hip_atomic_store(&wm[d], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    }
+                    dr[i] = d | ((c + lt) << 16);
+                }
+            }
+            __syncthreads();
+            uint32_t t = 0;
+            if (tid < (uint32_t)R) {
+                uint32_t s2 = 0;
+#pragma unroll
+                for (int w = 0; w < NW; ++w) {
+                    const uint32_t c = wcnt[w * R + tid];
+                    wcnt[w * R + tid] = (uint16_t)s2;
+                    s2 += c;
+                }
+                t = s2;
+                tot[tid] = s2;
+            }
+            {
+                uint32_t total;
+                const uint32_t ex = block_excl_scan<BS_NT>(t, wsum, &total);
+                if (tid < (uint32_t)R) loc[tid] = ex;
+            }
+            __syncthreads();
+            uint32_t slot[BS_ITEMS];
+#pragma unroll
+            for (int i = 0; i < BS_ITEMS; ++i) {
+                const uint32_t d = dr[i] & 0xFFFFu;
+                slot[i] = loc[d] + wcnt[wave * R + d] + (dr[i] >> 16);
+            }
+            __syncthreads();  // sk aliases the match slots
+#pragma unroll
+            for (int i = 0; i < BS_ITEMS; ++i) {
+                sk[slot[i]] = k[i];
+                sidx[slot[i]] = (uint16_t)(wb + i * WAVE);
+            }
+            __syncthreads();
+            for (uint32_t j = tid; j < nvalid; j += BS_NT) {
+                const uint64_t key = sk[j];
+                const uint32_t d = (uint32_t)(((key - mn) >> shift) & 255u);
+                const uint32_t o = run[d] - loc[d] + j;
+                if (o < L) {
+                    dk[o] = key;
+                    if constexpr (VB != 0) dv[o] = sv_src[base + sidx[j]];
+                }
+            }
+            __syncthreads();
+            if (tid < (uint32_t)R) run[tid] += tot[tid];
+        }
+    }
+    if (rounds & 1) {
+        // an odd number of rounds ends in the scratch copy
+        __syncthreads();
+        for (uint32_t q = tid; q < L; q += BS_NT) {
+            ka[q] = kb[q];
+            if constexpr (VB != 0) va[q] = vb[q];
+        }
+    }
+}
+
+// Stable sort of one bucket in LDS.  Keys (and values) are in place in
+// (keys, vals) at [start[b], start[b+1]).
+template <int VB>
+__global__ __launch_bounds__(BS_NT) void k_bucket_sort(uint64_t* __restrict__ keys, uint64_t* __restrict__ vals,
+                                                       const uint32_t* __restrict__ start, uint32_t cap,
+                                                       State* __restrict__ st,
+                                                       uint32_t* __restrict__ ovf_list,
+                                                       const uint64_t* __restrict__ spl,
+                                                       uint64_t* __restrict__ scr_k,
+                                                       uint64_t* __restrict__ scr_v) {
+    constexpr int NW = BS_NT / WAVE;
+    constexpr int R = 256;
+    __shared__ __align__(16) uint64_t sk[BS_CAP];   // also the LDS match slots (NW*R)
+    __shared__ uint16_t sidx[BS_CAP];
+    __shared__ uint16_t wcnt[NW * R];
+    __shared__ uint32_t loc[R];
+    __shared__ uint32_t wsum[NW + 1];
+    __shared__ uint64_t rmin[NW], rmax[NW];
+    __shared__ uint32_t tot[R], run[R];
+    uint64_t* wmask = sk;
+    const uint32_t b = blockIdx.x;
+    const uint32_t s0 = start[b], s1 = start[b + 1];
+    if (s1 <= s0 + 1) return;
+    const uint32_t L = s1 - s0;
+    const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    // Bucket b holds the keys in [spl[b-1], spl[b]) (from 0 for b = 0): a
+    // range of one key means one distinct key, already in input order.
+    {
+        const uint64_t lo = b ? spl[b - 1] : 0ull;
+        const uint64_t hi = spl[b];
+        if (b < st->reach && hi > lo && hi - lo == 1) return;
+    }
+    if (L > cap || L > BS_CAP) {
+        if (tid == 0) {
+            atomicAdd(&st->ovf_buckets, 1u);
+            atomicAdd(&st->ovf_keys, (unsigned long long)L);
+        }
+        if (L > MID_CAP) {
+            // too big for one workgroup: the host sorts it with the LSD rounds
+            if (tid == 0) {
+                const uint32_t at = atomicAdd(&st->big_buckets, 1u);
+                atomicAdd(&st->big_keys, (unsigned long long)L);
+                if (at < NB) ovf_list[at] = b;
+            }
+            return;
+        }
+        uint64_t mn = ~0ull, mx = 0;
+        for (uint32_t q = tid; q < L; q += BS_NT) {
+            const uint64_t v = keys[s0 + q];
+            mn = v < mn ? v : mn;
+            mx = v > mx ? v : mx;
+        }
+        for (int o = 32; o >= 1; o >>= 1) {
+            const uint64_t a = __shfl_xor(mn, o, WAVE), c = __shfl_xor(mx, o, WAVE);
+            mn = a < mn ? a : mn;
+            mx = c > mx ? c : mx;
+        }
+        if (lane == 0) {
+            rmin[wave] = mn;
+            rmax[wave] = mx;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            for (int w = 1; w < NW; ++w) {
+                mn = rmin[w] < mn ? rmin[w] : mn;
+                mx = rmax[w] > mx ? rmax[w] : mx;
+            }
+            mn = rmin[0] < mn ? rmin[0] : mn;
+            mx = rmax[0] > mx ? rmax[0] : mx;
+            rmin[0] = mn;
+            rmax[0] = mx;
+        }
+        __syncthreads();
+        mn = rmin[0];
+        mx = rmax[0];
+        if (mn == mx) return;  // one distinct key: already in order
+        bucket_global_lsd<VB>(keys + s0, vals ? vals + s0 : nullptr, scr_k + s0, scr_v ? scr_v + s0 : nullptr,
+                              L, mn, mx, sk, sidx, wcnt, loc, wsum, tot, run);
+        return;
+    }
+    const uint32_t wb = wave * (BS_ITEMS * WAVE) + lane;
+    uint64_t k[BS_ITEMS];
+    uint32_t ix[BS_ITEMS];
+    uint64_t mn = ~0ull, mx = 0;
+#pragma unroll
+    for (int i = 0; i < BS_ITEMS; ++i) {
+        const uint32_t j = wb + i * WAVE;
+        k[i] = j < L ? keys[s0 + j] : ~0ull;
+        ix[i] = j;
+        if (j < L) {
+            mn = k[i] < mn ? k[i] : mn;
+            mx = k[i] > mx ? k[i] : mx;
+        }
+    }
+    for (int o = 32; o >= 1; o >>= 1) {
+        const uint64_t a = __shfl_xor(mn, o, WAVE), c = __shfl_xor(mx, o, WAVE);
+        mn = a < mn ? a : mn;
+        mx = c > mx ? c : mx;
+    }
+    if (lane == 0) {
+        rmin[wave] = mn;
+        rmax[wave] = mx;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+        mn = rmin[w] < mn ? rmin[w] : mn;
+        mx = rmax[w] > mx ? rmax[w] : mx;
+    }
+    if (mn == mx) return;  // one distinct key: already in order
+    // rounds needed for the key range of this bucket
+    const uint64_t span = mx - mn;
+    const int rounds = (64 - __clzll((unsigned long long)span) + 7) / 8;
+    const uint64_t mybit = 1ull << lane;
+    for (int r = 0; r < rounds; ++r) {
+        const int shift = 8 * r;
+        __syncthreads();
+        for (int i = tid; i < NW * R; i += BS_NT) {
+            wcnt[i] = 0;
+            wmask[i] = 0;
+        }
+        __syncthreads();
+        uint32_t dr[BS_ITEMS];
+        uint16_t* wc = wcnt + wave * R;
+        uint64_t* wm = wmask + wave * R;
+#pragma unroll
+        for (int i = 0; i < BS_ITEMS; ++i) {
+            // padding (index >= L) holds the largest key; it sorts last
+            const uint32_t d = k[i] == ~0ull && ix[i] >= L ? 255u
+                                                          : (uint32_t)(((k[i] - mn) >> shift) & 255u);
+            atomicOr((unsigned long long*)&wm[d], (unsigned long long)mybit);
+            const uint64_t m = __hip_atomic_load(&wm[d], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            const uint32_t lt = mbcnt(m);
+            const uint32_t cnt = (uint32_t)__popcll(m);
+            const uint32_t c = wc[d];
+            if (lt + 1 == cnt) {
+                wc[d] = (uint16_t)(c + cnt);
+                __hip_atomic_store(&wm[d], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            }
+            dr[i] = d | ((c + lt) << 16);
+        }
+        __syncthreads();
+        uint32_t tot = 0;
+        if (tid < (uint32_t)R) {
+            uint32_t s = 0;
+#pragma unroll
+            for (int w = 0; w < NW; ++w) {
+                const uint32_t c = wcnt[w * R + tid];
+                wcnt[w * R + tid] = (uint16_t)s;
+                s += c;
+            }
+            tot = s;
+        }
+        uint32_t total;
+        const uint32_t ex = block_excl_scan<BS_NT>(tot, wsum, &total);
+        if (tid < (uint32_t)R) loc[tid] = ex;
+        __syncthreads();
+        uint32_t slot[BS_ITEMS];
+#pragma unroll
+        for (int i = 0; i < BS_ITEMS; ++i) {
+            const uint32_t d = dr[i] & 0xFFFFu;
+            slot[i] = loc[d] + wcnt[wave * R + d] + (dr[i] >> 16);
+        }
+        __syncthreads();  // sk aliases the match slots
+#pragma unroll
+        for (int i = 0; i < BS_ITEMS; ++i) {
+            sk[slot[i]] = k[i];
+            sidx[slot[i]] = (uint16_t)ix[i];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < BS_ITEMS; ++i) {
+            k[i] = sk[wb + i * WAVE];
+            ix[i] = sidx[wb + i * WAVE];
+        }
+    }
+    // keys: the sorted order is in sk; values: gather by original position
+    uint64_t v[VB ? (BS_CAP + BS_NT - 1) / BS_NT : 1];
+    if constexpr (VB != 0) {
+#pragma unroll
+        for (int q = 0; q < (int)((BS_CAP + BS_NT - 1) / BS_NT); ++q) {
+            const uint32_t j = q * BS_NT + tid;
+            if (j < L) v[q] = vals[s0 + sidx[j]];
+        }
+    }
+    __syncthreads();
+    for (uint32_t j = tid; j < L; j += BS_NT) keys[s0 + j] = sk[j];
+    if constexpr (VB != 0) {
+#pragma unroll
+        for (int q = 0; q < (int)((BS_CAP + BS_NT - 1) / BS_NT); ++q) {
+            const uint32_t j = q * BS_NT + tid;
+            if (j < L) vals[s0 + j] = v[q];
+        }
+    }
+}
+
+__global__ void k_check_sorted(const uint64_t* __restrict__ keys, uint64_t n, State* __restrict__ st) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    bool bad = false;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x + 1; i < n; i += stride)
+        bad |= keys[i - 1] > keys[i];
+    if (ballot(bad) && (threadIdx.x & 63) == 0) atomicOr(&st->unsorted, 1u);
+}
+
+__global__ void k_mlp_forward(const float* __restrict__ params, const float* __restrict__ x,
+                              float* __restrict__ y, uint64_t m) {
+    __shared__ Mlp W;
+    __shared__ float raw[NP];
+    for (int p = threadIdx.x; p < NP; p += blockDim.x) raw[p] = params[p];
+    __syncthreads();
+    mlp_derive(raw, W, false);
+    __syncthreads();
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < m) y[i] = mlp_y(W, x[i]);
+}
+
+}  // namespace
+
+// ---- host side --------------------------------------------------------------------
+
+namespace {
+
+LearnOpts g_opts = {32, 1e-2f, 1, (int32_t)BS_CAP, -1, 0.25, 64, 64};
+
+struct LearnLayout {
+    size_t off_state, off_sample, off_sorted, off_sample_ws, off_xs, off_ts, off_params, off_gbuf,
+        off_spl, off_knot, off_start, off_ovf, off_bid0, off_big, total;
+    LsdPlan sample_plan, pass_plan, fb_plan;
+};
+
+bool learn_layout(size_t n, int vb, LearnLayout* L) {
+    LearnLayout q;
+    if (!lsd_plan(M, 8, 0, 8, &q.sample_plan)) return false;
+    if (!lsd_plan(n, 2, 8, 8, &q.pass_plan, vb)) return false;
+    if (!lsd_plan(n, 8, vb, 8, &q.fb_plan)) return false;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off += align_up(bytes ? bytes : 1);
+        return o;
+    };
+    q.off_state = take(sizeof(State));
+    q.off_sample = take(8 * (size_t)M);
+    q.off_sorted = take(8 * (size_t)M);
+    q.off_sample_ws = take(q.sample_plan.total);
+    q.off_xs = take(4 * (size_t)M);
+    q.off_ts = take(4 * (size_t)M);
+    q.off_params = take(4 * (size_t)NP);
+    q.off_gbuf = take(4 * (size_t)GBUF * 3);
+    q.off_spl = take(8 * (size_t)NB);
+    q.off_knot = take(4 * (size_t)(KNOTS + 1));
+    q.off_start = take(4 * ((size_t)NB + 1));
+    q.off_ovf = take(4 * (size_t)NB);
+    q.off_bid0 = take(2 * n);
+    // the rounds' workspace and the final bucket ids, or the fallback's
+    // workspace (never live at the same time)
+    const size_t learned_big = align_up(q.pass_plan.total) + align_up(2 * n);
+    q.off_big = take(learned_big > q.fb_plan.total ? learned_big : q.fb_plan.total);
+    q.total = off;
+    *L = q;
+    return true;
+}
+
+int g_coop_grid = 0;
+
+}  // namespace
+
+LearnOpts& learn_opts() { return g_opts; }
+
+size_t learned_ws_bytes(size_t n, int vb) {
+    LearnLayout L;
+    if (!learn_layout(n, vb, &L)) return 0;
+    return L.total;
+}
+
+static rs_status launch_train(const float* xs, const float* ts, float* params, float* gbuf, State* st,
+                              const TrainCfg& cfg, int init, int grid, hipStream_t s) {
+    void* args[] = {(void*)&xs, (void*)&ts, (void*)&params, (void*)&gbuf, (void*)&st, (void*)&cfg,
+                    (void*)&init};
+    hipError_t e = hipLaunchCooperativeKernel((const void*)k_train, dim3(grid), dim3(TR_NT), args, 0, s);
+    return e == hipSuccess ? RS_OK : hip_fail(e);
+}
+
+rs_status learned_run(const void* kin, void* kout, const void* vin, void* vout, size_t n, int vb,
+                      void* ws_, size_t ws_bytes, hipStream_t s, LearnReport* rep) {
+    memset(rep, 0, sizeof(*rep));
+    LearnLayout L;
+    if (!learn_layout(n, vb, &L)) return RS_ERR_UNSUPPORTED;
+    if (!ws_ || ws_bytes < L.total || (reinterpret_cast<uintptr_t>(ws_) % ALIGN)) return RS_ERR_WORKSPACE;
+    unsigned char* ws = static_cast<unsigned char*>(ws_);
+    State* st = reinterpret_cast<State*>(ws + L.off_state);
+    uint64_t* sample = reinterpret_cast<uint64_t*>(ws + L.off_sample);
+    uint64_t* sorted = reinterpret_cast<uint64_t*>(ws + L.off_sorted);
+    float* xs = reinterpret_cast<float*>(ws + L.off_xs);
+    float* ts = reinterpret_cast<float*>(ws + L.off_ts);
+    float* params = reinterpret_cast<float*>(ws + L.off_params);
+    float* gbuf = reinterpret_cast<float*>(ws + L.off_gbuf);
+    uint64_t* spl = reinterpret_cast<uint64_t*>(ws + L.off_spl);
+    float* knot = reinterpret_cast<float*>(ws + L.off_knot);
+    uint32_t* start = reinterpret_cast<uint32_t*>(ws + L.off_start);
+    uint32_t* ovf = reinterpret_cast<uint32_t*>(ws + L.off_ovf);
+    uint16_t* bid0 = reinterpret_cast<uint16_t*>(ws + L.off_bid0);
+    unsigned char* big = ws + L.off_big;
+    uint16_t* bid1 = reinterpret_cast<uint16_t*>(big + align_up(L.pass_plan.total));
+    const LearnOpts opt = g_opts;
+    rs_status rc;
+    hipError_t e;
+
+    // 1. sample and targets
+    if ((rc = fill_u32(st, sizeof(State) / 4, 0u, s)) != RS_OK) return rc;
+    if ((rc = fill_u32(gbuf, GBUF * 3, 0u, s)) != RS_OK) return rc;
+    prof(s, KID_LEARN_SAMPLE, 0);
+    hipLaunchKernelGGL(k_sample, dim3(M / 256), dim3(256), 0, s, (const uint64_t*)kin, (uint64_t)n,
+                       (uint64_t)0x1A7E5EEDull, sample);
+    prof(s, KID_LEARN_SAMPLE, 1);
+    if ((rc = launch_status()) != RS_OK) return rc;
+    if ((rc = lsd_run(L.sample_plan, sample, sorted, nullptr, nullptr, ws + L.off_sample_ws, s)) != RS_OK)
+        return rc;
+    prof(s, KID_LEARN_SAMPLE, 0);
+    hipLaunchKernelGGL(k_setup, dim3(1), dim3(64), 0, s, sorted, st, opt.feature_mode);
+    hipLaunchKernelGGL(k_targets, dim3(M / 256), dim3(256), 0, s, sorted, st, xs, ts);
+    prof(s, KID_LEARN_SAMPLE, 1);
+    if ((rc = launch_status()) != RS_OK) return rc;
+
+    // 2. training (one cooperative launch)
+    if (g_coop_grid == 0) {
+        int dev = 0, cus = 0, per = 0;
+        if ((e = hipGetDevice(&dev)) != hipSuccess) return hip_fail(e);
+        if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)
+            return hip_fail(e);
+        if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_train, TR_NT, 0)) != hipSuccess)
+            return hip_fail(e);
+        const int cap = cus * (per > 0 ? per : 1);
+        g_coop_grid = opt.train_blocks < cap ? opt.train_blocks : cap;
+        if (g_coop_grid < 1) g_coop_grid = 1;
+    }
+    if (opt.use_network) {
+        TrainCfg cfg{opt.train_steps, opt.lr, 0.9f, 0.999f, 1e-8f, M, 0};
+        prof(s, KID_LEARN_TRAIN, 0);
+        rc = launch_train(xs, ts, params, gbuf, st, cfg, 1, g_coop_grid, s);
+        prof(s, KID_LEARN_TRAIN, 1);
+        if (rc != RS_OK) return rc;
+    }
+
+    // 3. calibration knots, splitters
+    prof(s, KID_LEARN_SPLIT, 0);
+    hipLaunchKernelGGL(k_calibrate, dim3(1), dim3(256), 0, s, params, xs, knot, opt.use_network);
+    hipLaunchKernelGGL(k_splitters, dim3(NB / 256), dim3(256), 0, s, params, st, knot, spl, opt.use_network);
+    hipLaunchKernelGGL(k_split_fix, dim3(1), dim3(1024), 0, s, spl);
+    prof(s, KID_LEARN_SPLIT, 1);
+    if ((rc = launch_status()) != RS_OK) return rc;
+
+    // 4. bucket ids
+    {
+        uint64_t g = (n + AS_NT * AS_KEYS - 1) / (AS_NT * AS_KEYS);
+        if (g > 8192) g = 8192;
+        prof(s, KID_LEARN_ASSIGN, 0);
+        hipLaunchKernelGGL(k_assign, dim3((unsigned)g), dim3(AS_NT), 0, s, (const uint64_t*)kin, (uint64_t)n,
+                           spl, st, bid0);
+        prof(s, KID_LEARN_ASSIGN, 1);
+        if ((rc = launch_status()) != RS_OK) return rc;
+    }
+    // 5. two stable rounds on the bucket id carry keys and values
+    if ((rc = lsd_run(L.pass_plan, bid0, bid1, kin, kout, big, s, vb ? vin : nullptr, vb ? vout : nullptr)) !=
+        RS_OK)
+        return rc;
+    // 6. bucket bounds, per-bucket sort
+    if ((rc = fill_u32(start, NB + 1, (uint32_t)n, s)) != RS_OK) return rc;
+    {
+        uint64_t g = (n + 255) / 256;
+        if (g > 8192) g = 8192;
+        prof(s, KID_LEARN_BUCKET, 0);
+        hipLaunchKernelGGL(k_bucket_first, dim3((unsigned)g), dim3(256), 0, s, bid1, (uint64_t)n, start);
+        hipLaunchKernelGGL(k_bucket_fix, dim3(1), dim3(1024), 0, s, start);
+        const uint32_t cap = (uint32_t)(opt.bucket_cap > 0 && opt.bucket_cap < (int)BS_CAP ? opt.bucket_cap : BS_CAP);
+        // scratch for mid-size buckets: the rounds' temporary key and value
+        // arrays, free again once the bucket ids have been sorted
+        uint64_t* scr_k = reinterpret_cast<uint64_t*>(big + L.pass_plan.off_tv);
+        uint64_t* scr_v = vb ? reinterpret_cast<uint64_t*>(big + L.pass_plan.off_tv2) : nullptr;
+        if (vb)
+            hipLaunchKernelGGL(k_bucket_sort<8>, dim3(NB), dim3(BS_NT), 0, s, (uint64_t*)kout, (uint64_t*)vout,
+                               start, cap, st, ovf, spl, scr_k, scr_v);
+        else
+            hipLaunchKernelGGL(k_bucket_sort<0>, dim3(NB), dim3(BS_NT), 0, s, (uint64_t*)kout, (uint64_t*)nullptr,
+                               start, cap, st, ovf, spl, scr_k, scr_v);
+        prof(s, KID_LEARN_BUCKET, 1);
+        if ((rc = launch_status()) != RS_OK) return rc;
+    }
+    State hs;
+    if ((e = hipMemcpyAsync(&hs, st, sizeof(State), hipMemcpyDeviceToHost, s)) != hipSuccess) return hip_fail(e);
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e);
+    rep->train_loss = hs.loss;
+    rep->buckets_overflowed = hs.ovf_buckets;
+    rep->keys_overflowed = (int64_t)hs.ovf_keys;
+    rep->device_error = hs.err;
+    rep->feature_mode = hs.mode;
+
+    // too many keys, or too many separate buckets, beyond what one workgroup
+    // sorts: the whole array goes through the LSD rounds instead
+    bool whole = (double)hs.big_keys > opt.fallback_frac * (double)n ||
+                 (int64_t)hs.big_buckets > (int64_t)opt.max_fallback_buckets;
+    // 7. overflowed buckets by the LSD rounds, in place
+    if (!whole && hs.big_buckets > 0) {
+        const uint32_t nb = hs.big_buckets < NB ? hs.big_buckets : NB;
+        std::vector<uint32_t> list(nb), st_h(NB + 1);
+        if ((e = hipMemcpy(list.data(), ovf, 4 * (size_t)nb, hipMemcpyDeviceToHost)) != hipSuccess)
+            return hip_fail(e);
+        if ((e = hipMemcpy(st_h.data(), start, 4 * ((size_t)NB + 1), hipMemcpyDeviceToHost)) != hipSuccess)
+            return hip_fail(e);
+        for (uint32_t b : list) {
+            const size_t a = st_h[b], z = st_h[b + 1];
+            LsdPlan bp;
+            if (!lsd_plan(z - a, 8, vb, 8, &bp)) return RS_ERR_UNSUPPORTED;
+            uint64_t* kp = static_cast<uint64_t*>(kout) + a;
+            uint64_t* vp = vb ? static_cast<uint64_t*>(vout) + a : nullptr;
+            if ((rc = lsd_run(bp, kp, kp, vp, vp, big, s)) != RS_OK) return rc;
+        }
+    }
+    if (!whole) {
+        prof(s, KID_LEARN_CHECK, 0);
+        hipLaunchKernelGGL(k_check_sorted, dim3(4096), dim3(256), 0, s, (const uint64_t*)kout, (uint64_t)n, st);
+        prof(s, KID_LEARN_CHECK, 1);
+        if ((rc = launch_status()) != RS_OK) return rc;
+        uint32_t unsorted = 0;
+        if ((e = hipMemcpyAsync(&unsorted, &st->unsorted, 4, hipMemcpyDeviceToHost, s)) != hipSuccess)
+            return hip_fail(e);
+        if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e);
+        rep->unsorted = unsorted;
+        whole = unsorted != 0;
+    }
+    if (whole) {
+        rep->fallback = 1;
+        return lsd_run(L.fb_plan, kin, kout, vb ? vin : nullptr, vb ? vout : nullptr, big, s);
+    }
+    return RS_OK;
+}
+
+// ---- test entry points ---------------------------------------------------------------
+
+rs_status mlp_forward(const float* params, const float* x, float* y, size_t m, hipStream_t s) {
+    if (!m) return RS_OK;
+    hipLaunchKernelGGL(k_mlp_forward, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, params, x, y,
+                       (uint64_t)m);
+    return launch_status();
+}
+
+rs_status mlp_loss_grad(const float* params, const float* x, const float* t, size_t m, float* grad,
+                        hipStream_t s) {
+    if (!m || m > 0x7FFFFFFFu) return RS_ERR_INVALID;
+    rs_status rc = fill_u32(grad, GBUF, 0u, s);
+    if (rc != RS_OK) return rc;
+    TrainCfg cfg{1, 0.f, 0.9f, 0.999f, 1e-8f, (uint32_t)m, 1};
+    const int init = 0;
+    State* st = nullptr;
+    hipLaunchKernelGGL(k_train, dim3(64), dim3(TR_NT), 0, s, x, t, const_cast<float*>(params), grad, st, cfg, init);
+    return launch_status();
+}
+
+}  // namespace rs

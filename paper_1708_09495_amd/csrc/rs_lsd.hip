@@ -48,6 +48,8 @@ template <> struct LBW<uint64_t> {
 
 // keys per thread of a onesweep tile
 constexpr int lsd_items(int kb, int vb) { return kb == 4 ? (vb == 0 ? 24 : 16) : 8; }
+// 16-bit digit keys carry up to two 8-byte payloads (the learned path moves
+// bucket ids with their keys and values)
 
 template <int VB> struct ValT { using type = uint32_t; };
 template <> struct ValT<8> { using type = uint64_t; };
@@ -72,16 +74,33 @@ __global__ __launch_bounds__(HIST_NT) void k_hist(const K* __restrict__ keys, ui
     __syncthreads();
     const uint64_t stride = (uint64_t)gridDim.x * HIST_NT;
     uint64_t i = (uint64_t)blockIdx.x * HIST_NT + threadIdx.x;
-    // four independent loads in flight per thread
-    for (; i + 3 * stride < n; i += 4 * stride) {
+    // Counting: when every lane of the wave holds the same digit (a common
+    // case for the high digits of skewed keys) one lane adds 64 instead of
+    // 64 lanes colliding on one counter.
+    auto count = [&](uint32_t slot) {
+        const uint32_t first = __builtin_amdgcn_readfirstlane(slot);
+        if (ballot(slot != first) == 0) {
+            if ((threadIdx.x & 63) == 0) atomicAdd(&h[first], 64u);
+        } else {
+            atomicAdd(&h[slot], 1u);
+        }
+    };
+    // four independent loads in flight per thread; whole waves only, so the
+    // uniform-digit test sees 64 keys
+    const uint64_t nfull = n - n % ((uint64_t)HIST_NT * gridDim.x);
+    for (; i + 3 * stride < nfull; i += 4 * stride) {
         K k0 = keys[i], k1 = keys[i + stride], k2 = keys[i + 2 * stride], k3 = keys[i + 3 * stride];
         for (int p = 0; p < passes; ++p) {
             const int s = p * bits;
-            atomicAdd(&h[p * R + ((uint32_t)(k0 >> s) & mask)], 1u);
-            atomicAdd(&h[p * R + ((uint32_t)(k1 >> s) & mask)], 1u);
-            atomicAdd(&h[p * R + ((uint32_t)(k2 >> s) & mask)], 1u);
-            atomicAdd(&h[p * R + ((uint32_t)(k3 >> s) & mask)], 1u);
+            count(p * R + ((uint32_t)(k0 >> s) & mask));
+            count(p * R + ((uint32_t)(k1 >> s) & mask));
+            count(p * R + ((uint32_t)(k2 >> s) & mask));
+            count(p * R + ((uint32_t)(k3 >> s) & mask));
         }
+    }
+    for (; i < nfull; i += stride) {
+        K k0 = keys[i];
+        for (int p = 0; p < passes; ++p) count(p * R + ((uint32_t)(k0 >> (p * bits)) & mask));
     }
     for (; i < n; i += stride) {
         K k0 = keys[i];
@@ -98,6 +117,7 @@ __global__ __launch_bounds__(HIST_NT) void k_hist(const K* __restrict__ keys, ui
 // One stable count-sort round over tiles of NT*ITEMS keys.
 //   MAXB  : largest radix bits the LDS arrays are sized for (bits <= MAXB)
 //   VB    : value bytes (0 = keys only)
+//   VB2   : bytes of a second payload array (0 = none)
 //   LB    : look-back word type (32-bit while n < 2^30)
 //   OFF   : int32_t destinations while n < 2^31, else int64_t
 //
@@ -111,18 +131,19 @@ __global__ __launch_bounds__(HIST_NT) void k_hist(const K* __restrict__ keys, ui
 // wave is the wave's running count for the digit plus the number of peer
 // lanes below it; the highest peer lane advances the running count and
 // clears the slot.
-template <typename K, int VB, int MAXB, int ITEMS, typename LB, typename OFF>
+template <typename K, int VB, int MAXB, int ITEMS, typename LB, typename OFF, int VB2 = 0>
 __global__ __launch_bounds__(NT) void k_onesweep(
     const K* __restrict__ kin, K* __restrict__ kout, const void* __restrict__ vin_,
     void* __restrict__ vout_, uint64_t n, int shift, int bits, uint32_t* __restrict__ tile_ctr,
-    LB* __restrict__ lb, const uint32_t* __restrict__ ghist, uint32_t* __restrict__ status) {
+    LB* __restrict__ lb, const uint32_t* __restrict__ ghist, uint32_t* __restrict__ status,
+    const void* __restrict__ vin2_ = nullptr, void* __restrict__ vout2_ = nullptr) {
     using V = typename ValT<VB>::type;
     constexpr int RMAX = 1 << MAXB;
     constexpr int RLO = RMAX < 256 ? RMAX : 256;      // slots of the LDS match
     constexpr int T = NT * ITEMS;
     constexpr int PER = (RMAX + NT - 1) / NT;  // digits per thread in the digit scans
     constexpr size_t KEYB = (size_t)T * sizeof(K);
-    constexpr size_t VALB = VB ? (size_t)T * sizeof(V) : 0;
+    constexpr size_t VALB = (size_t)T * (VB > VB2 ? VB : VB2);
     constexpr size_t CNTB = (size_t)NW * RMAX * sizeof(uint16_t);
     constexpr size_t MSKB = (size_t)NW * RLO * sizeof(uint64_t);
     constexpr size_t RANKB = CNTB + MSKB;
@@ -332,7 +353,7 @@ __global__ __launch_bounds__(NT) void k_onesweep(
     //      check keeps a wrong prefix (or an abandoned look-back) from writing
     //      outside the array and reports it instead.
     using UOFF = typename std::make_unsigned<OFF>::type;
-    OFF dst[VB ? ITEMS : 1];
+    OFF dst[(VB || VB2) ? ITEMS : 1];
 #pragma unroll
     for (int q = 0; q < ITEMS; ++q) {
         const uint32_t j = q * NT + tid;
@@ -346,7 +367,7 @@ __global__ __launch_bounds__(NT) void k_onesweep(
             } else {
                 kout[(UOFF)o] = key;
             }
-            if constexpr (VB != 0) dst[q] = o;
+            if constexpr (VB != 0 || VB2 != 0) dst[q] = o;
         }
     }
     if constexpr (VB != 0) {
@@ -360,19 +381,42 @@ __global__ __launch_bounds__(NT) void k_onesweep(
             if ((full || j < nvalid) && dst[q] >= 0) vout[(UOFF)dst[q]] = svals[j];
         }
     }
+    if constexpr (VB2 != 0) {
+        // the second payload follows the same slots and destinations
+        using V2 = typename ValT<VB2>::type;
+        const V2* __restrict__ v2in = reinterpret_cast<const V2*>(vin2_) + base;
+        V2* __restrict__ v2out = reinterpret_cast<V2*>(vout2_);
+        V2* sv2 = reinterpret_cast<V2*>(u_raw);
+        V2 w[ITEMS];
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+            const uint32_t j = wb + i * WAVE;
+            w[i] = (full || j < nvalid) ? v2in[j] : V2(0);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) sv2[dr[i]] = w[i];
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < ITEMS; ++q) {
+            const uint32_t j = q * NT + tid;
+            if ((full || j < nvalid) && dst[q] >= 0) v2out[(UOFF)dst[q]] = sv2[j];
+        }
+    }
 }
 
-template <typename K, int VB, int MAXB, int ITEMS, typename LB, typename OFF>
+template <typename K, int VB, int MAXB, int ITEMS, typename LB, typename OFF, int VB2 = 0>
 hipError_t launch_pass(const LsdPlan& p, const void* src, void* dst, const void* vsrc, void* vdst,
-                       int pass, unsigned char* ws, hipStream_t st) {
+                       int pass, unsigned char* ws, hipStream_t st, const void* v2src = nullptr,
+                       void* v2dst = nullptr) {
     uint32_t* ctr = reinterpret_cast<uint32_t*>(ws + p.off_ctr) + pass;
     LB* lb = reinterpret_cast<LB*>(ws + p.off_lb) + (size_t)pass * p.lb_words;
     const uint32_t* gh = reinterpret_cast<const uint32_t*>(ws + p.off_hist) + (size_t)pass * p.R;
     uint32_t* status = reinterpret_cast<uint32_t*>(ws + p.off_status);
     prof(st, KID_ONESWEEP, 0);
-    hipLaunchKernelGGL((k_onesweep<K, VB, MAXB, ITEMS, LB, OFF>), dim3((unsigned)p.tiles), dim3(NT), 0, st,
-                       (const K*)src, (K*)dst, vsrc, vdst, (uint64_t)p.n, pass * p.bits, p.bits, ctr,
-                       lb, gh, status);
+    hipLaunchKernelGGL((k_onesweep<K, VB, MAXB, ITEMS, LB, OFF, VB2>), dim3((unsigned)p.tiles), dim3(NT),
+                       0, st, (const K*)src, (K*)dst, vsrc, vdst, (uint64_t)p.n, pass * p.bits, p.bits,
+                       ctr, lb, gh, status, v2src, v2dst);
     prof(st, KID_ONESWEEP, 1);
     return hipGetLastError();
 }
@@ -395,8 +439,24 @@ hipError_t launch_pass_k(const LsdPlan& p, const void* src, void* dst, const voi
     return launch_pass_lb<K, VB, 11, ITEMS>(p, src, dst, vsrc, vdst, pass, ws, st);
 }
 
+// 16-bit digit keys with an 8-byte payload and an optional second one
+template <int VB2>
+hipError_t launch_pass_k16(const LsdPlan& p, const void* src, void* dst, const void* vsrc,
+                           void* vdst, int pass, unsigned char* ws, hipStream_t st,
+                           const void* v2src, void* v2dst) {
+    if (p.lb64)
+        return launch_pass<uint16_t, 8, 8, 8, uint64_t, int64_t, VB2>(p, src, dst, vsrc, vdst, pass, ws,
+                                                                        st, v2src, v2dst);
+    return launch_pass<uint16_t, 8, 8, 8, uint32_t, int32_t, VB2>(p, src, dst, vsrc, vdst, pass, ws, st,
+                                                                    v2src, v2dst);
+}
+
 hipError_t launch_pass_any(const LsdPlan& p, const void* src, void* dst, const void* vsrc,
-                           void* vdst, int pass, unsigned char* ws, hipStream_t st) {
+                           void* vdst, int pass, unsigned char* ws, hipStream_t st,
+                           const void* v2src = nullptr, void* v2dst = nullptr) {
+    if (p.kb == 2)
+        return p.vb2 ? launch_pass_k16<8>(p, src, dst, vsrc, vdst, pass, ws, st, v2src, v2dst)
+                     : launch_pass_k16<0>(p, src, dst, vsrc, vdst, pass, ws, st, v2src, v2dst);
     if (p.kb == 4) {
         if (p.vb == 0) return launch_pass_k<uint32_t, 0>(p, src, dst, vsrc, vdst, pass, ws, st);
         if (p.vb == 4) return launch_pass_k<uint32_t, 4>(p, src, dst, vsrc, vdst, pass, ws, st);
@@ -419,8 +479,12 @@ rs_status fill_u32(void* p, size_t words, uint32_t v, hipStream_t st) {
     return launch_status();
 }
 
-bool lsd_plan(size_t n, int kb, int vb, int bits, LsdPlan* p) {
-    if ((kb != 4 && kb != 8) || (vb != 0 && vb != 4 && vb != 8) || bits < 1 || bits > 11) return false;
+bool lsd_plan(size_t n, int kb, int vb, int bits, LsdPlan* p, int vb2) {
+    if ((kb != 4 && kb != 8) || (vb != 0 && vb != 4 && vb != 8) || bits < 1 || bits > 11) {
+        // the only other shape: 16-bit digit keys, radix 2^8, 8-byte payload(s)
+        if (!(kb == 2 && vb == 8 && (vb2 == 0 || vb2 == 8) && bits == 8)) return false;
+    }
+    if (kb != 2 && vb2 != 0) return false;
     LsdPlan q;
     q.n = n;
     q.kb = kb;
@@ -428,7 +492,8 @@ bool lsd_plan(size_t n, int kb, int vb, int bits, LsdPlan* p) {
     q.bits = bits;
     q.passes = (8 * kb + bits - 1) / bits;
     q.R = 1 << bits;
-    q.tile = NT * lsd_items(kb, vb);
+    q.vb2 = vb2;
+    q.tile = NT * (kb == 2 ? 8 : lsd_items(kb, vb));
     q.tiles = n ? (n + q.tile - 1) / q.tile : 0;
     q.lb64 = n >= (1ull << 30);
     q.lb_words = q.tiles * (size_t)q.R;
@@ -446,13 +511,15 @@ bool lsd_plan(size_t n, int kb, int vb, int bits, LsdPlan* p) {
     off += align_up((size_t)kb * n);
     q.off_tv = off;
     off += align_up((size_t)vb * n);
+    q.off_tv2 = off;
+    off += align_up((size_t)vb2 * n);
     q.total = off;
     *p = q;
     return true;
 }
 
 rs_status lsd_run(const LsdPlan& p, const void* kin, void* kout, const void* vin, void* vout,
-                  void* ws_, hipStream_t st) {
+                  void* ws_, hipStream_t st, const void* vin2, void* vout2) {
     if (p.n == 0) return RS_OK;
     unsigned char* ws = static_cast<unsigned char*>(ws_);
     rs_status rc = fill_u32(ws + p.off_status, p.zero_bytes / 4, 0u, st);
@@ -469,7 +536,11 @@ rs_status lsd_run(const LsdPlan& p, const void* kin, void* kout, const void* vin
         uint32_t* gh = reinterpret_cast<uint32_t*>(ws + p.off_hist);
         uint32_t* zp = reinterpret_cast<uint32_t*>(ws + p.off_lb);
         prof(st, KID_HIST, 0);
-        if (p.kb == 4)
+        if (p.kb == 2)
+            hipLaunchKernelGGL(k_hist<uint16_t>, dim3((unsigned)g), dim3(HIST_NT), shm, st,
+                               (const uint16_t*)kin, (uint64_t)p.n, p.bits, p.passes, gh, zp,
+                               (uint64_t)lb_u32);
+        else if (p.kb == 4)
             hipLaunchKernelGGL(k_hist<uint32_t>, dim3((unsigned)g), dim3(HIST_NT), shm, st,
                                (const uint32_t*)kin, (uint64_t)p.n, p.bits, p.passes, gh, zp,
                                (uint64_t)lb_u32);
@@ -486,27 +557,33 @@ rs_status lsd_run(const LsdPlan& p, const void* kin, void* kout, const void* vin
     // the rounds end in the workspace and one copy follows.
     void* tk = ws + p.off_tk;
     void* tv = ws + p.off_tv;
+    void* tv2 = ws + p.off_tv2;
     const int P = p.passes;
     const bool inplace = kin == kout;
     const bool copy_back = inplace && (P % 2 == 1);
     const void* src = kin;
     const void* vsrc = vin;
+    const void* v2src = vin2;
     for (int j = 0; j < P; ++j) {
         const int left = P - 1 - j;  // rounds after this one
         bool to_out = (left % 2 == 0);
         if (copy_back) to_out = !to_out;
         void* dst = to_out ? kout : tk;
         void* vdst = to_out ? vout : tv;
-        hipError_t e = launch_pass_any(p, src, dst, vsrc, vdst, j, ws, st);
+        void* v2dst = to_out ? vout2 : tv2;
+        hipError_t e = launch_pass_any(p, src, dst, vsrc, vdst, j, ws, st, v2src, v2dst);
         if (e != hipSuccess) return hip_fail(e);
         src = dst;
         vsrc = vdst;
+        v2src = v2dst;
     }
     if (copy_back) {
         prof(st, KID_COPY, 0);
         hipError_t e = hipMemcpyAsync(kout, tk, p.n * p.kb, hipMemcpyDeviceToDevice, st);
         if (e == hipSuccess && p.vb)
             e = hipMemcpyAsync(vout, tv, p.n * p.vb, hipMemcpyDeviceToDevice, st);
+        if (e == hipSuccess && p.vb2)
+            e = hipMemcpyAsync(vout2, tv2, p.n * p.vb2, hipMemcpyDeviceToDevice, st);
         if (e != hipSuccess) return hip_fail(e);
         prof(st, KID_COPY, 1);
     }

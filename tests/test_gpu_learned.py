@@ -1,0 +1,173 @@
+"""GPU tests of the learned-CDF bucket path (an extension; not in the
+paper): the network's forward pass and gradient against the fp64 oracle, and
+the sort itself bit for bit against the oracle's stable LSD sort, including
+the fallback paths forced from the host."""
+import numpy as np
+import pytest
+
+from gpu_util import first_mismatch, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+H = 32
+I_V1, I_B1, I_V2, I_B2, I_V3, I_B3 = 0, H, 2 * H, 2 * H + H * H, 3 * H + H * H, 4 * H + H * H
+
+
+@pytest.fixture(scope="module")
+def rs():
+    import paper_1708_09495_amd as rs
+    rs.lib()
+    return rs
+
+
+def _params(seed):
+    rng = np.random.default_rng(seed)
+    q = rng.normal(0.0, 0.5, 1153)
+    for lo, hi in ((I_V1, I_B1), (I_V2, I_B2), (I_V3, I_B3)):
+        q[lo:hi] -= 2.0
+    return q
+
+
+def _f32(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def test_forward_matches_fp64_oracle(rs, orc):
+    for seed in (1, 2, 3):
+        q = _params(seed)
+        x = np.linspace(0, 1, 4097)
+        y = rs.rs_mlp_forward(_f32(q), _f32(x)).cpu().numpy().astype(np.float64)
+        ref = np.array([orc.mlp_forward_f64(q.astype(np.float32).astype(np.float64), xi)
+                        for xi in x.astype(np.float32)])
+        assert np.max(np.abs(y - ref) / np.maximum(np.abs(ref), 1e-3)) < 1e-4
+        assert np.all(np.diff(y) >= -1e-7)          # monotone up to float rounding
+
+
+def test_gradient_matches_fp64_oracle(rs, orc):
+    rng = np.random.default_rng(4)
+    for seed, m in ((5, 1000), (6, 4096), (7, 777)):
+        q = _params(seed).astype(np.float32).astype(np.float64)
+        xs = rng.random(m).astype(np.float32).astype(np.float64)
+        ts = rng.random(m).astype(np.float32).astype(np.float64)
+        g = rs.rs_mlp_loss_grad(_f32(q), _f32(xs), _f32(ts)).cpu().numpy().astype(np.float64)
+        loss_ref, g_ref = orc.mlp_loss_grad_f64(q, xs, ts)
+        rel = np.linalg.norm(g[:1153] - g_ref) / np.linalg.norm(g_ref)
+        assert rel < 1e-4, rel
+        assert abs(g[1153] / m - loss_ref) / loss_ref < 1e-5
+
+
+def _dist(name, n, seed):
+    import gen
+    return {"zipf": lambda: gen.zipf_u64(seed, n),
+            "lognormal": lambda: gen.lognormal_u64(seed, n),
+            "mixture": lambda: gen.gauss_mix_u64(seed, n),
+            "uniform": lambda: gen.uniform_u64(seed, n)}[name]()
+
+
+def _learned(rs, keys, vals=None):
+    kt = to_dev(keys)
+    if vals is None:
+        out = rs.rs_sort_u64(kt, algo=rs.RS_ALGO_LEARNED)
+        return to_host(out, np.uint64), None, rs.rs_get_stats()
+    ko, vo = rs.rs_sort_kv(kt, to_dev(vals), algo=rs.RS_ALGO_LEARNED)
+    return to_host(ko, np.uint64), to_host(vo, np.uint64), rs.rs_get_stats()
+
+
+@pytest.mark.parametrize("dist", ["zipf", "lognormal", "mixture", "uniform"])
+def test_learned_kv_parity(rs, orc, dist):
+    import gen
+    for n in (1 << 20, (1 << 22) + 977):
+        print("case learned kv %s n=%d" % (dist, n), flush=True)
+        keys = _dist(dist, n, gen.S0 + 5)
+        vals = np.arange(n, dtype=np.uint64)
+        ko, vo, st = _learned(rs, keys, vals)
+        rk, rv = orc.lsd(keys, 8, vals=vals)
+        assert first_mismatch(ko, rk) is None
+        assert first_mismatch(vo, rv) is None
+        assert st.algo == rs.RS_ALGO_LEARNED and st.device_error == 0
+        print("  loss %.3g overflowed buckets %d keys %d fallback %d" %
+              (st.train_loss, st.buckets_overflowed, st.keys_overflowed, st.fallback))
+
+
+def test_learned_keys_only(rs, orc):
+    import gen
+    keys = gen.lognormal_u64(gen.S0 + 6, 1 << 20)
+    ko, _, st = _learned(rs, keys)
+    assert first_mismatch(ko, orc.lsd(keys, 8)) is None
+
+
+@pytest.mark.parametrize("opts", [dict(bucket_cap=2), dict(bucket_cap=16),
+                                  dict(use_network=0), dict(feature_mode=0), dict(feature_mode=1),
+                                  dict(train_steps=0)])
+def test_learned_forced_paths_stay_exact(rs, orc, opts):
+    import gen
+    old = rs.rs_learned_set_opts(**opts)
+    try:
+        keys = gen.gauss_mix_u64(gen.S0 + 7, 300_001)
+        vals = np.arange(keys.size, dtype=np.uint64)
+        ko, vo, st = _learned(rs, keys, vals)
+        rk, rv = orc.lsd(keys, 8, vals=vals)
+        assert first_mismatch(ko, rk) is None and first_mismatch(vo, rv) is None
+        if "bucket_cap" in opts:
+            # buckets over the capacity go through the one-workgroup rounds
+            assert st.buckets_overflowed > 0 and st.fallback == 0
+    finally:
+        rs.rs_learned_set_opts(**old)
+
+
+@pytest.mark.parametrize("whole", [False, True])
+def test_learned_giant_bucket_fallbacks(rs, orc, whole):
+    """2.5M distinct keys within 2^40 of 2^63 next to 300K small keys,
+    bucketed by a linear feature without the network: the dense cluster is
+    one float value of the feature, hence one bucket, far more keys than one
+    workgroup sorts.  It is sorted by the device-wide LSD rounds
+    (whole=False), or the whole array is (whole=True); exact either way."""
+    old = rs.rs_learned_set_opts(use_network=0, feature_mode=0,
+                                 fallback_frac=(0.0 if whole else 1.0))
+    try:
+        rng = np.random.default_rng(12)
+        small = rng.permutation(300_000).astype(np.uint64)
+        high = (np.uint64(1) << np.uint64(63)) + rng.integers(0, 1 << 40, 2_500_000).astype(np.uint64)
+        keys = rng.permutation(np.concatenate([small, high]))
+        vals = np.arange(keys.size, dtype=np.uint64)
+        ko, vo, st = _learned(rs, keys, vals)
+        rk, rv = orc.lsd(keys, 8, vals=vals)
+        assert first_mismatch(ko, rk) is None and first_mismatch(vo, rv) is None
+        assert st.fallback == (1 if whole else 0)
+        assert st.keys_overflowed >= 2_500_000
+    finally:
+        rs.rs_learned_set_opts(**old)
+
+
+def test_small_and_in_place_take_lsd(rs, orc):
+    import gen
+    keys = gen.zipf_u64(gen.S0 + 8, 1000)
+    ko, _, st = _learned(rs, keys)
+    assert st.fallback == 1 and first_mismatch(ko, np.sort(keys)) is None
+    big = gen.zipf_u64(gen.S0 + 8, 1 << 17)
+    t = to_dev(big)
+    rs.rs_sort_u64(t, t, algo=rs.RS_ALGO_LEARNED)
+    assert first_mismatch(to_host(t, np.uint64), np.sort(big)) is None
+
+
+def test_network_gain_over_feature_only(rs):
+    """What the trained network buys: the share of keys landing in buckets
+    over LDS capacity, with the network and with the key's feature alone."""
+    import gen
+    n = 1 << 22
+    res = {}
+    for dist in ("mixture", "lognormal", "zipf"):
+        keys = _dist(dist, n, gen.S0 + 9)
+        vals = np.arange(n, dtype=np.uint64)
+        old = rs.rs_learned_set_opts(fallback_frac=1.0, max_fallback_buckets=1 << 30)
+        try:
+            _, _, st_net = _learned(rs, keys, vals)
+            rs.rs_learned_set_opts(use_network=0)
+            _, _, st_feat = _learned(rs, keys, vals)
+        finally:
+            rs.rs_learned_set_opts(**old)
+        res[dist] = (st_net.keys_overflowed / n, st_feat.keys_overflowed / n, st_net.train_loss)
+        print("%-9s overflowed keys: network %.4f  feature only %.4f  (loss %.2e)" %
+              ((dist,) + res[dist]), flush=True)
+    assert res["mixture"][0] < res["mixture"][1]
