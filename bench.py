@@ -153,14 +153,17 @@ def main():
     gkeys = n / (ms_per_step * 1e-3) / 1e9
     # whole-call algorithmic bytes: one histogram read, then one read + write
     # of keys (and values) per round
-    call_bytes = n * kb + passes * 2 * n * (kb + vb)
-    launches, tot_ms = prof.get("onesweep", (0, 0.0))
+    # (wide digits: a counting read of the keys in every round instead)
+    wide = bits >= 12
+    kname = "wide_scatter" if wide else "onesweep"
+    call_bytes = (passes if wide else 1) * n * kb + passes * 2 * n * (kb + vb)
+    launches, tot_ms = prof.get(kname, (0, 0.0))
     avg_ms = tot_ms / launches if launches else float("nan")
     bytes_per_launch = 2 * n * (kb + vb)
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9 if launches else None
     workload = "lsd_%s%s_n2p%d_b%d" % ("u32" if kb == 4 else "u64", "_kv32" if args.kv else "",
                                         args.log2n, bits)
-    traffic = pmc_traffic("onesweep", workload, source_hash())
+    traffic = pmc_traffic(kname, workload, source_hash())
     kernels = {k: {"launches": c, "avg_ms": (t / c if c else None)} for k, (c, t) in prof.items()}
 
     res = {
@@ -189,7 +192,7 @@ def main():
         "roofline": {
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": traffic,
-            "kernel": "onesweep", "bytes_per_launch": bytes_per_launch, "avg_launch_ms": avg_ms,
+            "kernel": kname, "bytes_per_launch": bytes_per_launch, "avg_launch_ms": avg_ms,
         },
         "kernels": kernels,
     }

@@ -19,6 +19,7 @@ LIB = os.path.join(PKG, "librs.so")
 
 SOURCES = [
     "rs_lsd.hip",
+    "rs_wide.hip",
     "rs_small.hip",
     "rs_seg.hip",
     "rs_learned.hip",

@@ -37,8 +37,29 @@ rs_status check_ws(const void* ws, size_t ws_bytes, size_t need) {
 int default_bits(int bits) { return bits == 0 ? 8 : bits; }
 
 // Keys (and optionally values) through the LSD rounds.
+rs_status sort_wide(const void* kin, void* kout, const void* vin, void* vout, size_t n, int kb,
+                    int vb, int bits, void* ws, size_t ws_bytes, hipStream_t st) {
+    WidePlan p;
+    if (!wide_plan(n, kb, vb, bits, &p)) return RS_ERR_UNSUPPORTED;
+    begin_call(RS_ALGO_LSD);
+    g_call.stats.radix_bits = bits;
+    g_call.stats.passes = p.passes;
+    g_call.stats.tile_keys = (int64_t)p.tile_keys;
+    if (n == 0) return RS_OK;
+    rs_status rc = check_ws(ws, ws_bytes, p.total);
+    if (rc != RS_OK) return rc;
+    rc = wide_run(p, kin, kout, vin, vout, ws, st);
+    if (rc == RS_OK) {
+        g_call.stream = st;
+        g_call.status = reinterpret_cast<const uint32_t*>(static_cast<unsigned char*>(ws) + p.off_status);
+        g_call.pending = true;
+    }
+    return rc;
+}
+
 rs_status sort_lsd(const void* kin, void* kout, const void* vin, void* vout, size_t n, int kb,
                    int vb, int bits, void* ws, size_t ws_bytes, hipStream_t st) {
+    if (bits >= 12) return sort_wide(kin, kout, vin, vout, n, kb, vb, bits, ws, ws_bytes, st);
     LsdPlan p;
     if (!lsd_plan(n, kb, vb, bits, &p)) return RS_ERR_UNSUPPORTED;
     begin_call(RS_ALGO_LSD);
@@ -250,8 +271,13 @@ size_t rs_workspace_bytes(int op, size_t n, int key_bytes, int val_bytes, int ra
             const size_t l = (n >= (1u << 16) && n < (1ull << 32)) ? learned_ws_bytes(n, vb) : 0;
             return l > p.total ? l : p.total;
         }
+        const int vb = op == RS_OP_SORT ? 0 : val_bytes;
+        if (radix_bits >= 12) {
+            WidePlan w;
+            return wide_plan(n, key_bytes, vb, radix_bits, &w) ? w.total : 0;
+        }
         LsdPlan p;
-        if (!lsd_plan(n, key_bytes, op == RS_OP_SORT ? 0 : val_bytes, radix_bits, &p)) return 0;
+        if (!lsd_plan(n, key_bytes, vb, radix_bits, &p)) return 0;
         return p.total;
     }
     if (op == RS_OP_BATCH) return ALIGN;
@@ -398,7 +424,8 @@ bool g_prof_on = false;
 namespace {
 const char* const KNAMES[KID_COUNT_] = {
     "fill", "hist", "onesweep", "copy", "batch", "seg_plan", "seg",
-    "learn_sample", "learn_train", "learn_split", "learn_assign", "learn_bucket", "learn_check"};
+    "learn_sample", "learn_train", "learn_split", "learn_assign", "learn_bucket", "learn_check",
+    "wide_count", "wide_scatter"};
 struct Mark {
     int kid;
     hipEvent_t b, e;

@@ -35,6 +35,8 @@ enum KernelId {
     KID_LEARN_ASSIGN,
     KID_LEARN_BUCKET,
     KID_LEARN_CHECK,
+    KID_WIDE_COUNT,
+    KID_WIDE_SCATTER,
     KID_COUNT_
 };
 extern bool g_prof_on;
@@ -67,6 +69,23 @@ bool lsd_plan(size_t n, int kb, int vb, int bits, LsdPlan* p, int vb2 = 0);
 // Enqueues the whole LSD sort on `st`.  `ws` holds at least p.total bytes.
 rs_status lsd_run(const LsdPlan& p, const void* kin, void* kout, const void* vin, void* vout,
                   void* ws, hipStream_t st, const void* vin2 = nullptr, void* vout2 = nullptr);
+
+// ---- wide-digit count-sort rounds (b = 12..16, reduce-then-scan) ----------
+struct WidePlan {
+    size_t n = 0;
+    int kb = 4, vb = 0;
+    int bits = 16;
+    int passes = 0;           // ceil(8*kb / b)
+    uint32_t R = 0;           // 2^b
+    uint64_t tile_keys = 0;   // keys per tile (whole 4096-key sub-tiles)
+    uint32_t tiles = 0;
+    size_t off_status = 0, off_table = 0, off_base = 0, off_tk = 0, off_tv = 0;
+    size_t total = 0;
+};
+// Plans a wide-digit sort; false unless 12 <= bits <= 16 and n < 2^32.
+bool wide_plan(size_t n, int kb, int vb, int bits, WidePlan* p);
+rs_status wide_run(const WidePlan& p, const void* kin, void* kout, const void* vin, void* vout, void* ws,
+                   hipStream_t st);
 
 // Records the HIP error of a failed launch or runtime call for rs_get_stats
 // and returns RS_ERR_HIP.

@@ -35,3 +35,55 @@ def multiset_hash(a, chunk=1 << 24):
 def first_mismatch(a, b):
     d = np.nonzero(a != b)[0]
     return None if d.size == 0 else int(d[0])
+
+
+def _ordered(t):
+    """Device tensor holding uint32/uint64 bit patterns (as int32/int64) mapped
+    to int64 values with the same order as the unsigned keys."""
+    import torch
+    if t.dtype == torch.int32:
+        return t.to(torch.int64) & 0xFFFFFFFF
+    return t ^ torch.iinfo(torch.int64).min
+
+
+def is_sorted_dev(t):
+    """True when the unsigned keys in device tensor t are non-decreasing."""
+    o = _ordered(t)
+    return bool((o[1:] >= o[:-1]).all()) if t.numel() > 1 else True
+
+
+def stable_index_kv_ok(keys_in, ko, vo):
+    """For a key-value sort whose input values are 0..n-1 (the original
+    index): true when ko is non-decreasing, vo is a permutation of 0..n-1,
+    ko[i] == keys_in[vo[i]] and equal keys keep increasing indexes.  These
+    four facts determine the stable sort's output uniquely."""
+    import torch
+    n = keys_in.numel()
+    if n == 0:
+        return True
+    idx = vo.to(torch.int64)
+    if int(idx.min()) < 0 or int(idx.max()) >= n:
+        return False
+    seen = torch.zeros(n, dtype=torch.bool, device=vo.device)
+    seen[idx] = True
+    if not bool(seen.all()):
+        return False
+    del seen
+    if not torch.equal(keys_in[idx], ko):
+        return False
+    o = _ordered(ko)
+    if n > 1 and not bool(((o[1:] > o[:-1]) | ((o[1:] == o[:-1]) & (idx[1:] > idx[:-1]))).all()):
+        return False
+    return True
+
+
+def ranks_ok(host_in, host_out, positions):
+    """The sorted position of a key is fixed by the number of smaller and
+    equal keys in the input: check below <= i < below + equal at each i."""
+    for i in positions:
+        k = host_out[i]
+        below = int(np.count_nonzero(host_in < k))
+        equal = int(np.count_nonzero(host_in == k))
+        if not (below <= i < below + equal):
+            return False
+    return True

@@ -52,6 +52,8 @@ def test_host_side_queries(lib):
     ws = lib.rs_workspace_bytes(0, n, 4, 0, 8, 1, 0)
     assert ws >= 4 * n and ws % 256 == 0                # one n-key copy plus tables
     assert lib.rs_workspace_bytes(0, n, 4, 0, 17, 1, 0) == 0   # no such radix
+    assert lib.rs_workspace_bytes(0, n, 4, 0, 16, 1, 0) >= 4 * n + 4 * 65536   # wide digits
+    assert lib.rs_workspace_bytes(0, 1 << 32, 4, 0, 16, 1, 0) == 0  # 32-bit cursors
     assert lib.rs_workspace_bytes(1, n, 8, 8, 8, 4, 0) > 16 * n  # learned kv u64
     assert lib.rs_workspace_bytes(3, 1000, 4, 0, 0, 0, 10) >= 4000
     assert lib.rs_small_capacity(4) == 16384
