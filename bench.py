@@ -1,20 +1,24 @@
 #!/usr/bin/env python3
-"""Benchmark of the plain LSD radix sort hot path on one MI355X.
+"""Benchmark of the integer-sorting hot path on one MI355X.  Prints ONE JSON
+line per invocation.
 
-One step = one complete rs_sort_u32 call (all count-sort rounds: the fill,
-the all-round histogram and the four rank-and-scatter rounds) over 2^28
-uint32 keys drawn uniform on [0, 2^32) by SplitMix64, radix 2^8, with the
-input already resident in HBM.  Prints ONE JSON line.
+Default workload (the headline): one step = one complete rs_sort_u32 call
+(all count-sort rounds: the fill, the all-round histogram and the four
+rank-and-scatter rounds) over 2^28 uint32 keys drawn uniform on [0, 2^32)
+by SplitMix64, radix 2^8, with the input already resident in HBM.
 
   python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu]
-                  [--radix-bits B] [--key-bytes 4|8] [--kv]
+                  [--workload lsd|small|segmented|learned]
+                  lsd:       [--log2n 28] [--radix-bits 8|11|16] [--key-bytes 4|8] [--kv]
+                  small:     [--small-n 4096] [--algo btn|oet|lds_radix|auto] [--p P]
+                  learned:   [--dist zipf|lognormal|mixture]
 
-The roofline object covers the dominant kernel (the onesweep rank-and-scatter
-round): its algorithmic bytes per launch (one read and one write of every key
-and value) over its mean launch time, timed with HIP events that the library
-records on the launch stream during the timed steps.  The cpu_baseline object
-times the serial C oracle on a bounded sample of the same input on one host
-core (mean of four runs, as the paper reports its timings).
+The roofline object covers the dominant kernel of the workload: its
+algorithmic bytes (or operations) per launch over its mean launch time,
+timed with HIP events that the library records on the launch stream during
+the timed steps.  The cpu_baseline object times the serial C oracle on a
+bounded sample of the same input on one host core (mean of four runs, as
+the paper reports its timings).
 """
 import argparse
 import json
@@ -26,7 +30,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "Gkeys/s + HBM GB/s, uint32 n=2^28; batched/learned vs plain radix"
-HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
+HBM_PEAK_GBS = 8000.0    # MI355X HBM3E, 8 TB/s
+VALU_PEAK_TOPS = 39.3    # 256 CUs x 64 lanes x 2.4 GHz, one 32-bit op per lane per clock
 
 
 def parse():
@@ -34,13 +39,33 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="lsd", choices=["lsd", "small", "segmented", "learned"])
     ap.add_argument("--log2n", type=int, default=28)
     ap.add_argument("--radix-bits", type=int, default=8)
     ap.add_argument("--key-bytes", type=int, default=4, choices=[4, 8])
     ap.add_argument("--kv", action="store_true", help="stable sort with a payload = index")
+    ap.add_argument("--small-n", type=int, default=4096)
+    ap.add_argument("--instances", type=int, default=10000)
+    ap.add_argument("--algo", default="auto", choices=["auto", "btn", "oet", "lds_radix"])
+    ap.add_argument("--p", type=int, default=0)
+    ap.add_argument("--segments", type=int, default=65536)
+    ap.add_argument("--plain-sample", type=int, default=512,
+                    help="segments timed one plain-radix call each (segmented workload)")
+    ap.add_argument("--dist", default="zipf", choices=["zipf", "lognormal", "mixture"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-log2n", type=int, default=26)
+    ap.add_argument("--cpu-log2n", type=int, default=28)
     return ap.parse_args()
+
+
+# ---- shared helpers ----------------------------------------------------------
+
+def source_hash(files):
+    import hashlib
+    h = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(ROOT, "paper_1708_09495_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
 
 
 def pmc_traffic(kernel, workload, src_hash):
@@ -57,35 +82,397 @@ def pmc_traffic(kernel, workload, src_hash):
     return d.get("hbm_bytes_per_launch")
 
 
-def source_hash():
-    import hashlib
-    h = hashlib.sha256()
-    for f in ("rs_lsd.hip", "rs_dev.h"):
-        with open(os.path.join(ROOT, "paper_1708_09495_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()
+def pin_one_core():
+    """Pin this process to one host core for the oracle timing; returns the
+    previous affinity set (or None where affinity is not available)."""
+    try:
+        old = os.sched_getaffinity(0)
+        os.sched_setaffinity(0, {min(old)})
+        return old
+    except (AttributeError, OSError):
+        return None
 
 
-def cpu_baseline(args, keys_host):
-    import numpy as np
+def time_oracle(fn, runs=4):
+    old = pin_one_core()
+    try:
+        times = []
+        for _ in range(runs):
+            t0 = time.perf_counter()
+            fn()
+            times.append(time.perf_counter() - t0)
+    finally:
+        if old is not None:
+            os.sched_setaffinity(0, old)
+    return sum(times) / len(times)
 
-    import oracle
-    m = 1 << args.cpu_log2n
-    sample = np.ascontiguousarray(keys_host[:m])
-    vals = np.arange(m, dtype=np.uint32) if args.kv else None
-    times = []
-    for _ in range(4):
-        t0 = time.perf_counter()
-        oracle.lsd(sample, args.radix_bits, vals=vals)
-        times.append(time.perf_counter() - t0)
-    mean = sum(times) / len(times)
+
+def timed_steps(step, steps, warmup, rs, torch):
+    """Warm-up, then exactly `steps` steps between device synchronisations,
+    with the library's launch timing on.  Returns (ms per step, profile)."""
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    rs.rs_profile_read()          # drop anything recorded before the timed region
+    rs.rs_profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    rs.rs_profile_enable(False)
+    return (t1 - t0) * 1e3 / steps, rs.rs_profile_read()
+
+
+def copy_ceiling_gbs(torch, nbytes):
+    """Read+write bandwidth of a plain device-to-device copy of nbytes."""
+    a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(2):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    reps = 10
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    return 2 * nbytes / (ms * 1e-3) / 1e9
+
+
+def kernels_of(prof):
+    return {k: {"launches": c, "avg_ms": (t / c if c else None)} for k, (c, t) in prof.items()}
+
+
+def hbm_roofline(prof, kname, bytes_per_launch, traffic=None):
+    launches, tot_ms = prof.get(kname, (0, 0.0))
+    avg_ms = tot_ms / launches if launches else float("nan")
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9 if launches else None
     return {
-        "value": m / mean / 1e9, "unit": "Gkeys/s", "cores": 1, "kind": "oracle",
-        "sample": "first 2^%d keys of the same input, serial C oracle o_lsd radix 2^%d%s, "
-                  "mean of 4 runs on one host core" % (args.cpu_log2n, args.radix_bits,
-                                                        ", payload = index" if args.kv else ""),
-        "seconds_per_run": mean,
+        "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": traffic,
+        "kernel": kname, "bytes_per_launch": bytes_per_launch, "avg_launch_ms": avg_ms,
     }
+
+
+def line(args, value, ms_per_step, dtype, data, config, roofline, prof, extra=None):
+    res = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "Gkeys/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": dtype,
+        "data": data,
+        "config": config,
+        "roofline": roofline,
+        "kernels": kernels_of(prof),
+    }
+    if extra:
+        res.update(extra)
+    return res
+
+
+# ---- plain LSD (the headline) --------------------------------------------------
+
+def bench_lsd(args, torch, rs, gen, np):
+    n = 1 << args.log2n
+    kb = args.key_bytes
+    bits = args.radix_bits
+    seed = gen.S0 + 2
+    kdt = torch.int32 if kb == 4 else torch.int64
+    keys = torch.empty(n, dtype=kdt, device="cuda")
+    (gen.uniform_u32_dev if kb == 4 else gen.uniform_u64_dev)(seed, keys)
+    out = torch.empty_like(keys)
+    vals = vout = None
+    vb = 0
+    if args.kv:
+        vb = 4
+        vals = torch.empty(n, dtype=torch.int32, device="cuda")
+        gen.iota_dev(vals)
+        vout = torch.empty_like(vals)
+    op = rs.RS_OP_SORT_KV if args.kv else rs.RS_OP_SORT
+    ws = torch.empty(rs.rs_workspace_bytes(op, n, kb, vb, bits, rs.RS_ALGO_LSD), dtype=torch.uint8,
+                     device="cuda")
+    torch.cuda.synchronize()
+
+    def step():
+        if args.kv:
+            rs.rs_sort_kv(keys, vals, out, vout, radix_bits=bits, algo=rs.RS_ALGO_LSD, ws=ws)
+        elif kb == 4:
+            rs.rs_sort_u32(keys, out, radix_bits=bits, algo=rs.RS_ALGO_LSD, ws=ws)
+        else:
+            rs.rs_sort_u64(keys, out, radix_bits=bits, algo=rs.RS_ALGO_LSD, ws=ws)
+
+    step()
+    torch.cuda.synchronize()
+    st = rs.rs_get_stats()
+    assert st.device_error == 0, "device reported a bounded-wait or range error"
+    passes = st.passes
+    ms, prof = timed_steps(step, args.steps, args.warmup, rs, torch)
+    gkeys = n / (ms * 1e-3) / 1e9
+    wide = bits >= 12
+    # whole-call algorithmic bytes: one histogram read (wide digits: a
+    # counting read in every round), then one read + write of keys (and
+    # values) per round
+    call_bytes = (passes if wide else 1) * n * kb + passes * 2 * n * (kb + vb)
+    kname = "wide_scatter" if wide else "onesweep"
+    workload = "lsd_%s%s_n2p%d_b%d" % ("u32" if kb == 4 else "u64", "_kv32" if args.kv else "",
+                                        args.log2n, bits)
+    srcs = ("rs_wide.hip", "rs_dev.h") if wide else ("rs_lsd.hip", "rs_dev.h")
+    roof = hbm_roofline(prof, kname, 2 * n * (kb + vb), pmc_traffic(kname, workload, source_hash(srcs)))
+    config = {
+        "workload": "plain LSD radix sort, %s keys%s, n=2^%d, radix 2^%d (%d count-sort rounds)"
+                    % ("uint32" if kb == 4 else "uint64",
+                       " + uint32 payload (stable)" if args.kv else " only", args.log2n, bits, passes),
+        "n": n, "key_bytes": kb, "val_bytes": vb, "radix_bits": bits, "passes": passes,
+        "tile_keys": st.tile_keys,
+    }
+    del ws, out, vout
+    torch.cuda.empty_cache()
+    extra = {
+        "hbm_gbs": call_bytes / (ms * 1e-3) / 1e9,
+        "copy_ceiling_gbs": copy_ceiling_gbs(torch, 1 << 30),
+    }
+    res = line(args, gkeys, ms, "u32" if kb == 4 else "u64",
+               "synthetic: SplitMix64 uniform keys on the full range, seed S0+2"
+               + (", payload = original index (u32)" if args.kv else ""), config, roof, prof, extra)
+    if not args.no_cpu:
+        import oracle
+        m = min(n, 1 << args.cpu_log2n)
+        kh = np.ascontiguousarray(keys[:m].cpu().numpy().view(np.uint32 if kb == 4 else np.uint64))
+        vh = np.arange(m, dtype=np.uint32) if args.kv else None
+        sec = time_oracle(lambda: oracle.lsd(kh, bits, vals=vh))
+        res["cpu_baseline"] = {
+            "value": m / sec / 1e9, "unit": "Gkeys/s", "cores": 1, "kind": "oracle",
+            "sample": "first 2^%d keys of the same input, serial C oracle o_lsd radix 2^%d%s, "
+                      "pinned to one host core, mean of 4 runs"
+                      % (m.bit_length() - 1, bits, ", payload = index" if args.kv else ""),
+            "seconds_per_run": sec,
+        }
+    return res
+
+
+# ---- small-n single arrays (BTN / OET / LDS radix) ---------------------------------
+
+def network_ops(algo, n, p):
+    """32-bit min/max operations one instance of the block network executes:
+    a register bitonic sort of each N-run (N = n_pad/p), then per merge-split
+    stage one min or max per key against the partner run and a bitonic merge
+    of the kept N keys.  Stages: lg p (lg p + 1)/2 (BTN) or p (OET)."""
+    import math
+    npad = 1 << (n - 1).bit_length()
+    N = npad // p
+    lgN = int(math.log2(N))
+    lgp = int(math.log2(p))
+    local = p * 2 * (N // 2) * lgN * (lgN + 1) // 2
+    stages = lgp * (lgp + 1) // 2 if algo == "btn" else (p if p > 1 else 0)
+    per_stage = p * (N + 2 * (N // 2) * lgN)
+    return local + stages * per_stage
+
+
+def bench_small(args, torch, rs, gen, np):
+    n = args.small_n
+    count = args.instances
+    algo = {"auto": rs.RS_ALGO_AUTO, "btn": rs.RS_ALGO_BTN, "oet": rs.RS_ALGO_OET,
+            "lds_radix": rs.RS_ALGO_LDS_RADIX}[args.algo]
+    host = gen.instances_u32(gen.S0 + 3, n, count)
+    keys = torch.from_numpy(host.reshape(-1).view(np.int32)).cuda()
+    out = torch.empty_like(keys)
+
+    def step():
+        rs.rs_sort_batch_u32(keys, n, count, out, algo=algo, p=args.p)
+
+    step()
+    torch.cuda.synchronize()
+    st = rs.rs_get_stats()
+    ms, prof = timed_steps(step, args.steps, args.warmup, rs, torch)
+    used = {rs.RS_ALGO_BTN: "btn", rs.RS_ALGO_OET: "oet", rs.RS_ALGO_LDS_RADIX: "lds_radix"}[st.algo]
+    p = st.runs_p
+    # one instance alone, and the device-wide LSD sort of one instance
+    one = keys[:n].clone()
+    one_out = torch.empty_like(one)
+    single_ms, _ = timed_steps(lambda: rs.rs_sort_batch_u32(one, n, 1, one_out, algo=algo, p=args.p),
+                               20, 3, rs, torch)
+    ws = torch.empty(rs.rs_workspace_bytes(rs.RS_OP_SORT, n, 4, 0, 8, rs.RS_ALGO_LSD), dtype=torch.uint8,
+                     device="cuda")
+    lsd_ms, _ = timed_steps(lambda: rs.rs_sort_u32(one, one_out, radix_bits=8, algo=rs.RS_ALGO_LSD, ws=ws),
+                            20, 3, rs, torch)
+    total = n * count
+    launches, tot_ms = prof.get("batch", (0, 0.0))
+    avg = tot_ms / launches if launches else float("nan")
+    if used in ("btn", "oet"):
+        ops = network_ops(used, n, p) * count
+        achieved = ops / (avg * 1e-3) / 1e12
+        roof = {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "Tops/s",
+                "frac": achieved / VALU_PEAK_TOPS, "traffic": None, "kernel": "batch",
+                "ops_per_launch": ops, "avg_launch_ms": avg}
+    else:
+        roof = hbm_roofline(prof, "batch", 8 * total)
+    res = line(args, total / (ms * 1e-3) / 1e9, ms, "u32",
+               "synthetic: %d instances of %d SplitMix64 uniform u32 keys, instance seeds from S0+3"
+               % (count, n),
+               {"workload": "small-n single arrays, %d instances of n=%d in one launch, %s p=%d"
+                            % (count, n, used, p), "n": n, "instances": count, "algo": used, "p": p},
+               roof, prof,
+               {"us_per_instance_batched": ms * 1e3 / count, "us_single_instance": single_ms * 1e3,
+                "us_device_lsd_one_instance": lsd_ms * 1e3})
+    if not args.no_cpu:
+        import oracle
+        k = max(1, min(count, (1 << 22) // n))
+
+        def run():
+            for i in range(k):
+                if used == "btn":
+                    oracle.bitonic_block(host[i], p)
+                elif used == "oet":
+                    oracle.oet_block(host[i], p)
+                else:
+                    oracle.lsd(host[i], 8)
+        sec = time_oracle(run)
+        res["cpu_baseline"] = {
+            "value": k * n / sec / 1e9, "unit": "Gkeys/s", "cores": 1, "kind": "oracle",
+            "sample": "first %d instances, serial C oracle %s, pinned to one host core, mean of 4 runs"
+                      % (k, {"btn": "o_bitonic_block", "oet": "o_oet_block"}.get(used, "o_lsd")),
+            "seconds_per_run": sec,
+        }
+    return res
+
+
+# ---- batched segmented ----------------------------------------------------------
+
+def bench_segmented(args, torch, rs, gen, np):
+    S = args.segments
+    lens = gen.loguniform_lengths(gen.S0 + 4, S, 4.0, 20.0)
+    off = np.zeros(S + 1, dtype=np.int64)
+    np.cumsum(lens, out=off[1:])
+    total = int(off[-1])
+    keys = torch.empty(total, dtype=torch.int32, device="cuda")
+    gen.uniform_u32_dev(gen.S0 + 4, keys)
+    offd = torch.from_numpy(off).cuda()
+    out = torch.empty_like(keys)
+    ws = torch.empty(rs.rs_workspace_bytes(rs.RS_OP_SEGMENTED, total, 4, 0, 0, rs.RS_ALGO_AUTO, S),
+                     dtype=torch.uint8, device="cuda")
+
+    def step():
+        rs.rs_sort_segmented(keys, offd, out, ws=ws)
+
+    step()
+    torch.cuda.synchronize()
+    assert rs.rs_get_stats().device_error == 0
+    ms, prof = timed_steps(step, args.steps, args.warmup, rs, torch)
+    # algorithmic bytes: a segment held in LDS is read and written once; a
+    # larger one takes four radix-2^8 rounds through HBM
+    small = lens <= 16384
+    alg = 8 * int(lens[small].sum()) + 32 * int(lens[~small].sum())
+    roof = hbm_roofline(prof, "seg", alg)
+    # one plain LSD call per array, on a seeded sample of the segments
+    rng = np.random.default_rng(int(gen.S0 + 4))
+    pick = rng.choice(S, size=min(args.plain_sample, S), replace=False)
+    lws = torch.empty(rs.rs_workspace_bytes(rs.RS_OP_SORT, int(lens.max()), 4, 0, 8, rs.RS_ALGO_LSD),
+                      dtype=torch.uint8, device="cuda")
+    views = [(keys[off[i]:off[i + 1]], out[off[i]:off[i + 1]]) for i in pick]
+
+    def plain():
+        for a, b in views:
+            rs.rs_sort_u32(a, b, radix_bits=8, algo=rs.RS_ALGO_LSD, ws=lws)
+
+    plain()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plain()
+    torch.cuda.synchronize()
+    plain_s = (time.perf_counter() - t0) * S / len(pick)   # scaled to all segments
+    res = line(args, total / (ms * 1e-3) / 1e9, ms, "u32",
+               "synthetic: %d segments, lengths log-uniform in [16, 2^20) (seed S0+4), "
+               "SplitMix64 uniform u32 keys (seed S0+4)" % S,
+               {"workload": "batched segmented sort, %d segments, %d keys, one persistent launch"
+                            % (S, total), "segments": S, "total_keys": total},
+               roof, prof,
+               {"hbm_gbs": alg / (ms * 1e-3) / 1e9,
+                "plain_per_array_gkeys": total / plain_s / 1e9,
+                "plain_per_array_sample": "%d seeded segments, one rs_sort_u32 (LSD, radix 2^8) each, "
+                                          "time scaled by %d/%d" % (len(pick), S, len(pick)),
+                "speedup_vs_plain_per_array": plain_s / (ms * 1e-3)})
+    del ws, lws, views
+    if not args.no_cpu:
+        import oracle
+        k = int(np.searchsorted(off, 1 << 24))
+        k = max(1, min(S, k))
+        hostk = keys[:off[k]].cpu().numpy().view(np.uint32)
+        sub = off[:k + 1].copy()
+        sec = time_oracle(lambda: oracle.segmented(hostk, sub))
+        res["cpu_baseline"] = {
+            "value": int(off[k]) / sec / 1e9, "unit": "Gkeys/s", "cores": 1, "kind": "oracle",
+            "sample": "first %d segments (%d keys), serial C oracle o_segmented, pinned to one host "
+                      "core, mean of 4 runs" % (k, int(off[k])),
+            "seconds_per_run": sec,
+        }
+    return res
+
+
+# ---- learned-CDF buckets ---------------------------------------------------------
+
+def bench_learned(args, torch, rs, gen, np):
+    n = 1 << args.log2n
+    host = {"zipf": gen.zipf_u64, "lognormal": gen.lognormal_u64,
+            "mixture": gen.gauss_mix_u64}[args.dist](gen.S0 + 5, n)
+    keys = torch.from_numpy(host.view(np.int64)).cuda()
+    vals = torch.empty(n, dtype=torch.int64, device="cuda")
+    gen.iota_dev(vals)
+    ko, vo = torch.empty_like(keys), torch.empty_like(vals)
+    ws = torch.empty(rs.rs_workspace_bytes(rs.RS_OP_SORT_KV, n, 8, 8, 0, rs.RS_ALGO_LEARNED),
+                     dtype=torch.uint8, device="cuda")
+
+    def step():
+        rs.rs_sort_kv(keys, vals, ko, vo, algo=rs.RS_ALGO_LEARNED, ws=ws)
+
+    step()
+    torch.cuda.synchronize()
+    st = rs.rs_get_stats()
+    assert st.device_error == 0
+    ms, prof = timed_steps(step, args.steps, args.warmup, rs, torch)
+
+    def plain():
+        rs.rs_sort_kv(keys, vals, ko, vo, radix_bits=8, algo=rs.RS_ALGO_LSD, ws=ws)
+
+    plain_ms, _ = timed_steps(plain, max(3, args.steps // 2), 1, rs, torch)
+    # dominant kernel: the two stable bucket-id rounds, each reading and
+    # writing the 2-byte id, the key and the payload
+    roof = hbm_roofline(prof, "learn_pass", 2 * n * (2 + 8 + 8))
+    res = line(args, n / (ms * 1e-3) / 1e9, ms, "u64",
+               "synthetic: %s u64 keys (seed S0+5), u64 payload = original index" % args.dist,
+               {"workload": "learned-CDF buckets, n=2^%d u64 keys + u64 payload, %s" % (args.log2n, args.dist),
+                "n": n, "dist": args.dist},
+               roof, prof,
+               {"plain_lsd_gkeys": n / (plain_ms * 1e-3) / 1e9, "plain_lsd_ms": plain_ms,
+                "speedup_vs_plain": plain_ms / ms,
+                "fallback": st.fallback, "buckets_overflowed": st.buckets_overflowed,
+                "keys_overflowed": st.keys_overflowed, "train_loss": st.train_loss})
+    del ws
+    if not args.no_cpu:
+        import oracle
+        m = min(n, 1 << 25)
+        kh = np.ascontiguousarray(host[:m])
+        vh = np.arange(m, dtype=np.uint64)
+        sec = time_oracle(lambda: oracle.lsd(kh, 8, vals=vh))
+        res["cpu_baseline"] = {
+            "value": m / sec / 1e9, "unit": "Gkeys/s", "cores": 1, "kind": "oracle",
+            "sample": "first 2^%d keys, serial C oracle o_lsd (stable kv, radix 2^8): the oracle "
+                      "of the learned path is the stable sort; pinned to one core, mean of 4 runs"
+                      % (m.bit_length() - 1),
+            "seconds_per_run": sec,
+        }
+    return res
 
 
 def main():
@@ -101,105 +488,10 @@ def main():
     import gen
     import paper_1708_09495_amd as rs
 
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
-    n = 1 << args.log2n
-    kb = args.key_bytes
-    bits = args.radix_bits
-    seed = gen.S0 + 2
-    kdt = torch.int32 if kb == 4 else torch.int64
-    keys = torch.empty(n, dtype=kdt, device=dev)
-    (gen.uniform_u32_dev if kb == 4 else gen.uniform_u64_dev)(seed, keys)
-    out = torch.empty_like(keys)
-    vals = vout = None
-    vb = 0
-    if args.kv:
-        vb = 4
-        vals = torch.empty(n, dtype=torch.int32, device=dev)
-        gen.iota_dev(vals)
-        vout = torch.empty_like(vals)
-    op = rs.RS_OP_SORT_KV if args.kv else rs.RS_OP_SORT
-    ws = torch.empty(rs.rs_workspace_bytes(op, n, kb, vb, bits, rs.RS_ALGO_LSD), dtype=torch.uint8,
-                     device=dev)
-    torch.cuda.synchronize()
-
-    def step():
-        if args.kv:
-            rs.rs_sort_kv(keys, vals, out, vout, radix_bits=bits, algo=rs.RS_ALGO_LSD, ws=ws)
-        elif kb == 4:
-            rs.rs_sort_u32(keys, out, radix_bits=bits, algo=rs.RS_ALGO_LSD, ws=ws)
-        else:
-            rs.rs_sort_u64(keys, out, radix_bits=bits, algo=rs.RS_ALGO_LSD, ws=ws)
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    st = rs.rs_get_stats()
-    assert st.device_error == 0, "device reported a bounded-wait error"
-    passes = st.passes
-
-    rs.rs_profile_read()          # drop anything recorded before the timed region
-    rs.rs_profile_enable(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    rs.rs_profile_enable(False)
-    prof = rs.rs_profile_read()
-
-    ms_per_step = (t1 - t0) * 1e3 / args.steps
-    gkeys = n / (ms_per_step * 1e-3) / 1e9
-    # whole-call algorithmic bytes: one histogram read, then one read + write
-    # of keys (and values) per round
-    # (wide digits: a counting read of the keys in every round instead)
-    wide = bits >= 12
-    kname = "wide_scatter" if wide else "onesweep"
-    call_bytes = (passes if wide else 1) * n * kb + passes * 2 * n * (kb + vb)
-    launches, tot_ms = prof.get(kname, (0, 0.0))
-    avg_ms = tot_ms / launches if launches else float("nan")
-    bytes_per_launch = 2 * n * (kb + vb)
-    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9 if launches else None
-    workload = "lsd_%s%s_n2p%d_b%d" % ("u32" if kb == 4 else "u64", "_kv32" if args.kv else "",
-                                        args.log2n, bits)
-    traffic = pmc_traffic(kname, workload, source_hash())
-    kernels = {k: {"launches": c, "avg_ms": (t / c if c else None)} for k, (c, t) in prof.items()}
-
-    res = {
-        "metric": METRIC,
-        "value": gkeys,
-        "unit": "Gkeys/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "u32" if kb == 4 else "u64",
-        "data": "synthetic: SplitMix64 uniform keys on the full range, seed S0+2"
-                + (", payload = original index (u32)" if args.kv else ""),
-        "config": {
-            "workload": "plain LSD radix sort, %s keys%s, n=2^%d, radix 2^%d (%d count-sort rounds)"
-                        % ("uint32" if kb == 4 else "uint64",
-                           " + uint32 payload (stable)" if args.kv else " only", args.log2n, bits,
-                           passes),
-            "n": n, "key_bytes": kb, "val_bytes": vb, "radix_bits": bits, "passes": passes,
-            "tile_keys": st.tile_keys,
-        },
-        "hbm_gbs": call_bytes / (ms_per_step * 1e-3) / 1e9,
-        "roofline": {
-            "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": traffic,
-            "kernel": kname, "bytes_per_launch": bytes_per_launch, "avg_launch_ms": avg_ms,
-        },
-        "kernels": kernels,
-    }
-    if not args.no_cpu:
-        kh = keys[: 1 << args.cpu_log2n].cpu().numpy().view(np.uint32 if kb == 4 else np.uint64)
-        res["cpu_baseline"] = cpu_baseline(args, kh)
-    print(json.dumps(res))
+    torch.cuda.set_device(torch.device("cuda:0"))
+    fn = {"lsd": bench_lsd, "small": bench_small, "segmented": bench_segmented,
+          "learned": bench_learned}[args.workload]
+    print(json.dumps(fn(args, torch, rs, gen, np)), flush=True)
 
 
 if __name__ == "__main__":

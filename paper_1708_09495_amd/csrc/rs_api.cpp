@@ -425,7 +425,7 @@ namespace {
 const char* const KNAMES[KID_COUNT_] = {
     "fill", "hist", "onesweep", "copy", "batch", "seg_plan", "seg",
     "learn_sample", "learn_train", "learn_split", "learn_assign", "learn_bucket", "learn_check",
-    "wide_count", "wide_scatter"};
+    "wide_count", "wide_scatter", "learn_pass"};
 struct Mark {
     int kid;
     hipEvent_t b, e;

@@ -37,6 +37,7 @@ enum KernelId {
     KID_LEARN_CHECK,
     KID_WIDE_COUNT,
     KID_WIDE_SCATTER,
+    KID_LEARN_PASS,
     KID_COUNT_
 };
 extern bool g_prof_on;
@@ -61,6 +62,8 @@ struct LsdPlan {
     size_t off_status = 0, off_ctr = 0, off_hist = 0, off_lb = 0, off_tk = 0, off_tv = 0, off_tv2 = 0;
     size_t zero_bytes = 0;   // bytes from off_status that must be zeroed (status, ctr, hist)
     size_t total = 0;
+    int kid_hist = KID_HIST;          // timing labels of the plan's launches
+    int kid_scatter = KID_ONESWEEP;
 };
 
 // Plans an LSD sort; returns false when (kb, vb, bits, vb2) is not supported.

@@ -947,6 +947,8 @@ bool learn_layout(size_t n, int vb, LearnLayout* L) {
     LearnLayout q;
     if (!lsd_plan(M, 8, 0, 8, &q.sample_plan)) return false;
     if (!lsd_plan(n, 2, 8, 8, &q.pass_plan, vb)) return false;
+    q.sample_plan.kid_hist = q.sample_plan.kid_scatter = KID_LEARN_SAMPLE;
+    q.pass_plan.kid_hist = q.pass_plan.kid_scatter = KID_LEARN_PASS;
     if (!lsd_plan(n, 8, vb, 8, &q.fb_plan)) return false;
     size_t off = 0;
     auto take = [&](size_t bytes) {

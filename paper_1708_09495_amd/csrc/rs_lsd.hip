@@ -231,38 +231,41 @@ __global__ __launch_bounds__(NT) void k_onesweep(
     }
     __syncthreads();
 
-    // ---- per digit: exclusive prefix over waves, tile total, published at
-    //      once for the tiles that follow
-    for (int d = tid; d < R; d += NT) {
-        uint32_t s = 0;
-#pragma unroll
-        for (int w = 0; w < NW; ++w) {
-            const uint32_t c = wcnt[w * R + d];
-            wcnt[w * R + d] = (uint16_t)s;
-            s += c;
-        }
-        tot[d] = s;
-        if (tile != 0)
-            st_agent(&lb[(size_t)tile * R + d], (LB)(((LB)FLAG_AGG << LBW<LB>::SH) | (LB)s));
-    }
-    __syncthreads();
-
-    // ---- local exclusive scan over digits -> first LDS slot of each digit
+    // ---- per digit: tile total (published at once for the tiles that
+    //      follow), first LDS slot (exclusive scan over digits) and, per
+    //      wave, the slot of the wave's first key of the digit
     {
         uint32_t part[PER];
         uint32_t s = 0;
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
             const int d = tid * PER + q;
-            part[q] = d < R ? tot[d] : 0u;
-            s += part[q];
+            uint32_t t = 0;
+            if (d < R) {
+#pragma unroll
+                for (int w = 0; w < NW; ++w) t += wcnt[w * R + d];
+                tot[d] = t;
+                if (tile != 0)
+                    st_agent(&lb[(size_t)tile * R + d], (LB)(((LB)FLAG_AGG << LBW<LB>::SH) | (LB)t));
+            }
+            part[q] = t;
+            s += t;
         }
         uint32_t total;
         uint32_t ex = block_excl_scan<NT>(s, wsum, &total);
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
             const int d = tid * PER + q;
-            if (d < R) loc[d] = ex;
+            if (d < R) {
+                loc[d] = ex;
+                uint32_t run = ex;
+#pragma unroll
+                for (int w = 0; w < NW; ++w) {
+                    const uint32_t c = wcnt[w * R + d];
+                    wcnt[w * R + d] = (uint16_t)run;
+                    run += c;
+                }
+            }
             ex += part[q];
         }
     }
@@ -340,7 +343,7 @@ __global__ __launch_bounds__(NT) void k_onesweep(
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
         const uint32_t d = dr[i] & 0xFFFFu;
-        dr[i] = loc[d] + wcnt[wave * R + d] + (dr[i] >> 16);
+        dr[i] = wcnt[wave * R + d] + (dr[i] >> 16);
     }
     __syncthreads();  // the counters share LDS with the key buffer
 #pragma unroll
@@ -413,11 +416,11 @@ hipError_t launch_pass(const LsdPlan& p, const void* src, void* dst, const void*
     LB* lb = reinterpret_cast<LB*>(ws + p.off_lb) + (size_t)pass * p.lb_words;
     const uint32_t* gh = reinterpret_cast<const uint32_t*>(ws + p.off_hist) + (size_t)pass * p.R;
     uint32_t* status = reinterpret_cast<uint32_t*>(ws + p.off_status);
-    prof(st, KID_ONESWEEP, 0);
+    prof(st, p.kid_scatter, 0);
     hipLaunchKernelGGL((k_onesweep<K, VB, MAXB, ITEMS, LB, OFF, VB2>), dim3((unsigned)p.tiles), dim3(NT),
                        0, st, (const K*)src, (K*)dst, vsrc, vdst, (uint64_t)p.n, pass * p.bits, p.bits,
                        ctr, lb, gh, status, v2src, v2dst);
-    prof(st, KID_ONESWEEP, 1);
+    prof(st, p.kid_scatter, 1);
     return hipGetLastError();
 }
 
@@ -535,7 +538,7 @@ rs_status lsd_run(const LsdPlan& p, const void* kin, void* kout, const void* vin
         const size_t shm = sizeof(uint32_t) * (size_t)p.passes * p.R;
         uint32_t* gh = reinterpret_cast<uint32_t*>(ws + p.off_hist);
         uint32_t* zp = reinterpret_cast<uint32_t*>(ws + p.off_lb);
-        prof(st, KID_HIST, 0);
+        prof(st, p.kid_hist, 0);
         if (p.kb == 2)
             hipLaunchKernelGGL(k_hist<uint16_t>, dim3((unsigned)g), dim3(HIST_NT), shm, st,
                                (const uint16_t*)kin, (uint64_t)p.n, p.bits, p.passes, gh, zp,
@@ -548,7 +551,7 @@ rs_status lsd_run(const LsdPlan& p, const void* kin, void* kout, const void* vin
             hipLaunchKernelGGL(k_hist<uint64_t>, dim3((unsigned)g), dim3(HIST_NT), shm, st,
                                (const uint64_t*)kin, (uint64_t)p.n, p.bits, p.passes, gh, zp,
                                (uint64_t)lb_u32);
-        prof(st, KID_HIST, 1);
+        prof(st, p.kid_hist, 1);
         if ((rc = launch_status()) != RS_OK) return rc;
     }
     // Buffers: the rounds alternate between `out` and the workspace copy so
