@@ -69,17 +69,21 @@ def source_hash(files):
 
 
 def pmc_traffic(kernel, workload, src_hash):
-    """HBM bytes per launch from a committed rocprofv3 --pmc summary, if one
-    exists for this kernel, workload and kernel source; else None."""
-    path = os.path.join(ROOT, "profiles", "pmc_%s_%s.json" % (kernel, workload))
+    """HBM bytes per launch from a committed rocprofv3 --pmc summary
+    (profiles/pmc_<kernel>_<workload>.txt, "key: value" lines), if one exists
+    for this kernel, workload and kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "pmc_%s_%s.txt" % (kernel, workload))
     try:
         with open(path) as f:
-            d = json.load(f)
-    except (OSError, ValueError):
+            d = dict(line.split(": ", 1) for line in f.read().splitlines() if ": " in line)
+    except OSError:
         return None
-    if d.get("source_sha256") != src_hash:
+    if d.get("source_sha256", "").strip() != src_hash:
         return None
-    return d.get("hbm_bytes_per_launch")
+    try:
+        return int(d["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def pin_one_core():
