@@ -24,11 +24,12 @@ extern "C" {
 #endif
 
 typedef struct {
-    int32_t train_steps;          /* Adam steps (default 256)                       */
+    int32_t train_steps;          /* Adam steps (default 32)                        */
     float lr;                     /* Adam learning rate (default 1e-2)              */
     int32_t use_network;          /* 0: buckets from the key's feature alone       */
     int32_t bucket_cap;           /* pairs one bucket may hold in LDS (<= 6144)    */
-    int32_t feature_mode;         /* -1 automatic, 0 linear in the key, 1 log2     */
+    int32_t feature_mode;         /* -1 automatic (2), 0 linear in the key, 1 log2, */
+                                  /* 2 piecewise linear between sample quantiles  */
     double fallback_frac;         /* overflowed-key share above which the whole    */
                                   /* array is sorted by the LSD rounds instead     */
     int32_t train_blocks;         /* workgroups of the training launch             */

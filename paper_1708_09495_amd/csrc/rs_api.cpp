@@ -325,7 +325,7 @@ rs_status rs_get_stats(rs_stats* out) {
 
 extern "C" rs_status rs_learned_set_opts(const rs_learned_opts* o) {
     if (!o || o->train_steps < 0 || o->train_steps > 100000 || !(o->lr > 0.f) || o->bucket_cap < 2 ||
-        o->feature_mode < -1 || o->feature_mode > 1 || o->fallback_frac < 0.0 || o->train_blocks < 1 ||
+        o->feature_mode < -1 || o->feature_mode > 2 || o->fallback_frac < 0.0 || o->train_blocks < 1 ||
         o->train_blocks > 4096 || o->max_fallback_buckets < 0)
         return RS_ERR_INVALID;
     rs::LearnOpts& d = rs::learn_opts();

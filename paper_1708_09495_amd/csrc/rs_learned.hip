@@ -37,7 +37,9 @@ constexpr int H = 32;
 constexpr int NP = 4 * H + H * H + 1;  // 1153 free parameters
 constexpr int P_V1 = 0, P_B1 = H, P_V2 = 2 * H, P_B2 = 2 * H + H * H, P_V3 = P_B2 + H, P_B3 = P_V3 + H;
 constexpr uint32_t NB = 65536;         // buckets
-constexpr uint32_t M = 65536;          // sample size
+constexpr uint32_t MS = 1u << 18;      // keys sampled and sorted (targets, calibration)
+constexpr uint32_t M = 65536;          // training points: every (MS/M)-th sorted sample key
+constexpr uint32_t MSTRIDE = MS / M;
 constexpr int TR_NT = 256;             // training threads per workgroup
 constexpr int BS_NT = 512;             // bucket-sort threads per workgroup
 constexpr int BS_ITEMS = 12;
@@ -47,21 +49,26 @@ constexpr int AS_KEYS = 8;             // keys per assignment thread
 constexpr int TOP = 4096;              // splitter groups of 16 held in LDS
 constexpr int GBUF = NP + 1;           // gradient buffer: parameters + loss
 constexpr uint32_t MID_CAP = 1u << 20; // largest bucket sorted by one workgroup
-constexpr int KNOTS = 256;             // calibration intervals of the network output
+constexpr uint32_t MID_GRID = 1024;    // workgroups sorting the mid-size buckets
+constexpr int KNOTS = 1024;            // calibration intervals of the network output
+constexpr int QK = 64;                 // key-quantile intervals of the piecewise-linear feature
 
 struct State {
     uint64_t kmin, kmax;
     double inv_span, inv_logspan;
-    int32_t mode;          // feature: 0 linear in the key, 1 linear in log2(key)
+    int32_t mode;          // feature: 0 linear in the key, 1 linear in log2(key),
+                           // 2 piecewise linear between the sample's key quantiles
     uint32_t reach;        // number of reachable splitters
     float loss;            // last training loss (mean squared error)
     uint32_t bar_count, bar_gen;
     uint32_t ovf_buckets;          // buckets over the LDS capacity
     unsigned long long ovf_keys;   // keys in them
+    uint32_t mid_buckets;          // buckets split and sorted by k_bucket_mid
     uint32_t big_buckets;          // buckets too big for one workgroup (host fallback)
     unsigned long long big_keys;
     uint32_t unsorted;
     uint32_t err;
+    uint64_t qk[QK + 1];   // sample keys at quantiles g/QK (mode 2)
 };
 
 __device__ __forceinline__ uint64_t mix64(uint64_t z) {
@@ -73,9 +80,28 @@ __device__ __forceinline__ uint64_t mix64(uint64_t z) {
 __device__ __forceinline__ float softplusf_(float v) { return v > 20.f ? v : log1pf(expf(v)); }
 __device__ __forceinline__ float sigmoidf_(float v) { return 1.f / (1.f + expf(-v)); }
 
-// Feature of a key: its position in [kmin, kmax], linear or log-scaled,
-// computed in double and rounded once to float.
+// Feature of a key, computed in double and rounded once to float.  Mode 2
+// (the default): the key's position among the sample's key quantiles qk[g]
+// (g/QK of the sample at or below), linear inside each interval, so the
+// feature spreads the keys nearly evenly over [0, 1] whatever their range and
+// keeps float resolution where the keys are dense.  Modes 0/1: the position
+// in [kmin, kmax], linear or log-scaled.  Every mode is non-decreasing in
+// the key.
 __device__ __forceinline__ float feat(uint64_t k, const State& s) {
+    if (s.mode == 2) {
+        if (k <= s.qk[0]) return 0.f;
+        if (k >= s.qk[QK]) return 1.f;
+        int lo = 0, hi = QK;  // qk[lo] <= k < qk[hi]
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (s.qk[mid] <= k) lo = mid;
+            else hi = mid;
+        }
+        const double f = (double)(k - s.qk[lo]) / (double)(s.qk[hi] - s.qk[lo]);
+        double x = ((double)lo + f) * (1.0 / QK);
+        x = x < 0.0 ? 0.0 : (x > 1.0 ? 1.0 : x);
+        return (float)x;
+    }
     const uint64_t d = k > s.kmin ? k - s.kmin : 0ull;
     double x = s.mode ? log2((double)d + 1.0) * s.inv_logspan : (double)d * s.inv_span;
     x = x < 0.0 ? 0.0 : (x > 1.0 ? 1.0 : x);
@@ -166,30 +192,34 @@ __device__ __forceinline__ uint32_t bucket_of(const Mlp& W, const State& s, cons
 __global__ void k_sample(const uint64_t* __restrict__ keys, uint64_t n, uint64_t seed,
                          uint64_t* __restrict__ sample) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < M) sample[i] = keys[mix64(seed + (uint64_t)(i + 1) * 0x9E3779B97F4A7C15ULL) % n];
+    if (i < MS) sample[i] = keys[mix64(seed + (uint64_t)(i + 1) * 0x9E3779B97F4A7C15ULL) % n];
 }
 
 __global__ void k_setup(const uint64_t* __restrict__ s, State* st, int mode_req) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    const uint64_t kmin = s[0], kmax = s[M - 1];
+    if (blockIdx.x != 0) return;
+    for (int g = threadIdx.x; g <= QK; g += blockDim.x) {
+        const uint64_t i = (uint64_t)g * MS / QK;
+        st->qk[g] = s[i < MS ? i : MS - 1];
+    }
+    if (threadIdx.x != 0) return;
+    const uint64_t kmin = s[0], kmax = s[MS - 1];
     const uint64_t span = kmax - kmin;
     st->kmin = kmin;
     st->kmax = kmax;
     st->inv_span = span ? 1.0 / (double)span : 0.0;
     const double ls = log2((double)span + 1.0);
     st->inv_logspan = span ? 1.0 / ls : 0.0;
-    // log features when the linear positions crowd near zero (the sample's
-    // median sits in the lowest thousandth of the key range)
-    const double xmed = (double)(s[M / 2] - kmin) * st->inv_span;
-    st->mode = mode_req >= 0 ? mode_req : (xmed < 1e-3 ? 1 : 0);
+    st->mode = mode_req >= 0 ? mode_req : 2;
 }
 
+// Training point i is the middle key of the i-th group of MSTRIDE sorted
+// sample keys; its target is its mid-rank in the whole sorted sample.
 __global__ void k_targets(const uint64_t* __restrict__ s, const State* __restrict__ st,
                           float* __restrict__ xs, float* __restrict__ ts) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= M) return;
-    const uint64_t k = s[i];
-    uint32_t lo = 0, hi = M;  // first index with s >= k
+    const uint64_t k = s[i * MSTRIDE + MSTRIDE / 2];
+    uint32_t lo = 0, hi = MS;  // first index with s >= k
     while (lo < hi) {
         const uint32_t mid = (lo + hi) >> 1;
         if (s[mid] < k) lo = mid + 1;
@@ -197,14 +227,14 @@ __global__ void k_targets(const uint64_t* __restrict__ s, const State* __restric
     }
     const uint32_t first = lo;
     lo = first;
-    hi = M;  // first index with s > k
+    hi = MS;  // first index with s > k
     while (lo < hi) {
         const uint32_t mid = (lo + hi) >> 1;
         if (s[mid] <= k) lo = mid + 1;
         else hi = mid;
     }
     xs[i] = feat(k, *st);
-    ts[i] = (float)(((double)first + (double)lo) / (2.0 * (double)M));
+    ts[i] = (float)(((double)first + (double)lo) / (2.0 * (double)MS));
 }
 
 // ---- 2. training -------------------------------------------------------------------
@@ -255,6 +285,22 @@ struct TrainCfg {
 // units into (0, 1).  Training then refines every parameter.
 __device__ float inv_softplus(float w) { return w > 20.f ? w : logf(expm1f(w)); }
 
+// Output layer at the start: after the first two layers every unit swings
+// between about -A and +A (A = tanh(1)), so z = b3 + sum w3_i h2_i climbs
+// by A (w3_k + w3_k+1) between the centres of slices k and k+1.  The
+// weights make that climb the logit difference of the centres' target CDF
+// values (k + 1/2)/H, so sigmoid(z) starts close to the sample's CDF.
+__device__ float logit_mid(int k) {
+    const float q = ((float)k + 0.5f) / (float)H;
+    return logf(q / (1.f - q));
+}
+__device__ float init_w3(int k) {
+    const float A = 0.7615942f;
+    const int a = k > 0 ? k - 1 : 0, b = k < H - 1 ? k : H - 2;
+    const float dl = logit_mid(a + 1) - logit_mid(a), dr = logit_mid(b + 1) - logit_mid(b);
+    return (dl + dr) / (4.f * A);
+}
+
 __device__ float init_param(int p, const float* __restrict__ xs, uint32_t m) {
     if (p < P_B2 && p >= P_V2) {
         const int o = (p - P_V2) / H, i = (p - P_V2) % H;
@@ -269,9 +315,14 @@ __device__ float init_param(int p, const float* __restrict__ xs, uint32_t m) {
         w = fminf(w, 1e6f);
         return p < P_B1 ? inv_softplus(w) : -w * c;
     }
-    if (p < P_V3) return 0.0f;                       // b2
-    if (p < P_B3) return inv_softplus(4.0f / (H * 0.76f));  // w3: 32 units of +-0.76 span +-4
-    return 0.0f;                                     // b3
+    if (p < P_V3) return 0.0f;                                  // b2
+    if (p < P_B3) return inv_softplus(init_w3(p - P_V3));       // w3
+    // b3: z at the middle slice's centre equals its target logit
+    const float A = 0.7615942f;
+    float acc = 0.f;
+    for (int i = 0; i < H; ++i)
+        if (i != H / 2) acc += (i < H / 2 ? A : -A) * init_w3(i);
+    return logit_mid(H / 2) - acc;
 }
 
 __global__ __launch_bounds__(TR_NT) void k_train(const float* __restrict__ xs, const float* __restrict__ ts,
@@ -414,27 +465,49 @@ __global__ __launch_bounds__(TR_NT) void k_train(const float* __restrict__ xs, c
 // ---- 3a. calibration knots ------------------------------------------------------------
 
 __global__ __launch_bounds__(256) void k_calibrate(const float* __restrict__ params,
-                                                   const float* __restrict__ xs, float* __restrict__ knot,
+                                                   const uint64_t* __restrict__ sorted,
+                                                   const State* __restrict__ st, float* __restrict__ knot,
                                                    int use_net) {
+    constexpr int PER = (KNOTS + 1 + 255) / 256;
     __shared__ Mlp W;
     __shared__ float raw[NP];
-    __shared__ float kv[KNOTS + 1];
+    __shared__ float part[256];
+    __shared__ State S;
     for (int p = threadIdx.x; p < NP; p += blockDim.x) raw[p] = params[p];
+    if (threadIdx.x == 0) S = *st;
     __syncthreads();
     mlp_derive(raw, W, false);
     __syncthreads();
-    for (int g = threadIdx.x; g <= KNOTS; g += blockDim.x) {
-        const uint32_t i = (uint64_t)g * M / KNOTS < M ? (uint32_t)((uint64_t)g * M / KNOTS) : M - 1;
-        const float x = xs[i];
-        kv[g] = use_net ? mlp_y(W, x) : x;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        float m = kv[0];
-        for (int g = 0; g <= KNOTS; ++g) {
-            m = kv[g] > m ? kv[g] : m;
-            knot[g] = m;
+    // knot g: the network output at the sample's g/KNOTS quantile; thread t
+    // holds knots [t*PER, t*PER + PER) and takes their running maximum
+    float kv[PER];
+    float m = -1.f;
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int g = threadIdx.x * PER + q;
+        if (g <= KNOTS) {
+            const uint64_t i = (uint64_t)g * MS / KNOTS;
+            const float x = feat(sorted[i < MS ? i : MS - 1], S);
+            const float y = use_net ? mlp_y(W, x) : x;
+            m = y > m ? y : m;
         }
+        kv[q] = m;
+    }
+    // exclusive maximum over the threads before this one (the knots must not
+    // decrease even where float rounding bends the network)
+    part[threadIdx.x] = m;
+    __syncthreads();
+    for (int o = 1; o < 256; o <<= 1) {
+        const float v = threadIdx.x >= (unsigned)o ? part[threadIdx.x - o] : -1.f;
+        __syncthreads();
+        if (v > part[threadIdx.x]) part[threadIdx.x] = v;
+        __syncthreads();
+    }
+    const float before = threadIdx.x ? part[threadIdx.x - 1] : -1.f;
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int g = threadIdx.x * PER + q;
+        if (g <= KNOTS) knot[g] = kv[q] > before ? kv[q] : before;
     }
 }
 
@@ -595,19 +668,20 @@ __global__ __launch_bounds__(1024) void k_bucket_fix(uint32_t* __restrict__ star
 // Data ping-pongs between the bucket's place and the same place in a
 // scratch array; values follow their keys by gathering from the tile.
 template <int VB>
-__device__ void bucket_global_lsd(uint64_t* __restrict__ ka, uint64_t* __restrict__ va,
+__device__ __forceinline__ void bucket_global_lsd(uint64_t* __restrict__ ka, uint64_t* __restrict__ va,
                                   uint64_t* __restrict__ kb, uint64_t* __restrict__ vb, uint32_t L,
                                   uint64_t mn, uint64_t mx, uint64_t* sk, uint16_t* sidx, uint16_t* wcnt,
-                                  uint32_t* loc, uint32_t* wsum, uint32_t* tot, uint32_t* run) {
+                                  uint32_t* loc, uint32_t* wsum, uint32_t* tot, uint32_t* run, int sh0 = 0,
+                                  int nrounds = 0, bool copy_back = true) {
     constexpr int NW = BS_NT / WAVE;
     constexpr int R = 256;
     uint64_t* wmask = sk;
     const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int rounds = (64 - __clzll((unsigned long long)(mx - mn)) + 7) / 8;
+    const int rounds = nrounds > 0 ? nrounds : (64 - __clzll((unsigned long long)(mx - mn)) + 7) / 8;
     const uint64_t mybit = 1ull << lane;
     const uint32_t wb = wave * (BS_ITEMS * WAVE) + lane;
     for (int r = 0; r < rounds; ++r) {
-        const int shift = 8 * r;
+        const int shift = sh0 + 8 * r;
         uint64_t* sk_src = (r & 1) ? kb : ka;
         uint64_t* sv_src = (r & 1) ? vb : va;
         uint64_t* dk = (r & 1) ? ka : kb;
@@ -700,10 +774,11 @@ __device__ void bucket_global_lsd(uint64_t* __restrict__ ka, uint64_t* __restric
                 }
             }
             __syncthreads();
-            if (tid < (uint32_t)R) run[tid] += tot[tid];
+            // the padding of a short tile ranked last in digit 255: not keys
+            if (tid < (uint32_t)R) run[tid] += tot[tid] - (tid == R - 1 ? BS_CAP - nvalid : 0u);
         }
     }
-    if (rounds & 1) {
+    if ((rounds & 1) && copy_back) {
         // an odd number of rounds ends in the scratch copy
         __syncthreads();
         for (uint32_t q = tid; q < L; q += BS_NT) {
@@ -713,136 +788,68 @@ __device__ void bucket_global_lsd(uint64_t* __restrict__ ka, uint64_t* __restric
     }
 }
 
-// Stable sort of one bucket in LDS.  Keys (and values) are in place in
-// (keys, vals) at [start[b], start[b+1]).
-template <int VB>
-__global__ __launch_bounds__(BS_NT) void k_bucket_sort(uint64_t* __restrict__ keys, uint64_t* __restrict__ vals,
-                                                       const uint32_t* __restrict__ start, uint32_t cap,
-                                                       State* __restrict__ st,
-                                                       uint32_t* __restrict__ ovf_list,
-                                                       const uint64_t* __restrict__ spl,
-                                                       uint64_t* __restrict__ scr_k,
-                                                       uint64_t* __restrict__ scr_v) {
+// LDS workspace of the bucket sort.
+struct BucketSmem {
+    uint64_t sk[BS_CAP];        // keys in slot order (also the LDS match slots, NW*R)
+    uint16_t sidx[BS_CAP];      // their positions in the source
+    uint16_t wcnt[(BS_NT / WAVE) * 256];
+    uint32_t loc[256];
+    uint32_t wsum[BS_NT / WAVE + 1];
+    uint64_t rmin[BS_NT / WAVE], rmax[BS_NT / WAVE];
+    uint32_t tot[256], run[256];
+    uint32_t sub_end[256];      // mid-size split: end of each sub-range
+    uint32_t maxrun;
+};
+
+// Minimum and maximum of v over the workgroup (every thread gets both).
+__device__ __forceinline__ void wg_minmax(uint64_t& mn, uint64_t& mx, BucketSmem& sm) {
     constexpr int NW = BS_NT / WAVE;
-    constexpr int R = 256;
-    __shared__ __align__(16) uint64_t sk[BS_CAP];   // also the LDS match slots (NW*R)
-    __shared__ uint16_t sidx[BS_CAP];
-    __shared__ uint16_t wcnt[NW * R];
-    __shared__ uint32_t loc[R];
-    __shared__ uint32_t wsum[NW + 1];
-    __shared__ uint64_t rmin[NW], rmax[NW];
-    __shared__ uint32_t tot[R], run[R];
-    uint64_t* wmask = sk;
-    const uint32_t b = blockIdx.x;
-    const uint32_t s0 = start[b], s1 = start[b + 1];
-    if (s1 <= s0 + 1) return;
-    const uint32_t L = s1 - s0;
-    const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    // Bucket b holds the keys in [spl[b-1], spl[b]) (from 0 for b = 0): a
-    // range of one key means one distinct key, already in input order.
-    {
-        const uint64_t lo = b ? spl[b - 1] : 0ull;
-        const uint64_t hi = spl[b];
-        if (b < st->reach && hi > lo && hi - lo == 1) return;
-    }
-    if (L > cap || L > BS_CAP) {
-        if (tid == 0) {
-            atomicAdd(&st->ovf_buckets, 1u);
-            atomicAdd(&st->ovf_keys, (unsigned long long)L);
-        }
-        if (L > MID_CAP) {
-            // too big for one workgroup: the host sorts it with the LSD rounds
-            if (tid == 0) {
-                const uint32_t at = atomicAdd(&st->big_buckets, 1u);
-                atomicAdd(&st->big_keys, (unsigned long long)L);
-                if (at < NB) ovf_list[at] = b;
-            }
-            return;
-        }
-        uint64_t mn = ~0ull, mx = 0;
-        for (uint32_t q = tid; q < L; q += BS_NT) {
-            const uint64_t v = keys[s0 + q];
-            mn = v < mn ? v : mn;
-            mx = v > mx ? v : mx;
-        }
-        for (int o = 32; o >= 1; o >>= 1) {
-            const uint64_t a = __shfl_xor(mn, o, WAVE), c = __shfl_xor(mx, o, WAVE);
-            mn = a < mn ? a : mn;
-            mx = c > mx ? c : mx;
-        }
-        if (lane == 0) {
-            rmin[wave] = mn;
-            rmax[wave] = mx;
-        }
-        __syncthreads();
-        if (tid == 0) {
-            for (int w = 1; w < NW; ++w) {
-                mn = rmin[w] < mn ? rmin[w] : mn;
-                mx = rmax[w] > mx ? rmax[w] : mx;
-            }
-            mn = rmin[0] < mn ? rmin[0] : mn;
-            mx = rmax[0] > mx ? rmax[0] : mx;
-            rmin[0] = mn;
-            rmax[0] = mx;
-        }
-        __syncthreads();
-        mn = rmin[0];
-        mx = rmax[0];
-        if (mn == mx) return;  // one distinct key: already in order
-        bucket_global_lsd<VB>(keys + s0, vals ? vals + s0 : nullptr, scr_k + s0, scr_v ? scr_v + s0 : nullptr,
-                              L, mn, mx, sk, sidx, wcnt, loc, wsum, tot, run);
-        return;
-    }
-    const uint32_t wb = wave * (BS_ITEMS * WAVE) + lane;
-    uint64_t k[BS_ITEMS];
-    uint32_t ix[BS_ITEMS];
-    uint64_t mn = ~0ull, mx = 0;
-#pragma unroll
-    for (int i = 0; i < BS_ITEMS; ++i) {
-        const uint32_t j = wb + i * WAVE;
-        k[i] = j < L ? keys[s0 + j] : ~0ull;
-        ix[i] = j;
-        if (j < L) {
-            mn = k[i] < mn ? k[i] : mn;
-            mx = k[i] > mx ? k[i] : mx;
-        }
-    }
+    const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int o = 32; o >= 1; o >>= 1) {
         const uint64_t a = __shfl_xor(mn, o, WAVE), c = __shfl_xor(mx, o, WAVE);
         mn = a < mn ? a : mn;
         mx = c > mx ? c : mx;
     }
+    __syncthreads();
     if (lane == 0) {
-        rmin[wave] = mn;
-        rmax[wave] = mx;
+        sm.rmin[wave] = mn;
+        sm.rmax[wave] = mx;
     }
     __syncthreads();
 #pragma unroll
     for (int w = 0; w < NW; ++w) {
-        mn = rmin[w] < mn ? rmin[w] : mn;
-        mx = rmax[w] > mx ? rmax[w] : mx;
+        mn = sm.rmin[w] < mn ? sm.rmin[w] : mn;
+        mx = sm.rmax[w] > mx ? sm.rmax[w] : mx;
     }
-    if (mn == mx) return;  // one distinct key: already in order
-    // rounds needed for the key range of this bucket
-    const uint64_t span = mx - mn;
-    const int rounds = (64 - __clzll((unsigned long long)span) + 7) / 8;
+}
+
+// Stable LDS rounds on the 8-bit digits ((k - mn) >> sh) >> 8r, r < rounds,
+// of the keys in registers (k, original positions ix); each round leaves
+// the keys in slot order in sm.sk / sm.sidx and reloads k, ix from there.
+__device__ __forceinline__ void lds_rounds(uint64_t (&k)[BS_ITEMS], uint32_t (&ix)[BS_ITEMS], uint32_t L, uint64_t mn, int sh,
+                           int rounds, BucketSmem& sm) {
+    constexpr int NW = BS_NT / WAVE;
+    constexpr int R = 256;
+    const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const uint32_t wb = wave * (BS_ITEMS * WAVE) + lane;
     const uint64_t mybit = 1ull << lane;
+    uint64_t* wmask = sm.sk;
+#pragma unroll 1
     for (int r = 0; r < rounds; ++r) {
-        const int shift = 8 * r;
+        const int shift = sh + 8 * r;
         __syncthreads();
         for (int i = tid; i < NW * R; i += BS_NT) {
-            wcnt[i] = 0;
+            sm.wcnt[i] = 0;
             wmask[i] = 0;
         }
         __syncthreads();
         uint32_t dr[BS_ITEMS];
-        uint16_t* wc = wcnt + wave * R;
+        uint16_t* wc = sm.wcnt + wave * R;
         uint64_t* wm = wmask + wave * R;
 #pragma unroll
         for (int i = 0; i < BS_ITEMS; ++i) {
-            // padding (index >= L) holds the largest key; it sorts last
-            const uint32_t d = k[i] == ~0ull && ix[i] >= L ? 255u
-                                                          : (uint32_t)(((k[i] - mn) >> shift) & 255u);
+            // padding (index >= L) takes the largest digit and comes last
+            const uint32_t d = ix[i] >= L ? 255u : (uint32_t)(((k[i] - mn) >> shift) & 255u);
             atomicOr((unsigned long long*)&wm[d], (unsigned long long)mybit);
             const uint64_t m = __hip_atomic_load(&wm[d], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
             const uint32_t lt = mbcnt(m);
@@ -855,56 +862,259 @@ __global__ __launch_bounds__(BS_NT) void k_bucket_sort(uint64_t* __restrict__ ke
             dr[i] = d | ((c + lt) << 16);
         }
         __syncthreads();
-        uint32_t tot = 0;
+        uint32_t t = 0;
         if (tid < (uint32_t)R) {
-            uint32_t s = 0;
+            uint32_t s2 = 0;
 #pragma unroll
             for (int w = 0; w < NW; ++w) {
-                const uint32_t c = wcnt[w * R + tid];
-                wcnt[w * R + tid] = (uint16_t)s;
-                s += c;
+                const uint32_t c = sm.wcnt[w * R + tid];
+                sm.wcnt[w * R + tid] = (uint16_t)s2;
+                s2 += c;
             }
-            tot = s;
+            t = s2;
         }
         uint32_t total;
-        const uint32_t ex = block_excl_scan<BS_NT>(tot, wsum, &total);
-        if (tid < (uint32_t)R) loc[tid] = ex;
+        const uint32_t ex = block_excl_scan<BS_NT>(t, sm.wsum, &total);
+        if (tid < (uint32_t)R) sm.loc[tid] = ex;
         __syncthreads();
         uint32_t slot[BS_ITEMS];
 #pragma unroll
         for (int i = 0; i < BS_ITEMS; ++i) {
             const uint32_t d = dr[i] & 0xFFFFu;
-            slot[i] = loc[d] + wcnt[wave * R + d] + (dr[i] >> 16);
+            slot[i] = sm.loc[d] + sm.wcnt[wave * R + d] + (dr[i] >> 16);
         }
         __syncthreads();  // sk aliases the match slots
 #pragma unroll
         for (int i = 0; i < BS_ITEMS; ++i) {
-            sk[slot[i]] = k[i];
-            sidx[slot[i]] = (uint16_t)ix[i];
+            sm.sk[slot[i]] = k[i];
+            sm.sidx[slot[i]] = (uint16_t)ix[i];
         }
         __syncthreads();
 #pragma unroll
         for (int i = 0; i < BS_ITEMS; ++i) {
-            k[i] = sk[wb + i * WAVE];
-            ix[i] = sidx[wb + i * WAVE];
+            k[i] = sm.sk[wb + i * WAVE];
+            ix[i] = sm.sidx[wb + i * WAVE];
         }
     }
-    // keys: the sorted order is in sk; values: gather by original position
-    uint64_t v[VB ? (BS_CAP + BS_NT - 1) / BS_NT : 1];
+}
+
+// Stable sort in LDS of L <= BS_CAP pairs from (sk_src, sv_src) to
+// (kd, vd) (the two may be the same place).  With full = false the keys are
+// ordered by their top 16 significant bits above the minimum (at most two
+// 8-bit LDS rounds); keys still tied on those bits sit in short runs in input
+// order and are finished by an insertion sort per run.  If some run is long
+// (keys crowded into a sliver of the range) nothing is written and false is
+// returned: the caller ranks that bucket on every bit (full = true) instead.
+template <int VB>
+__device__ __forceinline__ bool lds_sort(const uint64_t* sk_src, const uint64_t* sv_src, uint64_t* kd,
+                                         uint64_t* vd, uint32_t L, BucketSmem& sm, bool full) {
+    const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const uint32_t wb = wave * (BS_ITEMS * WAVE) + lane;
+    uint64_t k[BS_ITEMS];
+    uint32_t ix[BS_ITEMS];
+    uint64_t mn = ~0ull, mx = 0;
+#pragma unroll
+    for (int i = 0; i < BS_ITEMS; ++i) {
+        const uint32_t j = wb + i * WAVE;
+        k[i] = j < L ? sk_src[j] : ~0ull;
+        ix[i] = j;
+        if (j < L) {
+            mn = k[i] < mn ? k[i] : mn;
+            mx = k[i] > mx ? k[i] : mx;
+        }
+    }
+    wg_minmax(mn, mx, sm);
+    if (mn == mx) {  // one distinct key: already in order
+        if (kd != sk_src)
+            for (uint32_t j = tid; j < L; j += BS_NT) {
+                kd[j] = sk_src[j];
+                if constexpr (VB != 0) vd[j] = sv_src[j];
+            }
+        __syncthreads();
+        return true;
+    }
+    const int sig = 64 - __clzll((unsigned long long)(mx - mn));  // significant bits of the range
+    const int sh = (!full && sig > 16) ? sig - 16 : 0;
+    lds_rounds(k, ix, L, mn, sh, (sig - sh + 7) / 8, sm);
+    if (sh > 0) {
+        // runs of keys equal on the ranked bits: the longest decides
+        if (tid == 0) sm.maxrun = 0;
+        __syncthreads();
+        for (uint32_t j = tid; j < L; j += BS_NT) {
+            const uint64_t c = (sm.sk[j] - mn) >> sh;
+            if (j > 0 && ((sm.sk[j - 1] - mn) >> sh) == c) continue;
+            uint32_t e = j + 1;
+            while (e < L && ((sm.sk[e] - mn) >> sh) == c) ++e;
+            if (e - j > 1) atomicMax(&sm.maxrun, e - j);
+        }
+        __syncthreads();
+        const uint32_t longest = sm.maxrun;
+        if (longest > 64) {
+            __syncthreads();
+            return false;
+        }
+        if (longest > 1) {
+            for (uint32_t j = tid; j < L; j += BS_NT) {
+                const uint64_t c = (sm.sk[j] - mn) >> sh;
+                if (j > 0 && ((sm.sk[j - 1] - mn) >> sh) == c) continue;
+                uint32_t e = j + 1;
+                while (e < L && ((sm.sk[e] - mn) >> sh) == c) ++e;
+                // stable insertion sort of sk[j, e) by key; sidx follows
+                for (uint32_t a = j + 1; a < e; ++a) {
+                    const uint64_t kv = sm.sk[a];
+                    const uint16_t iv = sm.sidx[a];
+                    uint32_t q = a;
+                    while (q > j && sm.sk[q - 1] > kv) {
+                        sm.sk[q] = sm.sk[q - 1];
+                        sm.sidx[q] = sm.sidx[q - 1];
+                        --q;
+                    }
+                    sm.sk[q] = kv;
+                    sm.sidx[q] = iv;
+                }
+            }
+        }
+        __syncthreads();
+    }
+    // keys in sk; values gathered by original position, then both written
+    constexpr int PQ = (BS_CAP + BS_NT - 1) / BS_NT;
+    uint64_t v[VB ? PQ : 1];
     if constexpr (VB != 0) {
 #pragma unroll
-        for (int q = 0; q < (int)((BS_CAP + BS_NT - 1) / BS_NT); ++q) {
+        for (int q = 0; q < PQ; ++q) {
             const uint32_t j = q * BS_NT + tid;
-            if (j < L) v[q] = vals[s0 + sidx[j]];
+            if (j < L) v[q] = sv_src[sm.sidx[j]];
         }
     }
     __syncthreads();
-    for (uint32_t j = tid; j < L; j += BS_NT) keys[s0 + j] = sk[j];
+    for (uint32_t j = tid; j < L; j += BS_NT) kd[j] = sm.sk[j];
     if constexpr (VB != 0) {
 #pragma unroll
-        for (int q = 0; q < (int)((BS_CAP + BS_NT - 1) / BS_NT); ++q) {
+        for (int q = 0; q < PQ; ++q) {
             const uint32_t j = q * BS_NT + tid;
-            if (j < L) vals[s0 + j] = v[q];
+            if (j < L) vd[j] = v[q];
+        }
+    }
+    __syncthreads();
+    return true;
+}
+
+// Stable sort of one bucket of up to BS_CAP pairs (and the caller's cap) in
+// LDS; keys (and values) are in place in (keys, vals) at [start[b],
+// start[b+1]).  A larger bucket is listed: up to MID_CAP for k_bucket_mid,
+// beyond that for the host.
+template <int VB>
+__global__ __launch_bounds__(BS_NT) void k_bucket_sort(uint64_t* __restrict__ keys, uint64_t* __restrict__ vals,
+                                                       const uint32_t* __restrict__ start, uint32_t cap,
+                                                       State* __restrict__ st,
+                                                       uint32_t* __restrict__ ovf_list,
+                                                       uint32_t* __restrict__ mid_list,
+                                                       const uint64_t* __restrict__ spl) {
+    __shared__ BucketSmem sm;
+    const uint32_t b = blockIdx.x;
+    const uint32_t s0 = start[b], s1 = start[b + 1];
+    if (s1 <= s0 + 1) return;
+    const uint32_t L = s1 - s0;
+    // Bucket b holds the keys in [spl[b-1], spl[b]) (from 0 for b = 0): a
+    // range of one key means one distinct key, already in input order.
+    {
+        const uint64_t lo = b ? spl[b - 1] : 0ull;
+        const uint64_t hi = spl[b];
+        if (b < st->reach && hi > lo && hi - lo == 1) return;
+    }
+    if (L <= cap && L <= BS_CAP) {
+        uint64_t* kb = keys + s0;
+        uint64_t* vbk = VB ? vals + s0 : nullptr;
+        if (!lds_sort<VB>(kb, vbk, kb, vbk, L, sm, false) && threadIdx.x == 0) {
+            // crowded keys: ranked on every bit by k_bucket_mid
+            const uint32_t at = atomicAdd(&st->mid_buckets, 1u);
+            if (at < NB) mid_list[at] = b;
+        }
+        return;
+    }
+    if (threadIdx.x == 0) {
+        atomicAdd(&st->ovf_buckets, 1u);
+        atomicAdd(&st->ovf_keys, (unsigned long long)L);
+        if (L > MID_CAP) {
+            // too big for one workgroup: the host sorts it with the LSD rounds
+            const uint32_t at = atomicAdd(&st->big_buckets, 1u);
+            atomicAdd(&st->big_keys, (unsigned long long)L);
+            if (at < NB) ovf_list[at] = b;
+        } else {
+            const uint32_t at = atomicAdd(&st->mid_buckets, 1u);
+            if (at < NB) mid_list[at] = b;
+        }
+    }
+}
+
+// The listed buckets, one workgroup each at a time: crowded ones within the
+// LDS capacity are ranked on every bit; mid-size ones (above the capacity,
+// up to MID_CAP) are split first.  One stable round through the scratch arrays
+// splits a bucket into 2^t sub-ranges of equal key width (the keys of one
+// bucket spread almost evenly over its range), about half an LDS load each;
+// each sub-range is then sorted in LDS back into place, and a sub-range
+// still too large takes the global-memory rounds.
+template <int VB>
+__global__ __launch_bounds__(BS_NT) void k_bucket_mid(uint64_t* __restrict__ keys, uint64_t* __restrict__ vals,
+                                                      const uint32_t* __restrict__ start,
+                                                      const State* __restrict__ st,
+                                                      const uint32_t* __restrict__ mid_list,
+                                                      uint64_t* __restrict__ scr_k, uint64_t* __restrict__ scr_v) {
+    __shared__ BucketSmem sm;
+    const uint32_t tid = threadIdx.x;
+    const uint32_t count = st->mid_buckets < NB ? st->mid_buckets : NB;
+    for (uint32_t w = blockIdx.x; w < count; w += gridDim.x) {
+        const uint32_t b = mid_list[w];
+        const uint32_t s0 = start[b], L = start[b + 1] - s0;
+        uint64_t* kb = keys + s0;
+        uint64_t* vbk = VB ? vals + s0 : nullptr;
+        uint64_t* sck = scr_k + s0;
+        uint64_t* scv = VB ? scr_v + s0 : nullptr;
+        if (L <= BS_CAP) {  // a crowded bucket from k_bucket_sort
+            lds_sort<VB>(kb, vbk, kb, vbk, L, sm, true);
+            continue;
+        }
+        uint64_t mn = ~0ull, mx = 0;
+        for (uint32_t q = tid; q < L; q += BS_NT) {
+            const uint64_t v = kb[q];
+            mn = v < mn ? v : mn;
+            mx = v > mx ? v : mx;
+        }
+        wg_minmax(mn, mx, sm);
+        if (mn == mx) continue;  // one distinct key: already in order
+        int t = 1;
+        while (t < 8 && ((uint64_t)BS_CAP << (t - 1)) < 2ull * L) ++t;
+        const int sig = 64 - __clzll((unsigned long long)(mx - mn));
+        const int sh2 = sig > t ? sig - t : 0;
+        bucket_global_lsd<VB>(kb, vbk, sck, scv, L, mn, mx, sm.sk, sm.sidx, sm.wcnt, sm.loc, sm.wsum, sm.tot,
+                              sm.run, sh2, 1, false);
+        __syncthreads();
+        if (tid < 256u) sm.sub_end[tid] = sm.run[tid];  // ends of the sub-ranges
+        __syncthreads();
+        const uint32_t nsub = 1u << t;
+        for (uint32_t d = 0; d < nsub; ++d) {
+            const uint32_t a = __builtin_amdgcn_readfirstlane(d ? sm.sub_end[d - 1] : 0u);
+            const uint32_t c = __builtin_amdgcn_readfirstlane(sm.sub_end[d] - a);
+            if (c == 0) continue;
+            if (c <= BS_CAP) {
+                if (!lds_sort<VB>(sck + a, VB ? scv + a : nullptr, kb + a, VB ? vbk + a : nullptr, c, sm, false))
+                    lds_sort<VB>(sck + a, VB ? scv + a : nullptr, kb + a, VB ? vbk + a : nullptr, c, sm, true);
+                continue;
+            }
+            // crowded sub-range: back into place, then the global-memory rounds
+            uint64_t smn = ~0ull, smx = 0;
+            for (uint32_t q = tid; q < c; q += BS_NT) {
+                const uint64_t v = sck[a + q];
+                kb[a + q] = v;
+                if constexpr (VB != 0) vbk[a + q] = scv[a + q];
+                smn = v < smn ? v : smn;
+                smx = v > smx ? v : smx;
+            }
+            wg_minmax(smn, smx, sm);
+            if (smn != smx)
+                bucket_global_lsd<VB>(kb + a, VB ? vbk + a : nullptr, sck + a, VB ? scv + a : nullptr, c, smn,
+                                      smx, sm.sk, sm.sidx, sm.wcnt, sm.loc, sm.wsum, sm.tot, sm.run);
+            __syncthreads();
         }
     }
 }
@@ -939,13 +1149,13 @@ LearnOpts g_opts = {32, 1e-2f, 1, (int32_t)BS_CAP, -1, 0.25, 64, 64};
 
 struct LearnLayout {
     size_t off_state, off_sample, off_sorted, off_sample_ws, off_xs, off_ts, off_params, off_gbuf,
-        off_spl, off_knot, off_start, off_ovf, off_bid0, off_big, total;
+        off_spl, off_knot, off_start, off_ovf, off_mid, off_bid0, off_big, total;
     LsdPlan sample_plan, pass_plan, fb_plan;
 };
 
 bool learn_layout(size_t n, int vb, LearnLayout* L) {
     LearnLayout q;
-    if (!lsd_plan(M, 8, 0, 8, &q.sample_plan)) return false;
+    if (!lsd_plan(MS, 8, 0, 8, &q.sample_plan)) return false;
     if (!lsd_plan(n, 2, 8, 8, &q.pass_plan, vb)) return false;
     q.sample_plan.kid_hist = q.sample_plan.kid_scatter = KID_LEARN_SAMPLE;
     q.pass_plan.kid_hist = q.pass_plan.kid_scatter = KID_LEARN_PASS;
@@ -957,8 +1167,8 @@ bool learn_layout(size_t n, int vb, LearnLayout* L) {
         return o;
     };
     q.off_state = take(sizeof(State));
-    q.off_sample = take(8 * (size_t)M);
-    q.off_sorted = take(8 * (size_t)M);
+    q.off_sample = take(8 * (size_t)MS);
+    q.off_sorted = take(8 * (size_t)MS);
     q.off_sample_ws = take(q.sample_plan.total);
     q.off_xs = take(4 * (size_t)M);
     q.off_ts = take(4 * (size_t)M);
@@ -968,6 +1178,7 @@ bool learn_layout(size_t n, int vb, LearnLayout* L) {
     q.off_knot = take(4 * (size_t)(KNOTS + 1));
     q.off_start = take(4 * ((size_t)NB + 1));
     q.off_ovf = take(4 * (size_t)NB);
+    q.off_mid = take(4 * (size_t)NB);
     q.off_bid0 = take(2 * n);
     // the rounds' workspace and the final bucket ids, or the fallback's
     // workspace (never live at the same time)
@@ -1016,6 +1227,7 @@ rs_status learned_run(const void* kin, void* kout, const void* vin, void* vout, 
     float* knot = reinterpret_cast<float*>(ws + L.off_knot);
     uint32_t* start = reinterpret_cast<uint32_t*>(ws + L.off_start);
     uint32_t* ovf = reinterpret_cast<uint32_t*>(ws + L.off_ovf);
+    uint32_t* mid = reinterpret_cast<uint32_t*>(ws + L.off_mid);
     uint16_t* bid0 = reinterpret_cast<uint16_t*>(ws + L.off_bid0);
     unsigned char* big = ws + L.off_big;
     uint16_t* bid1 = reinterpret_cast<uint16_t*>(big + align_up(L.pass_plan.total));
@@ -1027,7 +1239,7 @@ rs_status learned_run(const void* kin, void* kout, const void* vin, void* vout, 
     if ((rc = fill_u32(st, sizeof(State) / 4, 0u, s)) != RS_OK) return rc;
     if ((rc = fill_u32(gbuf, GBUF * 3, 0u, s)) != RS_OK) return rc;
     prof(s, KID_LEARN_SAMPLE, 0);
-    hipLaunchKernelGGL(k_sample, dim3(M / 256), dim3(256), 0, s, (const uint64_t*)kin, (uint64_t)n,
+    hipLaunchKernelGGL(k_sample, dim3(MS / 256), dim3(256), 0, s, (const uint64_t*)kin, (uint64_t)n,
                        (uint64_t)0x1A7E5EEDull, sample);
     prof(s, KID_LEARN_SAMPLE, 1);
     if ((rc = launch_status()) != RS_OK) return rc;
@@ -1061,7 +1273,7 @@ rs_status learned_run(const void* kin, void* kout, const void* vin, void* vout, 
 
     // 3. calibration knots, splitters
     prof(s, KID_LEARN_SPLIT, 0);
-    hipLaunchKernelGGL(k_calibrate, dim3(1), dim3(256), 0, s, params, xs, knot, opt.use_network);
+    hipLaunchKernelGGL(k_calibrate, dim3(1), dim3(256), 0, s, params, sorted, st, knot, opt.use_network);
     hipLaunchKernelGGL(k_splitters, dim3(NB / 256), dim3(256), 0, s, params, st, knot, spl, opt.use_network);
     hipLaunchKernelGGL(k_split_fix, dim3(1), dim3(1024), 0, s, spl);
     prof(s, KID_LEARN_SPLIT, 1);
@@ -1094,12 +1306,17 @@ rs_status learned_run(const void* kin, void* kout, const void* vin, void* vout, 
         // arrays, free again once the bucket ids have been sorted
         uint64_t* scr_k = reinterpret_cast<uint64_t*>(big + L.pass_plan.off_tv);
         uint64_t* scr_v = vb ? reinterpret_cast<uint64_t*>(big + L.pass_plan.off_tv2) : nullptr;
-        if (vb)
+        if (vb) {
             hipLaunchKernelGGL(k_bucket_sort<8>, dim3(NB), dim3(BS_NT), 0, s, (uint64_t*)kout, (uint64_t*)vout,
-                               start, cap, st, ovf, spl, scr_k, scr_v);
-        else
+                               start, cap, st, ovf, mid, spl);
+            hipLaunchKernelGGL(k_bucket_mid<8>, dim3(MID_GRID), dim3(BS_NT), 0, s, (uint64_t*)kout,
+                               (uint64_t*)vout, start, st, mid, scr_k, scr_v);
+        } else {
             hipLaunchKernelGGL(k_bucket_sort<0>, dim3(NB), dim3(BS_NT), 0, s, (uint64_t*)kout, (uint64_t*)nullptr,
-                               start, cap, st, ovf, spl, scr_k, scr_v);
+                               start, cap, st, ovf, mid, spl);
+            hipLaunchKernelGGL(k_bucket_mid<0>, dim3(MID_GRID), dim3(BS_NT), 0, s, (uint64_t*)kout,
+                               (uint64_t*)nullptr, start, st, mid, scr_k, scr_v);
+        }
         prof(s, KID_LEARN_BUCKET, 1);
         if ((rc = launch_status()) != RS_OK) return rc;
     }

