@@ -38,6 +38,7 @@ enum KernelId {
     KID_WIDE_COUNT,
     KID_WIDE_SCATTER,
     KID_LEARN_PASS,
+    KID_LEARN_MID,
     KID_COUNT_
 };
 extern bool g_prof_on;

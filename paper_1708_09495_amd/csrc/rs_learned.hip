@@ -51,7 +51,7 @@ constexpr int GBUF = NP + 1;           // gradient buffer: parameters + loss
 constexpr uint32_t MID_CAP = 1u << 20; // largest bucket sorted by one workgroup
 constexpr uint32_t MID_GRID = 1024;    // workgroups sorting the mid-size buckets
 constexpr int KNOTS = 1024;            // calibration intervals of the network output
-constexpr int QK = 64;                 // key-quantile intervals of the piecewise-linear feature
+constexpr int QK = 4096;               // key-quantile intervals of the piecewise-linear feature
 
 struct State {
     uint64_t kmin, kmax;
@@ -474,7 +474,8 @@ __global__ __launch_bounds__(256) void k_calibrate(const float* __restrict__ par
     __shared__ float part[256];
     __shared__ State S;
     for (int p = threadIdx.x; p < NP; p += blockDim.x) raw[p] = params[p];
-    if (threadIdx.x == 0) S = *st;
+    for (uint32_t i = threadIdx.x; i < sizeof(State) / 8; i += blockDim.x)
+        reinterpret_cast<uint64_t*>(&S)[i] = reinterpret_cast<const uint64_t*>(st)[i];
     __syncthreads();
     mlp_derive(raw, W, false);
     __syncthreads();
@@ -522,7 +523,8 @@ __global__ __launch_bounds__(256) void k_splitters(const float* __restrict__ par
     __shared__ State S;
     for (int p = threadIdx.x; p < NP; p += blockDim.x) raw[p] = params[p];
     for (int g = threadIdx.x; g <= KNOTS; g += blockDim.x) knot[g] = knot_g[g];
-    if (threadIdx.x == 0) S = *st;
+    for (uint32_t i = threadIdx.x; i < sizeof(State) / 8; i += blockDim.x)
+        reinterpret_cast<uint64_t*>(&S)[i] = reinterpret_cast<const uint64_t*>(st)[i];
     __syncthreads();
     mlp_derive(raw, W, false);
     __syncthreads();
@@ -578,11 +580,19 @@ __global__ __launch_bounds__(1024) void k_split_fix(uint64_t* __restrict__ spl) 
 
 // ---- 4. bucket ids --------------------------------------------------------------------
 
+// The last splitter of every group of 16, packed (the assignment kernel's
+// LDS table, read contiguously by every workgroup).
+__global__ void k_top(const uint64_t* __restrict__ spl, uint64_t* __restrict__ topg) {
+    const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b < TOP) topg[b] = spl[16u * b + 15u];
+}
+
 __global__ __launch_bounds__(AS_NT) void k_assign(const uint64_t* __restrict__ keys, uint64_t n,
                                                   const uint64_t* __restrict__ spl,
+                                                  const uint64_t* __restrict__ topg,
                                                   const State* __restrict__ st, uint16_t* __restrict__ bid) {
     __shared__ uint64_t top[TOP];  // top[b] = spl[16 b + 15]
-    for (int b = threadIdx.x; b < TOP; b += AS_NT) top[b] = spl[16 * b + 15];
+    for (int b = threadIdx.x; b < TOP; b += AS_NT) top[b] = topg[b];
     const uint32_t reach = st->reach;
     __syncthreads();
     const uint64_t per_block = (uint64_t)AS_NT * AS_KEYS;
@@ -1149,7 +1159,7 @@ LearnOpts g_opts = {32, 1e-2f, 1, (int32_t)BS_CAP, -1, 0.25, 64, 64};
 
 struct LearnLayout {
     size_t off_state, off_sample, off_sorted, off_sample_ws, off_xs, off_ts, off_params, off_gbuf,
-        off_spl, off_knot, off_start, off_ovf, off_mid, off_bid0, off_big, total;
+        off_spl, off_top, off_knot, off_start, off_ovf, off_mid, off_bid0, off_big, total;
     LsdPlan sample_plan, pass_plan, fb_plan;
 };
 
@@ -1158,7 +1168,7 @@ bool learn_layout(size_t n, int vb, LearnLayout* L) {
     if (!lsd_plan(MS, 8, 0, 8, &q.sample_plan)) return false;
     if (!lsd_plan(n, 2, 8, 8, &q.pass_plan, vb)) return false;
     q.sample_plan.kid_hist = q.sample_plan.kid_scatter = KID_LEARN_SAMPLE;
-    q.pass_plan.kid_hist = q.pass_plan.kid_scatter = KID_LEARN_PASS;
+    q.pass_plan.kid_scatter = KID_LEARN_PASS;
     if (!lsd_plan(n, 8, vb, 8, &q.fb_plan)) return false;
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -1175,6 +1185,7 @@ bool learn_layout(size_t n, int vb, LearnLayout* L) {
     q.off_params = take(4 * (size_t)NP);
     q.off_gbuf = take(4 * (size_t)GBUF * 3);
     q.off_spl = take(8 * (size_t)NB);
+    q.off_top = take(8 * (size_t)TOP);
     q.off_knot = take(4 * (size_t)(KNOTS + 1));
     q.off_start = take(4 * ((size_t)NB + 1));
     q.off_ovf = take(4 * (size_t)NB);
@@ -1224,6 +1235,7 @@ rs_status learned_run(const void* kin, void* kout, const void* vin, void* vout, 
     float* params = reinterpret_cast<float*>(ws + L.off_params);
     float* gbuf = reinterpret_cast<float*>(ws + L.off_gbuf);
     uint64_t* spl = reinterpret_cast<uint64_t*>(ws + L.off_spl);
+    uint64_t* topg = reinterpret_cast<uint64_t*>(ws + L.off_top);
     float* knot = reinterpret_cast<float*>(ws + L.off_knot);
     uint32_t* start = reinterpret_cast<uint32_t*>(ws + L.off_start);
     uint32_t* ovf = reinterpret_cast<uint32_t*>(ws + L.off_ovf);
@@ -1276,16 +1288,17 @@ rs_status learned_run(const void* kin, void* kout, const void* vin, void* vout, 
     hipLaunchKernelGGL(k_calibrate, dim3(1), dim3(256), 0, s, params, sorted, st, knot, opt.use_network);
     hipLaunchKernelGGL(k_splitters, dim3(NB / 256), dim3(256), 0, s, params, st, knot, spl, opt.use_network);
     hipLaunchKernelGGL(k_split_fix, dim3(1), dim3(1024), 0, s, spl);
+    hipLaunchKernelGGL(k_top, dim3(TOP / 256), dim3(256), 0, s, spl, topg);
     prof(s, KID_LEARN_SPLIT, 1);
     if ((rc = launch_status()) != RS_OK) return rc;
 
     // 4. bucket ids
     {
         uint64_t g = (n + AS_NT * AS_KEYS - 1) / (AS_NT * AS_KEYS);
-        if (g > 8192) g = 8192;
+        if (g > 2048) g = 2048;  // each workgroup loads the 32 KiB table once
         prof(s, KID_LEARN_ASSIGN, 0);
         hipLaunchKernelGGL(k_assign, dim3((unsigned)g), dim3(AS_NT), 0, s, (const uint64_t*)kin, (uint64_t)n,
-                           spl, st, bid0);
+                           spl, topg, st, bid0);
         prof(s, KID_LEARN_ASSIGN, 1);
         if ((rc = launch_status()) != RS_OK) return rc;
     }
@@ -1306,18 +1319,21 @@ rs_status learned_run(const void* kin, void* kout, const void* vin, void* vout, 
         // arrays, free again once the bucket ids have been sorted
         uint64_t* scr_k = reinterpret_cast<uint64_t*>(big + L.pass_plan.off_tv);
         uint64_t* scr_v = vb ? reinterpret_cast<uint64_t*>(big + L.pass_plan.off_tv2) : nullptr;
-        if (vb) {
-            hipLaunchKernelGGL(k_bucket_sort<8>, dim3(NB), dim3(BS_NT), 0, s, (uint64_t*)kout, (uint64_t*)vout,
-                               start, cap, st, ovf, mid, spl);
+        if (vb)
+            hipLaunchKernelGGL(k_bucket_sort<8>, dim3(NB), dim3(BS_NT), 0, s, (uint64_t*)kout,
+                               (uint64_t*)vout, start, cap, st, ovf, mid, spl);
+        else
+            hipLaunchKernelGGL(k_bucket_sort<0>, dim3(NB), dim3(BS_NT), 0, s, (uint64_t*)kout,
+                               (uint64_t*)nullptr, start, cap, st, ovf, mid, spl);
+        prof(s, KID_LEARN_BUCKET, 1);
+        prof(s, KID_LEARN_MID, 0);
+        if (vb)
             hipLaunchKernelGGL(k_bucket_mid<8>, dim3(MID_GRID), dim3(BS_NT), 0, s, (uint64_t*)kout,
                                (uint64_t*)vout, start, st, mid, scr_k, scr_v);
-        } else {
-            hipLaunchKernelGGL(k_bucket_sort<0>, dim3(NB), dim3(BS_NT), 0, s, (uint64_t*)kout, (uint64_t*)nullptr,
-                               start, cap, st, ovf, mid, spl);
+        else
             hipLaunchKernelGGL(k_bucket_mid<0>, dim3(MID_GRID), dim3(BS_NT), 0, s, (uint64_t*)kout,
                                (uint64_t*)nullptr, start, st, mid, scr_k, scr_v);
-        }
-        prof(s, KID_LEARN_BUCKET, 1);
+        prof(s, KID_LEARN_MID, 1);
         if ((rc = launch_status()) != RS_OK) return rc;
     }
     State hs;

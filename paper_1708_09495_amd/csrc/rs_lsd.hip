@@ -448,9 +448,9 @@ hipError_t launch_pass_k16(const LsdPlan& p, const void* src, void* dst, const v
                            void* vdst, int pass, unsigned char* ws, hipStream_t st,
                            const void* v2src, void* v2dst) {
     if (p.lb64)
-        return launch_pass<uint16_t, 8, 8, 8, uint64_t, int64_t, VB2>(p, src, dst, vsrc, vdst, pass, ws,
+        return launch_pass<uint16_t, 8, 8, 16, uint64_t, int64_t, VB2>(p, src, dst, vsrc, vdst, pass, ws,
                                                                         st, v2src, v2dst);
-    return launch_pass<uint16_t, 8, 8, 8, uint32_t, int32_t, VB2>(p, src, dst, vsrc, vdst, pass, ws, st,
+    return launch_pass<uint16_t, 8, 8, 16, uint32_t, int32_t, VB2>(p, src, dst, vsrc, vdst, pass, ws, st,
                                                                     v2src, v2dst);
 }
 
@@ -496,7 +496,7 @@ bool lsd_plan(size_t n, int kb, int vb, int bits, LsdPlan* p, int vb2) {
     q.passes = (8 * kb + bits - 1) / bits;
     q.R = 1 << bits;
     q.vb2 = vb2;
-    q.tile = NT * (kb == 2 ? 8 : lsd_items(kb, vb));
+    q.tile = NT * (kb == 2 ? 16 : lsd_items(kb, vb));
     q.tiles = n ? (n + q.tile - 1) / q.tile : 0;
     q.lb64 = n >= (1ull << 30);
     q.lb_words = q.tiles * (size_t)q.R;
