@@ -147,11 +147,16 @@ __global__ __launch_bounds__(NT) void k_onesweep(
     constexpr size_t CNTB = (size_t)NW * RMAX * sizeof(uint16_t);
     constexpr size_t MSKB = (size_t)NW * RLO * sizeof(uint64_t);
     constexpr size_t RANKB = CNTB + MSKB;
-    constexpr size_t UB1 = KEYB > VALB ? KEYB : VALB;
+    // values get an LDS buffer of their own (and are placed before the
+    // look-back) when keys and values fit in 64 KiB together; otherwise
+    // they reuse the key buffer after the keys are written
+    constexpr bool SEPV = VB != 0 && VB2 == 0 && MAXB <= 8 && KEYB + VALB <= 65536;
+    constexpr size_t UB1 = (KEYB > VALB || SEPV) ? KEYB : VALB;
     constexpr size_t UB = UB1 > RANKB ? UB1 : RANKB;
     static_assert(T < 65536, "wave counters are 16-bit");
 
     __shared__ __align__(16) unsigned char u_raw[UB];
+    __shared__ __align__(16) unsigned char v_raw[SEPV ? VALB : 16];
     __shared__ OFF goff[RMAX];        // global destination of slot 0 of each digit
     __shared__ uint32_t tot[RMAX];    // this tile's count per digit
     __shared__ uint32_t loc[RMAX];    // first LDS slot of each digit
@@ -161,7 +166,7 @@ __global__ __launch_bounds__(NT) void k_onesweep(
     uint64_t* wmask = reinterpret_cast<uint64_t*>(u_raw);          // [NW][RLO]
     uint16_t* wcnt = reinterpret_cast<uint16_t*>(u_raw + MSKB);    // [NW][R]
     K* skeys = reinterpret_cast<K*>(u_raw);
-    V* svals = reinterpret_cast<V*>(u_raw);
+    V* svals = reinterpret_cast<V*>(SEPV ? v_raw : u_raw);
     const V* vin = reinterpret_cast<const V*>(vin_);
     V* vout = reinterpret_cast<V*>(vout_);
 
@@ -270,7 +275,26 @@ __global__ __launch_bounds__(NT) void k_onesweep(
         }
     }
 
-    // ---- global position of each digit's first key in this tile
+    __syncthreads();  // per-wave slot bases complete
+
+    // ---- LDS slot of every key, then the reorder
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+        const uint32_t d = dr[i] & 0xFFFFu;
+        dr[i] = wcnt[wave * R + d] + (dr[i] >> 16);
+    }
+    __syncthreads();  // the counters share LDS with the key buffer
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) skeys[dr[i]] = k[i];
+    if constexpr (SEPV) {
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) svals[dr[i]] = v[i];
+    }
+    __syncthreads();
+
+    // ---- global position of each digit's first key in this tile.  Taken
+    //      after the LDS reorder: by then the tiles before this one have
+    //      had longer to publish, so the look-back resolves in fewer steps.
     if (tile == 0) {
         // Tile 0 starts the chain: its exclusive prefix is the exclusive
         // scan of the round's global histogram.
@@ -339,16 +363,6 @@ __global__ __launch_bounds__(NT) void k_onesweep(
     }
     __syncthreads();
 
-    // ---- LDS slot of every key, then the reorder
-#pragma unroll
-    for (int i = 0; i < ITEMS; ++i) {
-        const uint32_t d = dr[i] & 0xFFFFu;
-        dr[i] = wcnt[wave * R + d] + (dr[i] >> 16);
-    }
-    __syncthreads();  // the counters share LDS with the key buffer
-#pragma unroll
-    for (int i = 0; i < ITEMS; ++i) skeys[dr[i]] = k[i];
-    __syncthreads();
 
     // ---- write out: consecutive slots of one digit go to consecutive
     //      addresses, so each digit's run is a coalesced burst.  The
@@ -374,10 +388,12 @@ __global__ __launch_bounds__(NT) void k_onesweep(
         }
     }
     if constexpr (VB != 0) {
-        __syncthreads();
+        if constexpr (!SEPV) {
+            __syncthreads();
 #pragma unroll
-        for (int i = 0; i < ITEMS; ++i) svals[dr[i]] = v[i];
-        __syncthreads();
+            for (int i = 0; i < ITEMS; ++i) svals[dr[i]] = v[i];
+            __syncthreads();
+        }
 #pragma unroll
         for (int q = 0; q < ITEMS; ++q) {
             const uint32_t j = q * NT + tid;
