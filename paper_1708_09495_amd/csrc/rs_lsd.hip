@@ -76,31 +76,38 @@ __global__ __launch_bounds__(HIST_NT) void k_hist(const K* __restrict__ keys, ui
     uint64_t i = (uint64_t)blockIdx.x * HIST_NT + threadIdx.x;
     // Counting: when every lane of the wave holds the same digit (a common
     // case for the high digits of skewed keys) one lane adds 64 instead of
-    // 64 lanes colliding on one counter.
-    auto count = [&](uint32_t slot) {
-        const uint32_t first = __builtin_amdgcn_readfirstlane(slot);
-        if (ballot(slot != first) == 0) {
-            if ((threadIdx.x & 63) == 0) atomicAdd(&h[first], 64u);
-        } else {
-            atomicAdd(&h[slot], 1u);
+    // 64 lanes colliding on one counter.  The test costs instructions, so a
+    // round whose digits were not wave-uniform drops out of it until the
+    // next re-test (every 16 steps); the counts are exact either way.
+    uint32_t fast = (1u << passes) - 1;  // rounds tested for uniform digits (wave-uniform)
+    auto count = [&](uint32_t slot, int p) {
+        if (fast & (1u << p)) {
+            const uint32_t first = __builtin_amdgcn_readfirstlane(slot);
+            if (ballot(slot != first) == 0) {
+                if ((threadIdx.x & 63) == 0) atomicAdd(&h[first], 64u);
+                return;
+            }
+            fast &= ~(1u << p);
         }
+        atomicAdd(&h[slot], 1u);
     };
     // four independent loads in flight per thread; whole waves only, so the
     // uniform-digit test sees 64 keys
     const uint64_t nfull = n - n % ((uint64_t)HIST_NT * gridDim.x);
-    for (; i + 3 * stride < nfull; i += 4 * stride) {
+    for (uint32_t step = 1; i + 3 * stride < nfull; i += 4 * stride, ++step) {
         K k0 = keys[i], k1 = keys[i + stride], k2 = keys[i + 2 * stride], k3 = keys[i + 3 * stride];
         for (int p = 0; p < passes; ++p) {
             const int s = p * bits;
-            count(p * R + ((uint32_t)(k0 >> s) & mask));
-            count(p * R + ((uint32_t)(k1 >> s) & mask));
-            count(p * R + ((uint32_t)(k2 >> s) & mask));
-            count(p * R + ((uint32_t)(k3 >> s) & mask));
+            count(p * R + ((uint32_t)(k0 >> s) & mask), p);
+            count(p * R + ((uint32_t)(k1 >> s) & mask), p);
+            count(p * R + ((uint32_t)(k2 >> s) & mask), p);
+            count(p * R + ((uint32_t)(k3 >> s) & mask), p);
         }
+        if ((step & 15) == 0) fast = (1u << passes) - 1;
     }
     for (; i < nfull; i += stride) {
         K k0 = keys[i];
-        for (int p = 0; p < passes; ++p) count(p * R + ((uint32_t)(k0 >> (p * bits)) & mask));
+        for (int p = 0; p < passes; ++p) count(p * R + ((uint32_t)(k0 >> (p * bits)) & mask), p);
     }
     for (; i < n; i += stride) {
         K k0 = keys[i];
@@ -549,7 +556,7 @@ rs_status lsd_run(const LsdPlan& p, const void* kin, void* kout, const void* vin
         size_t g = (p.n + HIST_NT * 16 - 1) / (HIST_NT * 16);
         size_t gz = (lb_u32 + HIST_NT * 16 - 1) / (HIST_NT * 16);
         if (gz > g) g = gz;
-        if (g > 2048) g = 2048;
+        if (g > 4096) g = 4096;
         if (g < 1) g = 1;
         const size_t shm = sizeof(uint32_t) * (size_t)p.passes * p.R;
         uint32_t* gh = reinterpret_cast<uint32_t*>(ws + p.off_hist);
