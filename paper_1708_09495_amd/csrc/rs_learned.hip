@@ -858,7 +858,12 @@ __device__ __forceinline__ void lds_rounds(uint64_t (&k)[BS_ITEMS], uint32_t (&i
         uint64_t* wm = wmask + wave * R;
 #pragma unroll
         for (int i = 0; i < BS_ITEMS; ++i) {
+            // an item past the bucket in every lane of the wave is skipped;
             // padding (index >= L) takes the largest digit and comes last
+            if (wave * (BS_ITEMS * WAVE) + i * WAVE >= L) {
+                dr[i] = 0;
+                continue;
+            }
             const uint32_t d = ix[i] >= L ? 255u : (uint32_t)(((k[i] - mn) >> shift) & 255u);
             atomicOr((unsigned long long*)&wm[d], (unsigned long long)mybit);
             const uint64_t m = __hip_atomic_load(&wm[d], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -890,20 +895,24 @@ __device__ __forceinline__ void lds_rounds(uint64_t (&k)[BS_ITEMS], uint32_t (&i
         uint32_t slot[BS_ITEMS];
 #pragma unroll
         for (int i = 0; i < BS_ITEMS; ++i) {
+            if (wave * (BS_ITEMS * WAVE) + i * WAVE >= L) continue;
             const uint32_t d = dr[i] & 0xFFFFu;
             slot[i] = sm.loc[d] + sm.wcnt[wave * R + d] + (dr[i] >> 16);
         }
         __syncthreads();  // sk aliases the match slots
 #pragma unroll
         for (int i = 0; i < BS_ITEMS; ++i) {
+            if (wave * (BS_ITEMS * WAVE) + i * WAVE >= L) continue;
             sm.sk[slot[i]] = k[i];
             sm.sidx[slot[i]] = (uint16_t)ix[i];
         }
         __syncthreads();
+        // slots past the bucket were not all written: they are padding
 #pragma unroll
         for (int i = 0; i < BS_ITEMS; ++i) {
-            k[i] = sm.sk[wb + i * WAVE];
-            ix[i] = sm.sidx[wb + i * WAVE];
+            const uint32_t j = wb + i * WAVE;
+            k[i] = j < L ? sm.sk[j] : ~0ull;
+            ix[i] = j < L ? sm.sidx[j] : j;
         }
     }
 }
