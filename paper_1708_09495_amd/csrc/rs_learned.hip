@@ -44,9 +44,10 @@ constexpr int TR_NT = 256;             // training threads per workgroup
 constexpr int BS_NT = 512;             // bucket-sort threads per workgroup
 constexpr int BS_ITEMS = 12;
 constexpr uint32_t BS_CAP = BS_NT * BS_ITEMS;  // 6144 pairs
-constexpr int AS_NT = 256;             // assignment threads per workgroup
+constexpr int AS_NT = 1024;            // assignment threads per workgroup
 constexpr int AS_KEYS = 8;             // keys per assignment thread
-constexpr int TOP = 4096;              // splitter groups of 16 held in LDS
+constexpr int TOP = 16384;             // splitter groups held in LDS (their last entries)
+constexpr int GS = (int)NB / TOP;       // splitters per group
 constexpr int GBUF = NP + 1;           // gradient buffer: parameters + loss
 constexpr uint32_t MID_CAP = 1u << 20; // largest bucket sorted by one workgroup
 constexpr uint32_t MID_GRID = 1024;    // workgroups sorting the mid-size buckets
@@ -584,14 +585,14 @@ __global__ __launch_bounds__(1024) void k_split_fix(uint64_t* __restrict__ spl) 
 // LDS table, read contiguously by every workgroup).
 __global__ void k_top(const uint64_t* __restrict__ spl, uint64_t* __restrict__ topg) {
     const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b < TOP) topg[b] = spl[16u * b + 15u];
+    if (b < TOP) topg[b] = spl[(uint32_t)GS * b + (GS - 1)];
 }
 
 __global__ __launch_bounds__(AS_NT) void k_assign(const uint64_t* __restrict__ keys, uint64_t n,
                                                   const uint64_t* __restrict__ spl,
                                                   const uint64_t* __restrict__ topg,
                                                   const State* __restrict__ st, uint16_t* __restrict__ bid) {
-    __shared__ uint64_t top[TOP];  // top[b] = spl[16 b + 15]
+    __shared__ uint64_t top[TOP];  // top[b] = spl[GS b + GS - 1]
     for (int b = threadIdx.x; b < TOP; b += AS_NT) top[b] = topg[b];
     const uint32_t reach = st->reach;
     __syncthreads();
@@ -605,7 +606,7 @@ __global__ __launch_bounds__(AS_NT) void k_assign(const uint64_t* __restrict__ k
             k[q] = i < n ? keys[i] : 0;
             lo[q] = 0;
         }
-        // number of groups whose last splitter is <= key (12 halvings)
+        // number of groups whose last splitter is <= key (log2 TOP halvings)
 #pragma unroll
         for (int step = TOP / 2; step >= 1; step >>= 1) {
 #pragma unroll
@@ -615,18 +616,24 @@ __global__ __launch_bounds__(AS_NT) void k_assign(const uint64_t* __restrict__ k
 #pragma unroll
         for (int q = 0; q < AS_KEYS; ++q) {
             const uint64_t i = base + (uint64_t)q * AS_NT + threadIdx.x;
-            uint32_t ub = 16u * lo[q];
-            if (top[TOP - 1] <= k[q]) ub = NB;
-            else {
-                // within the group: the last entry is > key, so 4 halvings
-                // over its first 15 entries find how many are <= key
-                const uint64_t* g = spl + 16u * lo[q];
-                uint32_t c = 0;
+            // a key at or above the last group's last splitter takes bucket NB
+            const bool past = top[TOP - 1] <= k[q];
+            const uint32_t gi = past ? (uint32_t)TOP - 1 : lo[q];
+            uint32_t c = 0;
+            if constexpr (GS == 4) {
+                // within the group the last entry is > key: its first three
+                // come in two independent 16-byte loads and are counted
+                const ulonglong2* g2 = reinterpret_cast<const ulonglong2*>(spl + 4u * gi);
+                const ulonglong2 x = g2[0], y = g2[1];
+                c = (uint32_t)(x.x <= k[q]) + (uint32_t)(x.y <= k[q]) + (uint32_t)(y.x <= k[q]);
+            } else {
+                // halvings over the group's first GS - 1 entries
+                const uint64_t* g = spl + (uint32_t)GS * gi;
 #pragma unroll
-                for (int step = 8; step >= 1; step >>= 1)
+                for (int step = GS / 2; step >= 1; step >>= 1)
                     if (g[c + step - 1] <= k[q]) c += step;
-                ub += c;
             }
+            const uint32_t ub = past ? NB : (uint32_t)GS * gi + c;
             const uint32_t b = ub < reach ? ub : reach;
             if (i < n) bid[i] = (uint16_t)(b < NB ? b : NB - 1);
         }
@@ -1304,7 +1311,7 @@ rs_status learned_run(const void* kin, void* kout, const void* vin, void* vout, 
     // 4. bucket ids
     {
         uint64_t g = (n + AS_NT * AS_KEYS - 1) / (AS_NT * AS_KEYS);
-        if (g > 2048) g = 2048;  // each workgroup loads the 32 KiB table once
+        if (g > 256) g = 256;  // each workgroup loads the 128 KiB table once
         prof(s, KID_LEARN_ASSIGN, 0);
         hipLaunchKernelGGL(k_assign, dim3((unsigned)g), dim3(AS_NT), 0, s, (const uint64_t*)kin, (uint64_t)n,
                            spl, topg, st, bid0);

@@ -138,8 +138,11 @@ __global__ __launch_bounds__(HIST_NT) void k_hist(const K* __restrict__ keys, ui
 // wave is the wave's running count for the digit plus the number of peer
 // lanes below it; the highest peer lane advances the running count and
 // clears the slot.
+// The two-payload form is held to 128 registers, so that two workgroups
+// share a compute unit (four spilled registers cost less than half the
+// occupancy).
 template <typename K, int VB, int MAXB, int ITEMS, typename LB, typename OFF, int VB2 = 0>
-__global__ __launch_bounds__(NT) void k_onesweep(
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(VB2 != 0 ? 4 : 1))) void k_onesweep(
     const K* __restrict__ kin, K* __restrict__ kout, const void* __restrict__ vin_,
     void* __restrict__ vout_, uint64_t n, int shift, int bits, uint32_t* __restrict__ tile_ctr,
     LB* __restrict__ lb, const uint32_t* __restrict__ ghist, uint32_t* __restrict__ status,
