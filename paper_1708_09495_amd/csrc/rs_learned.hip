@@ -931,9 +931,13 @@ __device__ __forceinline__ void lds_rounds(uint64_t (&k)[BS_ITEMS], uint32_t (&i
 // order and are finished by an insertion sort per run.  If some run is long
 // (keys crowded into a sliver of the range) nothing is written and false is
 // returned: the caller ranks that bucket on every bit (full = true) instead.
+// The range is the keys' own minimum and maximum, or, when bounded, the
+// caller's [lo, hi] known to hold every key (a bucket's splitters), which
+// spares the reduction over the keys.
 template <int VB>
 __device__ __forceinline__ bool lds_sort(const uint64_t* sk_src, const uint64_t* sv_src, uint64_t* kd,
-                                         uint64_t* vd, uint32_t L, BucketSmem& sm, bool full) {
+                                         uint64_t* vd, uint32_t L, BucketSmem& sm, bool full,
+                                         bool bounded = false, uint64_t lo = 0, uint64_t hi = 0) {
     const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const uint32_t wb = wave * (BS_ITEMS * WAVE) + lane;
     uint64_t k[BS_ITEMS];
@@ -944,12 +948,17 @@ __device__ __forceinline__ bool lds_sort(const uint64_t* sk_src, const uint64_t*
         const uint32_t j = wb + i * WAVE;
         k[i] = j < L ? sk_src[j] : ~0ull;
         ix[i] = j;
-        if (j < L) {
+        if (!bounded && j < L) {
             mn = k[i] < mn ? k[i] : mn;
             mx = k[i] > mx ? k[i] : mx;
         }
     }
-    wg_minmax(mn, mx, sm);
+    if (bounded) {
+        mn = lo;
+        mx = hi;
+    } else {
+        wg_minmax(mn, mx, sm);
+    }
     if (mn == mx) {  // one distinct key: already in order
         if (kd != sk_src)
             for (uint32_t j = tid; j < L; j += BS_NT) {
@@ -963,44 +972,69 @@ __device__ __forceinline__ bool lds_sort(const uint64_t* sk_src, const uint64_t*
     const int sh = (!full && sig > 16) ? sig - 16 : 0;
     lds_rounds(k, ix, L, mn, sh, (sig - sh + 7) / 8, sm);
     if (sh > 0) {
-        // runs of keys equal on the ranked bits: the longest decides
+        // Runs of keys equal on the ranked bits are finished by a stable
+        // insertion sort by key (sidx follows), done by the thread holding
+        // the run's first slot.  Ties are found in registers: the slot before
+        // j = wb + 64 i is lane - 1 of item i, the last lane of item i - 1, or
+        // (first slot of a wave) read from LDS.  A run only permutes its own
+        // slots, all of one cell, so a cell read at a run's edge while its
+        // owner sorts it is the same at every stage.  A run longer than 64
+        // fails the bucket.
         if (tid == 0) sm.maxrun = 0;
         __syncthreads();
-        for (uint32_t j = tid; j < L; j += BS_NT) {
+        uint64_t tmask[BS_ITEMS];  // per item: the lanes whose slot ties with the one before
+#pragma unroll
+        for (int i = 0; i < BS_ITEMS; ++i) {
+            const uint32_t j = wb + i * WAVE;
+            uint64_t p = __shfl_up(k[i], 1, WAVE);
+            if (i > 0) {
+                const uint64_t q = __shfl(k[i > 0 ? i - 1 : 0], 63, WAVE);
+                if (lane == 0) p = q;
+            } else if (lane == 0) {
+                p = j > 0 ? sm.sk[j - 1] : k[i];
+            }
+            tmask[i] = __ballot(j > 0 && j < L && ((p - mn) >> sh) == ((k[i] - mn) >> sh));
+        }
+        uint32_t starts = 0;  // items whose slot starts a run of two or more
+#pragma unroll
+        for (int i = 0; i < BS_ITEMS; ++i) {
+            const uint32_t j = wb + i * WAVE;
+            const bool t = (tmask[i] >> lane) & 1ull;
+            bool nt;
+            if (lane < 63) nt = (tmask[i] >> (lane + 1)) & 1ull;
+            else if (i + 1 < BS_ITEMS) nt = tmask[i + 1 < BS_ITEMS ? i + 1 : i] & 1ull;
+            else nt = j + 1 < L && ((sm.sk[j + 1] - mn) >> sh) == ((k[i] - mn) >> sh);
+            if (!t && nt && j < L) starts |= 1u << i;
+        }
+        while (starts) {
+            const int i = __builtin_ctz(starts);
+            starts &= starts - 1;
+            const uint32_t j = wb + i * WAVE;
             const uint64_t c = (sm.sk[j] - mn) >> sh;
-            if (j > 0 && ((sm.sk[j - 1] - mn) >> sh) == c) continue;
-            uint32_t e = j + 1;
-            while (e < L && ((sm.sk[e] - mn) >> sh) == c) ++e;
-            if (e - j > 1) atomicMax(&sm.maxrun, e - j);
-        }
-        __syncthreads();
-        const uint32_t longest = sm.maxrun;
-        if (longest > 64) {
-            __syncthreads();
-            return false;
-        }
-        if (longest > 1) {
-            for (uint32_t j = tid; j < L; j += BS_NT) {
-                const uint64_t c = (sm.sk[j] - mn) >> sh;
-                if (j > 0 && ((sm.sk[j - 1] - mn) >> sh) == c) continue;
-                uint32_t e = j + 1;
-                while (e < L && ((sm.sk[e] - mn) >> sh) == c) ++e;
-                // stable insertion sort of sk[j, e) by key; sidx follows
-                for (uint32_t a = j + 1; a < e; ++a) {
-                    const uint64_t kv = sm.sk[a];
-                    const uint16_t iv = sm.sidx[a];
-                    uint32_t q = a;
-                    while (q > j && sm.sk[q - 1] > kv) {
-                        sm.sk[q] = sm.sk[q - 1];
-                        sm.sidx[q] = sm.sidx[q - 1];
-                        --q;
-                    }
-                    sm.sk[q] = kv;
-                    sm.sidx[q] = iv;
+            uint32_t e = j + 2;
+            while (e < L && e - j <= 64 && ((sm.sk[e] - mn) >> sh) == c) ++e;
+            if (e - j > 64) {
+                atomicMax(&sm.maxrun, e - j);
+                continue;
+            }
+            for (uint32_t a = j + 1; a < e; ++a) {
+                const uint64_t kv = sm.sk[a];
+                const uint16_t iv = sm.sidx[a];
+                uint32_t q = a;
+                while (q > j && sm.sk[q - 1] > kv) {
+                    sm.sk[q] = sm.sk[q - 1];
+                    sm.sidx[q] = sm.sidx[q - 1];
+                    --q;
                 }
+                sm.sk[q] = kv;
+                sm.sidx[q] = iv;
             }
         }
         __syncthreads();
+        if (sm.maxrun > 64) {
+            __syncthreads();
+            return false;
+        }
     }
     // keys in sk; values gathered by original position, then both written
     constexpr int PQ = (BS_CAP + BS_NT - 1) / BS_NT;
@@ -1030,7 +1064,7 @@ __device__ __forceinline__ bool lds_sort(const uint64_t* sk_src, const uint64_t*
 // start[b+1]).  A larger bucket is listed: up to MID_CAP for k_bucket_mid,
 // beyond that for the host.
 template <int VB>
-__global__ __launch_bounds__(BS_NT) void k_bucket_sort(uint64_t* __restrict__ keys, uint64_t* __restrict__ vals,
+__global__ __launch_bounds__(BS_NT) __attribute__((amdgpu_waves_per_eu(4))) void k_bucket_sort(uint64_t* __restrict__ keys, uint64_t* __restrict__ vals,
                                                        const uint32_t* __restrict__ start, uint32_t cap,
                                                        State* __restrict__ st,
                                                        uint32_t* __restrict__ ovf_list,
@@ -1051,7 +1085,12 @@ __global__ __launch_bounds__(BS_NT) void k_bucket_sort(uint64_t* __restrict__ ke
     if (L <= cap && L <= BS_CAP) {
         uint64_t* kb = keys + s0;
         uint64_t* vbk = VB ? vals + s0 : nullptr;
-        if (!lds_sort<VB>(kb, vbk, kb, vbk, L, sm, false) && threadIdx.x == 0) {
+        // below the reach every key of bucket b is in [spl[b-1], spl[b])
+        const bool bounded = b < st->reach;
+        const uint64_t lo = b ? spl[b - 1] : 0ull;
+        const uint64_t hi = spl[b];
+        if (!lds_sort<VB>(kb, vbk, kb, vbk, L, sm, false, bounded && hi > lo, lo, hi - 1) &&
+            threadIdx.x == 0) {
             // crowded keys: ranked on every bit by k_bucket_mid
             const uint32_t at = atomicAdd(&st->mid_buckets, 1u);
             if (at < NB) mid_list[at] = b;
