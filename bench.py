@@ -8,9 +8,10 @@ rank-and-scatter rounds) over 2^28 uint32 keys drawn uniform on [0, 2^32)
 by SplitMix64, radix 2^8, with the input already resident in HBM.
 
   python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu]
-                  [--workload lsd|small|segmented|learned]
+                  [--workload lsd|small|segmented|learned|blocks]
                   lsd:       [--log2n 28] [--radix-bits 8|11|16] [--key-bytes 4|8] [--kv]
                   small:     [--small-n 4096] [--algo btn|oet|lds_radix|auto] [--p P]
+                  blocks:    [--log2n 27] [--algo btn|oet] [--p 256]
                   learned:   [--dist zipf|lognormal|mixture]
 
 The roofline object covers the dominant kernel of the workload: its
@@ -39,8 +40,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="lsd", choices=["lsd", "small", "segmented", "learned"])
-    ap.add_argument("--log2n", type=int, default=28)
+    ap.add_argument("--workload", default="lsd", choices=["lsd", "small", "segmented", "learned", "blocks"])
+    ap.add_argument("--log2n", type=int, default=None, help="lsd, learned: 28; blocks: 27")
     ap.add_argument("--radix-bits", type=int, default=8)
     ap.add_argument("--key-bytes", type=int, default=4, choices=[4, 8])
     ap.add_argument("--kv", action="store_true", help="stable sort with a payload = index")
@@ -479,6 +480,64 @@ def bench_learned(args, torch, rs, gen, np):
     return res
 
 
+# ---- BTN / OET at device scale: p runs in HBM -----------------------------------------
+
+def bench_blocks(args, torch, rs, gen, np):
+    n = 1 << args.log2n
+    name = "oet" if args.algo == "oet" else "btn"
+    algo = rs.RS_ALGO_OET if name == "oet" else rs.RS_ALGO_BTN
+    p = args.p if args.p else 256
+    keys = torch.empty(n, dtype=torch.int32, device="cuda")
+    gen.uniform_u32_dev(gen.S0 + 2, keys)
+    out = torch.empty_like(keys)
+    ws = torch.empty(rs.rs_workspace_bytes(rs.RS_OP_BLOCKS, n, 4, 0, 0, algo, p), dtype=torch.uint8,
+                     device="cuda")
+
+    def step():
+        rs.rs_sort_blocks_u32(keys, out, algo=algo, p=p, ws=ws)
+
+    step()
+    torch.cuda.synchronize()
+    st = rs.rs_get_stats()
+    assert st.device_error == 0, "device reported a bounded-wait or range error"
+    stages = st.network_stages
+    ms, prof = timed_steps(step, args.steps, args.warmup, rs, torch)
+    # one merge-split stage reads and writes every key of the p runs once
+    N = -(-n // p)
+    roof = hbm_roofline(prof, "block_merge", 2 * 4 * p * N)
+    del ws
+    # the plain LSD sort of the same keys, for the comparison the paper draws
+    lws = torch.empty(rs.rs_workspace_bytes(rs.RS_OP_SORT, n, 4, 0, 8, rs.RS_ALGO_LSD), dtype=torch.uint8,
+                      device="cuda")
+    lsd_ms, _ = timed_steps(lambda: rs.rs_sort_u32(keys, out, algo=rs.RS_ALGO_LSD, ws=lws),
+                            max(2, args.steps // 2), 1, rs, torch)
+    del lws, out
+    torch.cuda.empty_cache()
+    config = {
+        "workload": "%s on p=%d runs of ceil(n/p) keys in HBM, uint32 keys, n=2^%d: local sort per "
+                    "workgroup, then %d merge-split stages" % (name.upper(), p, args.log2n, stages),
+        "n": n, "p": p, "stages": stages,
+    }
+    extra = {"plain_lsd_ms": lsd_ms, "plain_lsd_gkeys": n / (lsd_ms * 1e-3) / 1e9,
+             "vs_plain_lsd": lsd_ms / ms}
+    res = line(args, n / (ms * 1e-3) / 1e9, ms, "u32", "synthetic: SplitMix64 uniform keys on the full "
+               "range, seed S0+2", config, roof, prof, extra)
+    if not args.no_cpu:
+        import oracle
+        m = min(n, 1 << min(args.cpu_log2n, 22 if name == "oet" else 24))  # OET: p rounds over the sample
+        kh = np.ascontiguousarray(keys[:m].cpu().numpy().view(np.uint32))
+        fn = (lambda: oracle.oet_block(kh, p)) if name == "oet" else (lambda: oracle.bitonic_block(kh, p))
+        sec = time_oracle(fn, runs=2)
+        res["cpu_baseline"] = {
+            "value": m / sec / 1e9, "unit": "Gkeys/s", "cores": 1, "kind": "oracle",
+            "sample": "first 2^%d keys of the same input, serial C oracle o_%s_block with the same "
+                      "p, pinned to one host core, mean of 2 runs"
+                      % (m.bit_length() - 1, "oet" if name == "oet" else "bitonic"),
+            "seconds_per_run": sec,
+        }
+    return res
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -493,8 +552,10 @@ def main():
     import paper_1708_09495_amd as rs
 
     torch.cuda.set_device(torch.device("cuda:0"))
+    if args.log2n is None:
+        args.log2n = 27 if args.workload == "blocks" else 28
     fn = {"lsd": bench_lsd, "small": bench_small, "segmented": bench_segmented,
-          "learned": bench_learned}[args.workload]
+          "learned": bench_learned, "blocks": bench_blocks}[args.workload]
     print(json.dumps(fn(args, torch, rs, gen, np)), flush=True)
 
 

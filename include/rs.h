@@ -58,7 +58,8 @@ typedef enum {
     RS_OP_SORT_KV = 1,    /* rs_sort_kv                                */
     RS_OP_BATCH = 2,      /* rs_sort_batch_u32                         */
     RS_OP_SEGMENTED = 3,  /* rs_sort_segmented                         */
-    RS_OP_TUNE = 4        /* rs_tune_run (n = instances)               */
+    RS_OP_TUNE = 4,       /* rs_tune_run (n = instances)               */
+    RS_OP_BLOCKS = 5      /* rs_sort_blocks_u32 (num_segments = p)     */
 } rs_op;
 
 /* Facts about the most recent call made on the calling host thread. */
@@ -82,7 +83,8 @@ typedef struct {
  * count-sort rounds at radix 2^b from the least significant digit, each a
  * per-tile digit histogram, a device-wide exclusive scan and a stable
  * rank-and-scatter.  radix_bits in [1, 16]; 0 = default (8).  algo: AUTO, LSD,
- * or BTN/OET/LDS_RADIX for n <= rs_small_capacity(4) (one workgroup).
+ * LDS_RADIX for n <= rs_small_capacity(4) (one workgroup), or BTN/OET: one
+ * workgroup up to that size, above it rs_sort_blocks_u32 with p = 0.
  * Layout: `in` and `out` are dense arrays of n keys. */
 rs_status rs_sort_u32(const uint32_t* in, uint32_t* out, size_t n, int radix_bits,
                       rs_algo algo, void* ws, size_t ws_bytes, void* stream);
@@ -120,9 +122,26 @@ rs_status rs_sort_segmented(const uint32_t* in, uint32_t* out, const int64_t* of
                             size_t num_segments, int64_t total_n, rs_algo algo, void* ws,
                             size_t ws_bytes, void* stream);
 
+/* The block networks at device scale (Section 2; Section 3, Eqs. Tb and
+ * To): the n keys are cut into p runs of N = ceil(n/p) keys (the tail padded
+ * with UINT32_MAX), every run is sorted by one workgroup, then BTN runs
+ * Batcher's bitonic sorter on p wires, lg p (lg p + 1)/2 stages, or OET runs
+ * p rounds of neighbour pairs (round t pairs runs i, i+1 with i = t mod 2),
+ * each comparator a merge-split of two runs (the N smallest keys to one run,
+ * ties taken from the lower-indexed run) and each stage one pass over all
+ * keys in device memory.  The first n keys of the result are written to
+ * `out`.  algo RS_ALGO_BTN (p a power of two) or RS_ALGO_OET; p in
+ * [2, 4096] with p * N < 2^32, 0 = default (256, fewer for n < 16,384).
+ * Layout: dense arrays of n keys; `in == out` is allowed.  Workspace:
+ * rs_workspace_bytes(RS_OP_BLOCKS, n, 4, 0, 0, algo, p) (two padded copies
+ * of the keys).  rs_get_stats reports p and the stage count. */
+rs_status rs_sort_blocks_u32(const uint32_t* in, uint32_t* out, size_t n, rs_algo algo, int p,
+                             void* ws, size_t ws_bytes, void* stream);
+
 /* Bytes of workspace the call (op, n, ...) needs.  For RS_OP_BATCH, n is
  * the array length and num_segments the count; for RS_OP_SEGMENTED, n is
- * total_n.  Returns 0 for arguments no call would accept. */
+ * total_n; for RS_OP_BLOCKS, num_segments is p (0 = default).  Returns 0 for
+ * arguments no call would accept. */
 size_t rs_workspace_bytes(int op, size_t n, int key_bytes, int val_bytes, int radix_bits,
                           rs_algo algo, size_t num_segments);
 

@@ -15,9 +15,10 @@ LIB_PATH = os.path.join(_HERE, "librs.so")
 
 RS_OK, RS_ERR_INVALID, RS_ERR_UNSUPPORTED, RS_ERR_WORKSPACE, RS_ERR_HIP = range(5)
 RS_ALGO_AUTO, RS_ALGO_LSD, RS_ALGO_BTN, RS_ALGO_OET, RS_ALGO_LEARNED, RS_ALGO_LDS_RADIX = range(6)
-RS_OP_SORT, RS_OP_SORT_KV, RS_OP_BATCH, RS_OP_SEGMENTED, RS_OP_TUNE = range(5)
+RS_OP_SORT, RS_OP_SORT_KV, RS_OP_BATCH, RS_OP_SEGMENTED, RS_OP_TUNE, RS_OP_BLOCKS = range(6)
 
 EXPORTS = ["rs_sort_u32", "rs_sort_u64", "rs_sort_kv", "rs_sort_batch_u32", "rs_sort_segmented",
+           "rs_sort_blocks_u32",
            "rs_workspace_bytes", "rs_small_capacity", "rs_status_string", "rs_get_stats",
            "rs_tune_set", "rs_tune_get", "rs_tune_run", "rs_profile_enable", "rs_profile_read",
            "rs_learned_set_opts", "rs_learned_get_opts", "rs_mlp_num_params", "rs_mlp_forward",
@@ -88,6 +89,7 @@ def lib():
         L.rs_sort_kv.argtypes = [vp, vp, vp, vp, sz, i, i, i, i, vp, sz, vp]
         L.rs_sort_batch_u32.argtypes = [vp, vp, sz, sz, i, i, vp, sz, vp]
         L.rs_sort_segmented.argtypes = [vp, vp, vp, sz, ctypes.c_int64, i, vp, sz, vp]
+        L.rs_sort_blocks_u32.argtypes = [vp, vp, sz, i, i, vp, sz, vp]
         L.rs_workspace_bytes.argtypes = [i, sz, i, i, i, i, sz]
         L.rs_workspace_bytes.restype = sz
         L.rs_small_capacity.argtypes = [i]
@@ -313,6 +315,18 @@ def rs_sort_batch_u32(keys_in, n, count, keys_out=None, algo=RS_ALGO_AUTO, p=0, 
     ws = _workspace(rs_workspace_bytes(RS_OP_BATCH, n, 4, 0, 0, algo, count), ws, keys_in.device)
     _call(lib().rs_sort_batch_u32(_ptr(keys_in), _ptr(keys_out), n, count, algo, p, _ptr(ws),
                                   ws.numel(), _stream(stream)), "rs_sort_batch_u32")
+    return keys_out
+
+
+def rs_sort_blocks_u32(keys_in, keys_out=None, algo=RS_ALGO_BTN, p=0, ws=None, stream=None):
+    """Sort a uint32 tensor with BTN or OET on p runs in device memory."""
+    _check_dev(keys_in, 4, "keys_in")
+    keys_out = keys_in.new_empty(keys_in.shape) if keys_out is None else keys_out
+    _check_dev(keys_out, 4, "keys_out")
+    n = keys_in.numel()
+    ws = _workspace(rs_workspace_bytes(RS_OP_BLOCKS, n, 4, 0, 0, algo, p), ws, keys_in.device)
+    _call(lib().rs_sort_blocks_u32(_ptr(keys_in), _ptr(keys_out), n, algo, p, _ptr(ws), ws.numel(),
+                                   _stream(stream)), "rs_sort_blocks_u32")
     return keys_out
 
 

@@ -22,6 +22,7 @@ SOURCES = [
     "rs_wide.hip",
     "rs_small.hip",
     "rs_seg.hip",
+    "rs_blocks.hip",
     "rs_learned.hip",
     "rs_tune.hip",
     "rs_api.cpp",

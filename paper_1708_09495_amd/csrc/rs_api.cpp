@@ -145,6 +145,27 @@ rs_status sort_small(const uint32_t* in, uint32_t* out, size_t n, size_t count, 
     return small_run(algo, in, out, (uint32_t)n, count, p, st);
 }
 
+rs_status sort_blocks(const uint32_t* in, uint32_t* out, size_t n, int algo, uint32_t p, void* ws,
+                      size_t ws_bytes, hipStream_t st) {
+    BlockPlan bp;
+    if (!block_plan(n, algo, p, &bp)) return RS_ERR_UNSUPPORTED;
+    begin_call(algo);
+    g_call.stats.runs_p = (int32_t)p;
+    g_call.stats.network_stages = block_stages(algo, p);
+    g_call.stats.radix_bits = 8;
+    g_call.stats.passes = 4;
+    rs_status rc = check_ws(ws, ws_bytes, bp.total);
+    if (rc != RS_OK) return rc;
+    rc = block_run(bp, algo, in, out, n, tune_table(), ws, st);
+    if (rc == RS_OK) {
+        g_call.stream = st;
+        g_call.status = reinterpret_cast<const uint32_t*>(static_cast<unsigned char*>(ws) + bp.off_seg +
+                                                          bp.seg.off_status);
+        g_call.pending = true;
+    }
+    return rc;
+}
+
 rs_status sort_keys_common(const void* kin, void* kout, const void* vin, void* vout, size_t n,
                            int kb, int vb, int bits, rs_algo algo, void* ws, size_t ws_bytes,
                            void* stream) {
@@ -169,6 +190,9 @@ rs_status sort_keys_common(const void* kin, void* kout, const void* vin, void* v
         case RS_ALGO_OET:
         case RS_ALGO_LDS_RADIX:
             if (kb != 4 || vb != 0) return RS_ERR_UNSUPPORTED;
+            if (algo != RS_ALGO_LDS_RADIX && n > SMALL_CAP_U32)
+                return sort_blocks(static_cast<const uint32_t*>(kin), static_cast<uint32_t*>(kout), n, algo,
+                                   block_default_p(n), ws, ws_bytes, st);
             return sort_small(static_cast<const uint32_t*>(kin), static_cast<uint32_t*>(kout), n, 1,
                               algo, 0, st);
         default:
@@ -207,6 +231,21 @@ rs_status rs_sort_kv(const void* keys_in, const void* vals_in, void* keys_out, v
     if (val_bytes != 4 && val_bytes != 8) return RS_ERR_INVALID;
     return sort_keys_common(keys_in, keys_out, vals_in, vals_out, n, key_bytes, val_bytes,
                             radix_bits, algo, ws, ws_bytes, stream);
+}
+
+rs_status rs_sort_blocks_u32(const uint32_t* in, uint32_t* out, size_t n, rs_algo algo, int p, void* ws,
+                             size_t ws_bytes, void* stream) {
+    if (n > 0 && (!in || !out)) return RS_ERR_INVALID;
+    if (n > 0 && in != out && overlaps(in, n * 4, out, n * 4)) return RS_ERR_INVALID;
+    if (algo != RS_ALGO_BTN && algo != RS_ALGO_OET) return RS_ERR_UNSUPPORTED;
+    if (p < 0 || p == 1 || p > 4096) return RS_ERR_INVALID;
+    if (algo == RS_ALGO_BTN && p > 0 && (p & (p - 1))) return RS_ERR_INVALID;
+    if (n == 0) {
+        begin_call(algo);
+        return RS_OK;
+    }
+    const uint32_t pp = p ? (uint32_t)p : block_default_p(n);
+    return sort_blocks(in, out, n, algo, pp, ws, ws_bytes, static_cast<hipStream_t>(stream));
 }
 
 rs_status rs_sort_batch_u32(const uint32_t* in, uint32_t* out, size_t n, size_t count, rs_algo algo,
@@ -263,6 +302,11 @@ size_t rs_workspace_bytes(int op, size_t n, int key_bytes, int val_bytes, int ra
     (void)num_segments;
     radix_bits = default_bits(radix_bits);
     if (op == RS_OP_SORT || op == RS_OP_SORT_KV) {
+        if ((algo == RS_ALGO_BTN || algo == RS_ALGO_OET) && op == RS_OP_SORT && key_bytes == 4 &&
+            n > SMALL_CAP_U32) {
+            BlockPlan bp;
+            return block_plan(n, algo, block_default_p(n), &bp) ? bp.total : 0;
+        }
         if (algo == RS_ALGO_BTN || algo == RS_ALGO_OET || algo == RS_ALGO_LDS_RADIX) return ALIGN;
         if (algo == RS_ALGO_LEARNED && key_bytes == 8) {
             const int vb = op == RS_OP_SORT ? 0 : val_bytes;
@@ -282,6 +326,12 @@ size_t rs_workspace_bytes(int op, size_t n, int key_bytes, int val_bytes, int ra
     }
     if (op == RS_OP_BATCH) return ALIGN;
     if (op == RS_OP_TUNE) return (n >= 1 && n <= 65536) ? tune_ws_bytes((int)n) : 0;
+    if (op == RS_OP_BLOCKS) {
+        if (key_bytes != 4 || n == 0 || num_segments > 4096) return n == 0 ? ALIGN : 0;
+        const uint32_t p = num_segments ? (uint32_t)num_segments : block_default_p(n);
+        BlockPlan bp;
+        return block_plan(n, algo, p, &bp) ? bp.total : 0;
+    }
     if (op == RS_OP_SEGMENTED) {
         SegPlan p;
         if ((int64_t)n < 0 || !seg_plan(num_segments, (int64_t)n, &p)) return 0;
@@ -425,7 +475,7 @@ namespace {
 const char* const KNAMES[KID_COUNT_] = {
     "fill", "hist", "onesweep", "copy", "batch", "seg_plan", "seg",
     "learn_sample", "learn_train", "learn_split", "learn_assign", "learn_bucket", "learn_check",
-    "wide_count", "wide_scatter", "learn_pass", "learn_mid"};
+    "wide_count", "wide_scatter", "learn_pass", "learn_mid", "block_merge"};
 struct Mark {
     int kid;
     hipEvent_t b, e;

@@ -39,6 +39,7 @@ enum KernelId {
     KID_WIDE_SCATTER,
     KID_LEARN_PASS,
     KID_LEARN_MID,
+    KID_BLOCK_MERGE,
     KID_COUNT_
 };
 extern bool g_prof_on;
@@ -125,6 +126,20 @@ rs_status seg_run(const SegPlan& p, const uint32_t* in, uint32_t* out, const int
                   uint64_t S, int64_t total, const SegTable& table, void* ws, hipStream_t st);
 
 size_t tune_ws_bytes(int instances);
+
+// ---- BTN / OET at device scale: p runs in HBM, merge-split stages -----------
+struct BlockPlan {
+    uint32_t p = 0;     // runs
+    uint64_t N = 0;     // keys per run (the tail padded with the largest key)
+    uint32_t nch = 0;   // merge chunks per pair
+    SegPlan seg;        // the runs' local sorts
+    size_t off_seg = 0, off_off = 0, off_x = 0, off_y = 0, off_cr = 0, total = 0;
+};
+uint32_t block_default_p(size_t n);
+bool block_plan(size_t n, int algo, uint32_t p, BlockPlan* bp);
+int64_t block_stages(int algo, uint32_t p);
+rs_status block_run(const BlockPlan& bp, int algo, const uint32_t* in, uint32_t* out, size_t n,
+                    const SegTable& table, void* ws, hipStream_t st);
 
 // The process-wide tuning table (defaults until rs_tune_set / rs_tune_run).
 SegTable& tune_table();

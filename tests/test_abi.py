@@ -73,3 +73,31 @@ def test_argument_errors_return_before_device_work(lib):
     lib.rs_sort_kv.argtypes = [vp, vp, vp, vp, ctypes.c_size_t, ctypes.c_int, ctypes.c_int,
                                ctypes.c_int, ctypes.c_int, vp, ctypes.c_size_t, vp]
     assert lib.rs_sort_kv(vp(256), vp(4096), vp(8192), vp(16384), 10, 4, 2, 8, 1, None, 0, None) == 1
+
+
+def test_block_network_queries_and_errors(lib):
+    vp, sz = ctypes.c_void_p, ctypes.c_size_t
+    lib.rs_workspace_bytes.restype = ctypes.c_size_t
+    lib.rs_workspace_bytes.argtypes = [ctypes.c_int, sz, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                       ctypes.c_int, sz]
+    n = 1_000_003
+    # two padded copies of the keys plus the runs' local-sort tables
+    for algo, p in ((2, 256), (2, 2), (3, 7), (3, 256)):
+        pn = p * -(-n // p)
+        ws = lib.rs_workspace_bytes(5, n, 4, 0, 0, algo, p)
+        assert ws >= 8 * pn and ws % 256 == 0, (algo, p, ws)
+    assert lib.rs_workspace_bytes(5, n, 4, 0, 0, 2, 3) == 0       # BTN needs a power of two
+    assert lib.rs_workspace_bytes(5, n, 4, 0, 0, 2, 8192) == 0    # p above 4096
+    assert lib.rs_workspace_bytes(5, n, 8, 0, 0, 2, 256) == 0     # uint32 keys only
+    assert lib.rs_workspace_bytes(5, n, 4, 0, 0, 1, 256) == 0     # BTN or OET only
+    assert lib.rs_workspace_bytes(5, n, 4, 0, 0, 2, 0) == lib.rs_workspace_bytes(5, n, 4, 0, 0, 2, 256)
+    # rs_sort_u32 with BTN above one workgroup's capacity takes the same path
+    assert lib.rs_workspace_bytes(0, n, 4, 0, 0, 2, 0) == lib.rs_workspace_bytes(5, n, 4, 0, 0, 2, 0)
+    assert lib.rs_workspace_bytes(0, 1000, 4, 0, 0, 2, 0) == 256
+    lib.rs_sort_blocks_u32.argtypes = [vp, vp, sz, ctypes.c_int, ctypes.c_int, vp, sz, vp]
+    assert lib.rs_sort_blocks_u32(None, vp(256), 10, 2, 4, None, 0, None) == 1   # null input
+    assert lib.rs_sort_blocks_u32(vp(256), vp(4096), 10, 2, 3, None, 0, None) == 1  # p not 2^k
+    assert lib.rs_sort_blocks_u32(vp(256), vp(4096), 10, 3, 1, None, 0, None) == 1  # p = 1
+    assert lib.rs_sort_blocks_u32(vp(256), vp(4096), 10, 3, 5000, None, 0, None) == 1
+    assert lib.rs_sort_blocks_u32(vp(256), vp(4096), 10, 1, 4, None, 0, None) == 2  # LSD
+    assert lib.rs_sort_blocks_u32(None, None, 0, 2, 0, None, 0, None) == 0
