@@ -451,6 +451,13 @@ def bench_learned(args, torch, rs, gen, np):
         rs.rs_sort_kv(keys, vals, ko, vo, radix_bits=8, algo=rs.RS_ALGO_LSD, ws=ws)
 
     plain_ms, _ = timed_steps(plain, max(3, args.steps // 2), 1, rs, torch)
+
+    def plain_skip():
+        rs.rs_sort_kv(keys, vals, ko, vo, radix_bits=8, algo=rs.RS_ALGO_AUTO, ws=ws)
+
+    # the same rounds, skipping those whose digit is the same for every key
+    skip_ms, _ = timed_steps(plain_skip, max(3, args.steps // 2), 1, rs, torch)
+    skipped = rs.rs_get_stats().passes_skipped
     # dominant kernel: the two stable bucket-id rounds, each reading and
     # writing the 2-byte id, the key and the payload
     roof = hbm_roofline(prof, "learn_pass", 2 * n * (2 + 8 + 8))
@@ -461,6 +468,8 @@ def bench_learned(args, torch, rs, gen, np):
                roof, prof,
                {"plain_lsd_gkeys": n / (plain_ms * 1e-3) / 1e9, "plain_lsd_ms": plain_ms,
                 "speedup_vs_plain": plain_ms / ms,
+                "plain_skip_gkeys": n / (skip_ms * 1e-3) / 1e9, "plain_skip_rounds_skipped": skipped,
+                "speedup_vs_plain_skip": skip_ms / ms,
                 "fallback": st.fallback, "buckets_overflowed": st.buckets_overflowed,
                 "keys_overflowed": st.keys_overflowed, "train_loss": st.train_loss})
     del ws

@@ -77,14 +77,19 @@ typedef struct {
     uint32_t device_error;      /* bit 0: a bounded wait gave up; bit 1: a computed
                                    destination was out of range (not written)    */
     int32_t hip_error;          /* hipError_t of the failing call when RS_ERR_HIP */
+    int32_t passes_skipped;     /* RS_ALGO_AUTO: rounds of `passes` not run because
+                                   every key has the same digit there           */
 } rs_stats;
 
 /* Sort n uint32 keys ascending.  Follows Section 3: ceil(32/b) stable
  * count-sort rounds at radix 2^b from the least significant digit, each a
  * per-tile digit histogram, a device-wide exclusive scan and a stable
- * rank-and-scatter.  radix_bits in [1, 16]; 0 = default (8).  algo: AUTO, LSD,
- * LDS_RADIX for n <= rs_small_capacity(4) (one workgroup), or BTN/OET: one
- * workgroup up to that size, above it rs_sort_blocks_u32 with p = 0.
+ * rank-and-scatter.  radix_bits in [1, 16]; 0 = default (8).  algo: LSD runs
+ * every round; AUTO (radix_bits <= 11) skips the rounds whose digit is the
+ * same for every key -- such a stable round is the identity; the all-round
+ * histogram shows them, and the choice is made on the device --; LDS_RADIX
+ * for n <= rs_small_capacity(4) (one workgroup); BTN/OET: one workgroup up
+ * to that size, above it rs_sort_blocks_u32 with p = 0.
  * Layout: `in` and `out` are dense arrays of n keys. */
 rs_status rs_sort_u32(const uint32_t* in, uint32_t* out, size_t n, int radix_bits,
                       rs_algo algo, void* ws, size_t ws_bytes, void* stream);

@@ -43,7 +43,8 @@ class rs_stats(ctypes.Structure):
                 ("network_stages", ctypes.c_int64), ("tile_keys", ctypes.c_int32),
                 ("fallback", ctypes.c_int32), ("buckets_overflowed", ctypes.c_int64),
                 ("keys_overflowed", ctypes.c_int64), ("train_loss", ctypes.c_double),
-                ("device_error", ctypes.c_uint32), ("hip_error", ctypes.c_int32)]
+                ("device_error", ctypes.c_uint32), ("hip_error", ctypes.c_int32),
+                ("passes_skipped", ctypes.c_int32)]
 
 
 class rs_tune_entry(ctypes.Structure):

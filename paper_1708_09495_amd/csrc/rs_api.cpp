@@ -14,6 +14,7 @@ struct CallState {
     rs_stats stats{};
     hipStream_t stream = nullptr;
     const uint32_t* status = nullptr;   // device status word of the last call
+    const uint32_t* skipped = nullptr;  // device mask of skipped rounds (or none)
     bool pending = false;               // stats still need the device's word
 };
 thread_local CallState g_call;
@@ -24,6 +25,7 @@ void begin_call(int algo) {
     g_call.stats.algo = algo;
     g_call.stream = nullptr;
     g_call.status = nullptr;
+    g_call.skipped = nullptr;
     g_call.pending = false;
 }
 
@@ -57,11 +59,14 @@ rs_status sort_wide(const void* kin, void* kout, const void* vin, void* vout, si
     return rc;
 }
 
+// skip: rounds whose digit is the same for every key are skipped (decided on
+// the device from the all-round histogram).
 rs_status sort_lsd(const void* kin, void* kout, const void* vin, void* vout, size_t n, int kb,
-                   int vb, int bits, void* ws, size_t ws_bytes, hipStream_t st) {
+                   int vb, int bits, void* ws, size_t ws_bytes, hipStream_t st, bool skip = false) {
     if (bits >= 12) return sort_wide(kin, kout, vin, vout, n, kb, vb, bits, ws, ws_bytes, st);
     LsdPlan p;
     if (!lsd_plan(n, kb, vb, bits, &p)) return RS_ERR_UNSUPPORTED;
+    p.skip = skip && n < (1ull << 32) && p.passes <= 32;
     begin_call(RS_ALGO_LSD);
     g_call.stats.radix_bits = bits;
     g_call.stats.passes = p.passes;
@@ -73,6 +78,9 @@ rs_status sort_lsd(const void* kin, void* kout, const void* vin, void* vout, siz
     if (rc == RS_OK) {
         g_call.stream = st;
         g_call.status = reinterpret_cast<const uint32_t*>(static_cast<unsigned char*>(ws) + p.off_status);
+        if (p.skip)
+            g_call.skipped = reinterpret_cast<const uint32_t*>(static_cast<unsigned char*>(ws) + p.off_status +
+                                                               ROUTE_OFFSET);
         g_call.pending = true;
     }
     return rc;
@@ -181,6 +189,7 @@ rs_status sort_keys_common(const void* kin, void* kout, const void* vin, void* v
     hipStream_t st = static_cast<hipStream_t>(stream);
     switch (algo) {
         case RS_ALGO_AUTO:
+            return sort_lsd(kin, kout, vin, vout, n, kb, vb, bits, ws, ws_bytes, st, true);
         case RS_ALGO_LSD:
             return sort_lsd(kin, kout, vin, vout, n, kb, vb, bits, ws, ws_bytes, st);
         case RS_ALGO_LEARNED:
@@ -361,8 +370,12 @@ rs_status rs_get_stats(rs_stats* out) {
         uint32_t word = 0;
         hipError_t e = hipStreamSynchronize(g_call.stream);
         if (e == hipSuccess) e = hipMemcpy(&word, g_call.status, sizeof(word), hipMemcpyDeviceToHost);
+        uint32_t mask = 0;
+        if (e == hipSuccess && g_call.skipped)
+            e = hipMemcpy(&mask, g_call.skipped, sizeof(mask), hipMemcpyDeviceToHost);
         if (e != hipSuccess) return hip_fail(e);
         g_call.stats.device_error = word;
+        g_call.stats.passes_skipped = __builtin_popcount(mask);
         g_call.pending = false;
     }
     *out = g_call.stats;

@@ -66,7 +66,11 @@ struct LsdPlan {
     size_t total = 0;
     int kid_hist = KID_HIST;          // timing labels of the plan's launches
     int kid_scatter = KID_ONESWEEP;
+    bool skip = false;       // skip the rounds whose digit is the same for every key
 };
+// Byte offset, inside the status block, of the route of a sort that skips
+// rounds (its first word: the mask of skipped rounds).
+constexpr size_t ROUTE_OFFSET = 16;
 
 // Plans an LSD sort; returns false when (kb, vb, bits, vb2) is not supported.
 bool lsd_plan(size_t n, int kb, int vb, int bits, LsdPlan* p, int vb2 = 0);

@@ -54,6 +54,73 @@ constexpr int lsd_items(int kb, int vb) { return kb == 4 ? (vb == 0 ? 24 : 16) :
 template <int VB> struct ValT { using type = uint32_t; };
 template <> struct ValT<8> { using type = uint64_t; };
 
+// Buffers of a sort that skips the rounds whose digit is the same for every
+// key (in the workspace's status block, written on the device once the
+// histograms are known).
+struct Route {
+    uint32_t mask;              // bit j: round j is skipped
+    uint32_t passes, inplace;
+    uint32_t pad_;
+    const void* in;
+    void* out;
+    void* tmp;
+    const void* vin;
+    void* vout;
+    void* vtmp;
+};
+static_assert(ROUTE_OFFSET + sizeof(Route) <= ALIGN, "the route lives in the status block");
+
+// One workgroup: the rounds whose global histogram has a single non-empty
+// bin (a count of n) are the identity and are skipped; thread 0 writes the
+// route the rounds follow.
+__global__ void k_route(const uint32_t* __restrict__ ghist, int passes, int R, uint64_t n, Route* __restrict__ rt,
+                        const void* in, void* out, void* tmp, const void* vin, void* vout, void* vtmp) {
+    __shared__ uint32_t m;
+    if (threadIdx.x == 0) m = 0;
+    __syncthreads();
+    for (int i = threadIdx.x; i < passes * R; i += blockDim.x)
+        if ((uint64_t)ghist[i] == n) atomicOr(&m, 1u << (i / R));
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        Route r;
+        r.mask = m;
+        r.passes = (uint32_t)passes;
+        r.inplace = in == out;
+        r.pad_ = 0;
+        r.in = in;
+        r.out = out;
+        r.tmp = tmp;
+        r.vin = vin;
+        r.vout = vout;
+        r.vtmp = vtmp;
+        *rt = r;
+    }
+}
+
+// After the rounds: the sorted keys (and values) are still in the input when
+// no round ran, or in the workspace copy after an odd number of rounds of an
+// in-place sort; then they are copied to `out`.
+__global__ void k_route_copy(const Route* __restrict__ rt, uint64_t kwords, uint64_t vwords) {
+    const uint32_t m = rt->mask;
+    const int E = __popc(~m & (rt->passes >= 32 ? ~0u : (1u << rt->passes) - 1u));
+    const uint32_t* ks;
+    const uint32_t* vs;
+    if (rt->inplace) {
+        if (!(E & 1)) return;
+        ks = static_cast<const uint32_t*>(rt->tmp);
+        vs = static_cast<const uint32_t*>(rt->vtmp);
+    } else {
+        if (E != 0) return;
+        ks = static_cast<const uint32_t*>(rt->in);
+        vs = static_cast<const uint32_t*>(rt->vin);
+    }
+    uint32_t* kd = static_cast<uint32_t*>(rt->out);
+    uint32_t* vd = static_cast<uint32_t*>(rt->vout);
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < kwords; i += stride) kd[i] = ks[i];
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < vwords; i += stride) vd[i] = vs[i];
+}
+
 __global__ void k_fill(uint32_t* __restrict__ p, uint64_t n, uint32_t v) {
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = v;
@@ -143,10 +210,11 @@ __global__ __launch_bounds__(HIST_NT) void k_hist(const K* __restrict__ keys, ui
 // occupancy).
 template <typename K, int VB, int MAXB, int ITEMS, typename LB, typename OFF, int VB2 = 0>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(VB2 != 0 ? 4 : 1))) void k_onesweep(
-    const K* __restrict__ kin, K* __restrict__ kout, const void* __restrict__ vin_,
-    void* __restrict__ vout_, uint64_t n, int shift, int bits, uint32_t* __restrict__ tile_ctr,
+    const K* __restrict__ kin0, K* __restrict__ kout0, const void* __restrict__ vin0,
+    void* __restrict__ vout0, uint64_t n, int shift, int bits, uint32_t* __restrict__ tile_ctr,
     LB* __restrict__ lb, const uint32_t* __restrict__ ghist, uint32_t* __restrict__ status,
-    const void* __restrict__ vin2_ = nullptr, void* __restrict__ vout2_ = nullptr) {
+    const Route* __restrict__ route, const void* __restrict__ vin2_ = nullptr,
+    void* __restrict__ vout2_ = nullptr) {
     using V = typename ValT<VB>::type;
     constexpr int RMAX = 1 << MAXB;
     constexpr int RLO = RMAX < 256 ? RMAX : 256;      // slots of the LDS match
@@ -177,6 +245,29 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(VB2 != 0 ? 4
     uint16_t* wcnt = reinterpret_cast<uint16_t*>(u_raw + MSKB);    // [NW][R]
     K* skeys = reinterpret_cast<K*>(u_raw);
     V* svals = reinterpret_cast<V*>(SEPV ? v_raw : u_raw);
+
+    // With a route the buffers follow the rounds actually run: a round whose
+    // digit is the same for every key leaves the order as it is and is
+    // skipped; executed round e reads what round e-1 wrote (round 0 the
+    // input) and writes `out` when an even number of executed rounds follow
+    // it (in place: when e is odd, so that round 0 never writes its input).
+    const K* __restrict__ kin = kin0;
+    K* __restrict__ kout = kout0;
+    const void* __restrict__ vin_ = vin0;
+    void* __restrict__ vout_ = vout0;
+    if (route) {
+        const uint32_t m = route->mask;
+        const int pass = shift / bits;
+        if ((m >> pass) & 1u) return;
+        const int e = __popc(~m & ((1u << pass) - 1u));
+        const int E = __popc(~m & (route->passes >= 32 ? ~0u : (1u << route->passes) - 1u));
+        const bool in_out = route->inplace ? ((e - 1) & 1) != 0 : ((E - e) & 1) == 0;  // round e-1
+        const bool to_out = route->inplace ? (e & 1) != 0 : ((E - 1 - e) & 1) == 0;
+        kin = reinterpret_cast<const K*>(e == 0 ? route->in : (in_out ? route->out : route->tmp));
+        kout = reinterpret_cast<K*>(to_out ? route->out : route->tmp);
+        vin_ = e == 0 ? route->vin : (in_out ? route->vout : route->vtmp);
+        vout_ = to_out ? route->vout : route->vtmp;
+    }
     const V* vin = reinterpret_cast<const V*>(vin_);
     V* vout = reinterpret_cast<V*>(vout_);
 
@@ -436,8 +527,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(VB2 != 0 ? 4
 
 template <typename K, int VB, int MAXB, int ITEMS, typename LB, typename OFF, int VB2 = 0>
 hipError_t launch_pass(const LsdPlan& p, const void* src, void* dst, const void* vsrc, void* vdst,
-                       int pass, unsigned char* ws, hipStream_t st, const void* v2src = nullptr,
-                       void* v2dst = nullptr) {
+                       int pass, unsigned char* ws, hipStream_t st, const Route* route,
+                       const void* v2src = nullptr, void* v2dst = nullptr) {
     uint32_t* ctr = reinterpret_cast<uint32_t*>(ws + p.off_ctr) + pass;
     LB* lb = reinterpret_cast<LB*>(ws + p.off_lb) + (size_t)pass * p.lb_words;
     const uint32_t* gh = reinterpret_cast<const uint32_t*>(ws + p.off_hist) + (size_t)pass * p.R;
@@ -445,27 +536,27 @@ hipError_t launch_pass(const LsdPlan& p, const void* src, void* dst, const void*
     prof(st, p.kid_scatter, 0);
     hipLaunchKernelGGL((k_onesweep<K, VB, MAXB, ITEMS, LB, OFF, VB2>), dim3((unsigned)p.tiles), dim3(NT),
                        0, st, (const K*)src, (K*)dst, vsrc, vdst, (uint64_t)p.n, pass * p.bits, p.bits,
-                       ctr, lb, gh, status, v2src, v2dst);
+                       ctr, lb, gh, status, route, v2src, v2dst);
     prof(st, p.kid_scatter, 1);
     return hipGetLastError();
 }
 
 template <typename K, int VB, int MAXB, int ITEMS>
 hipError_t launch_pass_lb(const LsdPlan& p, const void* src, void* dst, const void* vsrc,
-                          void* vdst, int pass, unsigned char* ws, hipStream_t st) {
+                          void* vdst, int pass, unsigned char* ws, hipStream_t st, const Route* route) {
     if (p.n >= (1ull << 31))
-        return launch_pass<K, VB, MAXB, ITEMS, uint64_t, int64_t>(p, src, dst, vsrc, vdst, pass, ws, st);
+        return launch_pass<K, VB, MAXB, ITEMS, uint64_t, int64_t>(p, src, dst, vsrc, vdst, pass, ws, st, route);
     if (p.lb64)
-        return launch_pass<K, VB, MAXB, ITEMS, uint64_t, int32_t>(p, src, dst, vsrc, vdst, pass, ws, st);
-    return launch_pass<K, VB, MAXB, ITEMS, uint32_t, int32_t>(p, src, dst, vsrc, vdst, pass, ws, st);
+        return launch_pass<K, VB, MAXB, ITEMS, uint64_t, int32_t>(p, src, dst, vsrc, vdst, pass, ws, st, route);
+    return launch_pass<K, VB, MAXB, ITEMS, uint32_t, int32_t>(p, src, dst, vsrc, vdst, pass, ws, st, route);
 }
 
 template <typename K, int VB>
 hipError_t launch_pass_k(const LsdPlan& p, const void* src, void* dst, const void* vsrc,
-                         void* vdst, int pass, unsigned char* ws, hipStream_t st) {
+                         void* vdst, int pass, unsigned char* ws, hipStream_t st, const Route* route) {
     constexpr int ITEMS = lsd_items(sizeof(K), VB);
-    if (p.bits <= 8) return launch_pass_lb<K, VB, 8, ITEMS>(p, src, dst, vsrc, vdst, pass, ws, st);
-    return launch_pass_lb<K, VB, 11, ITEMS>(p, src, dst, vsrc, vdst, pass, ws, st);
+    if (p.bits <= 8) return launch_pass_lb<K, VB, 8, ITEMS>(p, src, dst, vsrc, vdst, pass, ws, st, route);
+    return launch_pass_lb<K, VB, 11, ITEMS>(p, src, dst, vsrc, vdst, pass, ws, st, route);
 }
 
 // 16-bit digit keys with an 8-byte payload and an optional second one
@@ -475,25 +566,25 @@ hipError_t launch_pass_k16(const LsdPlan& p, const void* src, void* dst, const v
                            const void* v2src, void* v2dst) {
     if (p.lb64)
         return launch_pass<uint16_t, 8, 8, 16, uint64_t, int64_t, VB2>(p, src, dst, vsrc, vdst, pass, ws,
-                                                                        st, v2src, v2dst);
+                                                                        st, nullptr, v2src, v2dst);
     return launch_pass<uint16_t, 8, 8, 16, uint32_t, int32_t, VB2>(p, src, dst, vsrc, vdst, pass, ws, st,
-                                                                    v2src, v2dst);
+                                                                    nullptr, v2src, v2dst);
 }
 
 hipError_t launch_pass_any(const LsdPlan& p, const void* src, void* dst, const void* vsrc,
-                           void* vdst, int pass, unsigned char* ws, hipStream_t st,
+                           void* vdst, int pass, unsigned char* ws, hipStream_t st, const Route* route,
                            const void* v2src = nullptr, void* v2dst = nullptr) {
     if (p.kb == 2)
         return p.vb2 ? launch_pass_k16<8>(p, src, dst, vsrc, vdst, pass, ws, st, v2src, v2dst)
                      : launch_pass_k16<0>(p, src, dst, vsrc, vdst, pass, ws, st, v2src, v2dst);
     if (p.kb == 4) {
-        if (p.vb == 0) return launch_pass_k<uint32_t, 0>(p, src, dst, vsrc, vdst, pass, ws, st);
-        if (p.vb == 4) return launch_pass_k<uint32_t, 4>(p, src, dst, vsrc, vdst, pass, ws, st);
-        return launch_pass_k<uint32_t, 8>(p, src, dst, vsrc, vdst, pass, ws, st);
+        if (p.vb == 0) return launch_pass_k<uint32_t, 0>(p, src, dst, vsrc, vdst, pass, ws, st, route);
+        if (p.vb == 4) return launch_pass_k<uint32_t, 4>(p, src, dst, vsrc, vdst, pass, ws, st, route);
+        return launch_pass_k<uint32_t, 8>(p, src, dst, vsrc, vdst, pass, ws, st, route);
     }
-    if (p.vb == 0) return launch_pass_k<uint64_t, 0>(p, src, dst, vsrc, vdst, pass, ws, st);
-    if (p.vb == 4) return launch_pass_k<uint64_t, 4>(p, src, dst, vsrc, vdst, pass, ws, st);
-    return launch_pass_k<uint64_t, 8>(p, src, dst, vsrc, vdst, pass, ws, st);
+    if (p.vb == 0) return launch_pass_k<uint64_t, 0>(p, src, dst, vsrc, vdst, pass, ws, st, route);
+    if (p.vb == 4) return launch_pass_k<uint64_t, 4>(p, src, dst, vsrc, vdst, pass, ws, st, route);
+    return launch_pass_k<uint64_t, 8>(p, src, dst, vsrc, vdst, pass, ws, st, route);
 }
 
 }  // namespace
@@ -588,6 +679,25 @@ rs_status lsd_run(const LsdPlan& p, const void* kin, void* kout, const void* vin
     void* tv = ws + p.off_tv;
     void* tv2 = ws + p.off_tv2;
     const int P = p.passes;
+    if (p.skip) {
+        // which rounds run is known only on the device: each round reads the
+        // route and finds its buffers there
+        Route* rt = reinterpret_cast<Route*>(ws + p.off_status + ROUTE_OFFSET);
+        hipLaunchKernelGGL(k_route, dim3(1), dim3(256), 0, st, reinterpret_cast<const uint32_t*>(ws + p.off_hist),
+                           P, p.R, (uint64_t)p.n, rt, kin, kout, (void*)tk, vin, vout, (void*)tv);
+        if ((rc = launch_status()) != RS_OK) return rc;
+        for (int j = 0; j < P; ++j) {
+            hipError_t e = launch_pass_any(p, kin, kout, vin, vout, j, ws, st, rt);
+            if (e != hipSuccess) return hip_fail(e);
+        }
+        prof(st, KID_COPY, 0);
+        const uint64_t kw = p.n * p.kb / 4, vw = p.n * p.vb / 4;
+        size_t g = (kw + 255) / 256;
+        if (g > 2048) g = 2048;
+        hipLaunchKernelGGL(k_route_copy, dim3((unsigned)g), dim3(256), 0, st, rt, kw, vw);
+        prof(st, KID_COPY, 1);
+        return launch_status();
+    }
     const bool inplace = kin == kout;
     const bool copy_back = inplace && (P % 2 == 1);
     const void* src = kin;
@@ -600,7 +710,7 @@ rs_status lsd_run(const LsdPlan& p, const void* kin, void* kout, const void* vin
         void* dst = to_out ? kout : tk;
         void* vdst = to_out ? vout : tv;
         void* v2dst = to_out ? vout2 : tv2;
-        hipError_t e = launch_pass_any(p, src, dst, vsrc, vdst, j, ws, st, v2src, v2dst);
+        hipError_t e = launch_pass_any(p, src, dst, vsrc, vdst, j, ws, st, nullptr, v2src, v2dst);
         if (e != hipSuccess) return hip_fail(e);
         src = dst;
         vsrc = vdst;
