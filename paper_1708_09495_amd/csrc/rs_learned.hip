@@ -48,6 +48,8 @@ constexpr int AS_NT = 1024;            // assignment threads per workgroup
 constexpr int AS_KEYS = 8;             // keys per assignment thread
 constexpr int TOP = 16384;             // splitter groups held in LDS (their last entries)
 constexpr int GS = (int)NB / TOP;       // splitters per group
+constexpr int LG_TOP = 14;             // lg TOP
+static_assert((1 << LG_TOP) == TOP, "TOP is 2^LG_TOP");
 constexpr int GBUF = NP + 1;           // gradient buffer: parameters + loss
 constexpr uint32_t MID_CAP = 1u << 20; // largest bucket sorted by one workgroup
 constexpr uint32_t MID_GRID = 1024;    // workgroups sorting the mid-size buckets
@@ -581,18 +583,29 @@ __global__ __launch_bounds__(1024) void k_split_fix(uint64_t* __restrict__ spl) 
 
 // ---- 4. bucket ids --------------------------------------------------------------------
 
-// The last splitter of every group of 16, packed (the assignment kernel's
-// LDS table, read contiguously by every workgroup).
+// The last splitter of every group, in breadth-first (Eytzinger) order: the
+// search over groups 0 .. TOP-2 is a complete binary tree of depth
+// lg TOP whose node t (1 <= t < TOP, at depth d = floor(lg t)) is group
+// ((t - 2^d) << (lg TOP - d)) + 2^(lg TOP - 1 - d) - 1.  Each depth is then
+// contiguous in LDS, so the lanes of a wave reading one depth hit
+// different banks (sorted order puts all nodes of a depth a power of two
+// apart: in one bank).  Entry 0 holds the last group's last splitter.
 __global__ void k_top(const uint64_t* __restrict__ spl, uint64_t* __restrict__ topg) {
-    const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b < TOP) topg[b] = spl[(uint32_t)GS * b + (GS - 1)];
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= TOP) return;
+    uint32_t grp = TOP - 1;
+    if (t > 0) {
+        const int d = 31 - __clz(t);
+        grp = ((t - (1u << d)) << (LG_TOP - d)) + (1u << (LG_TOP - 1 - d)) - 1;
+    }
+    topg[t] = spl[(uint32_t)GS * grp + (GS - 1)];
 }
 
 __global__ __launch_bounds__(AS_NT) void k_assign(const uint64_t* __restrict__ keys, uint64_t n,
                                                   const uint64_t* __restrict__ spl,
                                                   const uint64_t* __restrict__ topg,
                                                   const State* __restrict__ st, uint16_t* __restrict__ bid) {
-    __shared__ uint64_t top[TOP];  // top[b] = spl[GS b + GS - 1]
+    __shared__ uint64_t top[TOP];  // last splitters of the groups, breadth-first (k_top)
     for (int b = threadIdx.x; b < TOP; b += AS_NT) top[b] = topg[b];
     const uint32_t reach = st->reach;
     __syncthreads();
@@ -606,18 +619,22 @@ __global__ __launch_bounds__(AS_NT) void k_assign(const uint64_t* __restrict__ k
             k[q] = i < n ? keys[i] : 0;
             lo[q] = 0;
         }
-        // number of groups whose last splitter is <= key (log2 TOP halvings)
+        // number of groups whose last splitter is <= key: lg TOP steps down
+        // the breadth-first tree, one bit of the count per depth
 #pragma unroll
-        for (int step = TOP / 2; step >= 1; step >>= 1) {
+        for (int q = 0; q < AS_KEYS; ++q) lo[q] = 1;
 #pragma unroll
-            for (int q = 0; q < AS_KEYS; ++q)
-                if (top[lo[q] + step - 1] <= k[q]) lo[q] += step;
+        for (int d = 0; d < LG_TOP; ++d) {
+#pragma unroll
+            for (int q = 0; q < AS_KEYS; ++q) lo[q] = 2 * lo[q] + (top[lo[q]] <= k[q] ? 1u : 0u);
         }
+#pragma unroll
+        for (int q = 0; q < AS_KEYS; ++q) lo[q] -= TOP;
 #pragma unroll
         for (int q = 0; q < AS_KEYS; ++q) {
             const uint64_t i = base + (uint64_t)q * AS_NT + threadIdx.x;
             // a key at or above the last group's last splitter takes bucket NB
-            const bool past = top[TOP - 1] <= k[q];
+            const bool past = top[0] <= k[q];
             const uint32_t gi = past ? (uint32_t)TOP - 1 : lo[q];
             uint32_t c = 0;
             if constexpr (GS == 4) {
