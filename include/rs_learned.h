@@ -24,7 +24,7 @@ extern "C" {
 #endif
 
 typedef struct {
-    int32_t train_steps;          /* Adam steps (default 32)                        */
+    int32_t train_steps;          /* Adam steps (default 8)                         */
     float lr;                     /* Adam learning rate (default 1e-2)              */
     int32_t use_network;          /* 0: buckets from the key's feature alone       */
     int32_t bucket_cap;           /* pairs one bucket may hold in LDS (<= 6144)    */

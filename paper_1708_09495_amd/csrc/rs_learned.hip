@@ -1227,7 +1227,7 @@ __global__ void k_mlp_forward(const float* __restrict__ params, const float* __r
 
 namespace {
 
-LearnOpts g_opts = {32, 1e-2f, 1, (int32_t)BS_CAP, -1, 0.25, 64, 64};
+LearnOpts g_opts = {8, 1e-2f, 1, (int32_t)BS_CAP, -1, 0.25, 64, 64};
 
 struct LearnLayout {
     size_t off_state, off_sample, off_sorted, off_sample_ws, off_xs, off_ts, off_params, off_gbuf,

@@ -169,8 +169,11 @@ def test_network_gain_over_feature_only(rs):
         for dist in dists:
             keys = _dist(dist, n, gen.S0 + 9)
             vals = np.arange(n, dtype=np.uint64)
+            # mode 1: 32 Adam steps (the network has the whole CDF to learn);
+            # mode 2: the default training
+            steps = 32 if mode == 1 else rs.rs_learned_get_opts()["train_steps"]
             old = rs.rs_learned_set_opts(fallback_frac=1.0, max_fallback_buckets=1 << 30, bucket_cap=cap,
-                                         feature_mode=mode)
+                                         feature_mode=mode, train_steps=steps)
             try:
                 _, _, st_net = _learned(rs, keys, vals)
                 rs.rs_learned_set_opts(use_network=0)
