@@ -53,6 +53,9 @@ def parse():
     ap.add_argument("--plain-sample", type=int, default=512,
                     help="segments timed one plain-radix call each (segmented workload)")
     ap.add_argument("--dist", default="zipf", choices=["zipf", "lognormal", "mixture"])
+    ap.add_argument("--mbsp", action="store_true",
+                    help="blocks: also time OET and one workgroup's radix sort of the whole array and "
+                         "report the MBSP model's g, G and predictions (Section 3, Eqs. TsG, ToG, TbG)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-log2n", type=int, default=28)
     return ap.parse_args()
@@ -529,6 +532,8 @@ def bench_blocks(args, torch, rs, gen, np):
     }
     extra = {"plain_lsd_ms": lsd_ms, "plain_lsd_gkeys": n / (lsd_ms * 1e-3) / 1e9,
              "vs_plain_lsd": lsd_ms / ms}
+    if args.mbsp:
+        extra["mbsp"] = mbsp_check(args, torch, rs, keys, n, p, name, ms, stages, prof)
     res = line(args, n / (ms * 1e-3) / 1e9, ms, "u32", "synthetic: SplitMix64 uniform keys on the full "
                "range, seed S0+2", config, roof, prof, extra)
     if not args.no_cpu:
@@ -545,6 +550,56 @@ def bench_blocks(args, torch, rs, gen, np):
             "seconds_per_run": sec,
         }
     return res
+
+
+def mbsp_check(args, torch, rs, keys, n, p, name, ms, stages, prof):
+    """The MBSP model of Section 3 on this GPU, with a processor read as a
+    workgroup.  A run's local sort costs 68 (n/p) G (Eq. TsG: four rounds of
+    3 + 2 accesses per key at G, with g = 5G folded in as the paper does,
+    here measured instead) and one merge-split stage 4 (n/p) g; G and g are
+    calibrated on the network just timed, then used to predict the other
+    network (Eqs. ToG, TbG) and the serial sort, T_s = 68 n G (Eq. TsG):
+    one workgroup's radix sort of the whole array."""
+    import math
+    N = -(-n // p)
+    local_ms = prof["seg"][1] / prof["seg"][0] if prof.get("seg", (0, 0))[0] else float("nan")
+    stage_ms = prof["block_merge"][1] / prof["block_merge"][0]
+    G = local_ms * 1e-3 / (68 * N)
+    g = stage_ms * 1e-3 / (4 * N)
+    lg = int(math.log2(p)) if p & (p - 1) == 0 else math.log2(p)
+    other = "oet" if name == "btn" else "btn"
+    other_stages = p if other == "oet" else int(lg * (lg + 1) / 2)
+    pred_other_ms = local_ms + other_stages * stage_ms
+    # the other network, measured
+    algo = rs.RS_ALGO_OET if other == "oet" else rs.RS_ALGO_BTN
+    if other == "btn" and p & (p - 1):
+        other_ms = None
+    else:
+        out = torch.empty_like(keys)
+        ws = torch.empty(rs.rs_workspace_bytes(rs.RS_OP_BLOCKS, n, 4, 0, 0, algo, p), dtype=torch.uint8,
+                         device="cuda")
+        other_ms, _ = timed_steps(lambda: rs.rs_sort_blocks_u32(keys, out, algo=algo, p=p, ws=ws), 2, 1, rs, torch)
+        del ws, out
+    # the serial sort: one workgroup sorts all n keys (one segment)
+    off = torch.tensor([0, n], dtype=torch.int64, device="cuda")
+    out = torch.empty_like(keys)
+    ws = torch.empty(rs.rs_workspace_bytes(rs.RS_OP_SEGMENTED, n, 4, 0, 0, rs.RS_ALGO_AUTO, 1), dtype=torch.uint8,
+                     device="cuda")
+    serial_ms, _ = timed_steps(lambda: rs.rs_sort_segmented(keys, off, out, ws=ws), 1, 1, rs, torch)
+    del ws, out
+    btn_ms = ms if name == "btn" else other_ms
+    oet_ms = ms if name == "oet" else other_ms
+    btn_stages = int(lg * (lg + 1) / 2)
+    return {
+        "G_ps": G * 1e12, "g_ps": g * 1e12, "g_over_G": g / G,
+        "local_sort_ms": local_ms, "stage_ms": stage_ms,
+        "predicted_%s_ms" % other: pred_other_ms, "measured_%s_ms" % other: other_ms,
+        "oet_over_btn_measured": (oet_ms / btn_ms) if (oet_ms and btn_ms) else None,
+        "oet_over_btn_model": (68 + 4 * p * g / G) / (68 + 4 * btn_stages * g / G),
+        "serial_one_workgroup_ms": serial_ms, "serial_predicted_ms": 68 * n * G * 1e3,
+        "serial_over_btn_measured": (serial_ms / btn_ms) if btn_ms else None,
+        "serial_over_btn_model": 68 * p / (68 + 4 * btn_stages * g / G),
+    }
 
 
 def main():
