@@ -53,6 +53,8 @@ static_assert((1 << LG_TOP) == TOP, "TOP is 2^LG_TOP");
 constexpr int GBUF = NP + 1;           // gradient buffer: parameters + loss
 constexpr uint32_t MID_CAP = 1u << 20; // largest bucket sorted by one workgroup
 constexpr uint32_t MID_GRID = 1024;    // workgroups sorting the mid-size buckets
+constexpr uint32_t TASK_CAP = 1u << 16; // LDS sorts listed for any workgroup to take
+constexpr uint32_t TASK_FULL = 1u << 31;  // task flag: a crowded bucket, in place, every bit
 constexpr int KNOTS = 1024;            // calibration intervals of the network output
 constexpr int QK = 4096;               // key-quantile intervals of the piecewise-linear feature
 
@@ -71,6 +73,8 @@ struct State {
     unsigned long long big_keys;
     uint32_t unsorted;
     uint32_t err;
+    uint32_t mid_tasks;    // entries reserved in the mid-size task list
+    uint32_t pad_;
     uint64_t qk[QK + 1];   // sample keys at quantiles g/QK (mode 2)
 };
 
@@ -1136,12 +1140,30 @@ __global__ __launch_bounds__(BS_NT) __attribute__((amdgpu_waves_per_eu(4))) void
 // bucket spread almost evenly over its range), about half an LDS load each;
 // each sub-range is then sorted in LDS back into place, and a sub-range
 // still too large takes the global-memory rounds.
+// Reserves n entries of the task list for the calling workgroup (thread 0
+// reserves, every thread gets the answer): the index of the first, or
+// TASK_CAP when the list is full (then the caller does the work itself).  A
+// reservation that runs past the end marks its entries inside the list empty.
+__device__ uint32_t reserve_tasks(State* st, uint2* tasks, uint32_t n, BucketSmem& sm) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const uint32_t base = atomicAdd(&st->mid_tasks, n);
+        sm.maxrun = base + n <= TASK_CAP ? base : TASK_CAP;
+        for (uint32_t i = base; base + n > TASK_CAP && i < TASK_CAP; ++i) tasks[i] = make_uint2(0u, 0u);
+    }
+    __syncthreads();
+    const uint32_t r = sm.maxrun;
+    __syncthreads();
+    return r;
+}
+
 template <int VB>
 __global__ __launch_bounds__(BS_NT) void k_bucket_mid(uint64_t* __restrict__ keys, uint64_t* __restrict__ vals,
                                                       const uint32_t* __restrict__ start,
-                                                      const State* __restrict__ st,
+                                                      State* __restrict__ st,
                                                       const uint32_t* __restrict__ mid_list,
-                                                      uint64_t* __restrict__ scr_k, uint64_t* __restrict__ scr_v) {
+                                                      uint64_t* __restrict__ scr_k, uint64_t* __restrict__ scr_v,
+                                                      uint2* __restrict__ tasks) {
     __shared__ BucketSmem sm;
     const uint32_t tid = threadIdx.x;
     const uint32_t count = st->mid_buckets < NB ? st->mid_buckets : NB;
@@ -1153,6 +1175,11 @@ __global__ __launch_bounds__(BS_NT) void k_bucket_mid(uint64_t* __restrict__ key
         uint64_t* sck = scr_k + s0;
         uint64_t* scv = VB ? scr_v + s0 : nullptr;
         if (L <= BS_CAP) {  // a crowded bucket from k_bucket_sort
+            const uint32_t at = reserve_tasks(st, tasks, 1, sm);
+            if (at < TASK_CAP) {
+                if (tid == 0) tasks[at] = make_uint2(s0, L | TASK_FULL);
+                continue;
+            }
             lds_sort<VB>(kb, vbk, kb, vbk, L, sm, true);
             continue;
         }
@@ -1174,6 +1201,16 @@ __global__ __launch_bounds__(BS_NT) void k_bucket_mid(uint64_t* __restrict__ key
         if (tid < 256u) sm.sub_end[tid] = sm.run[tid];  // ends of the sub-ranges
         __syncthreads();
         const uint32_t nsub = 1u << t;
+        // the sub-ranges are listed for k_bucket_sub, so that every
+        // workgroup shares the LDS sorts of the few mid-size buckets
+        const uint32_t at = reserve_tasks(st, tasks, nsub, sm);
+        if (at < TASK_CAP) {
+            if (tid < nsub) {
+                const uint32_t a = tid ? sm.sub_end[tid - 1] : 0u;
+                tasks[at + tid] = make_uint2(s0 + a, sm.sub_end[tid] - a);
+            }
+            continue;
+        }
         for (uint32_t d = 0; d < nsub; ++d) {
             const uint32_t a = __builtin_amdgcn_readfirstlane(d ? sm.sub_end[d - 1] : 0u);
             const uint32_t c = __builtin_amdgcn_readfirstlane(sm.sub_end[d] - a);
@@ -1198,6 +1235,49 @@ __global__ __launch_bounds__(BS_NT) void k_bucket_mid(uint64_t* __restrict__ key
                                       smx, sm.sk, sm.sidx, sm.wcnt, sm.loc, sm.wsum, sm.tot, sm.run);
             __syncthreads();
         }
+    }
+}
+
+// The listed LDS sorts, one workgroup each at a time: a sub-range of a
+// split bucket goes from the scratch arrays back into place (a crowded one by
+// the global-memory rounds); a crowded bucket is ranked on every bit in
+// place.
+template <int VB>
+__global__ __launch_bounds__(BS_NT) void k_bucket_sub(uint64_t* __restrict__ keys, uint64_t* __restrict__ vals,
+                                                      const State* __restrict__ st, const uint2* __restrict__ tasks,
+                                                      uint64_t* __restrict__ scr_k, uint64_t* __restrict__ scr_v) {
+    __shared__ BucketSmem sm;
+    const uint32_t tid = threadIdx.x;
+    const uint32_t count = st->mid_tasks < TASK_CAP ? st->mid_tasks : TASK_CAP;
+    for (uint32_t w = blockIdx.x; w < count; w += gridDim.x) {
+        const uint2 tk = tasks[w];
+        const uint32_t a = tk.x, c = tk.y & ~TASK_FULL;
+        if (c == 0) continue;
+        uint64_t* kb = keys + a;
+        uint64_t* vbk = VB ? vals + a : nullptr;
+        if (tk.y & TASK_FULL) {
+            lds_sort<VB>(kb, vbk, kb, vbk, c, sm, true);
+            continue;
+        }
+        uint64_t* sck = scr_k + a;
+        uint64_t* scv = VB ? scr_v + a : nullptr;
+        if (c <= BS_CAP) {
+            if (!lds_sort<VB>(sck, scv, kb, vbk, c, sm, false)) lds_sort<VB>(sck, scv, kb, vbk, c, sm, true);
+            continue;
+        }
+        uint64_t smn = ~0ull, smx = 0;
+        for (uint32_t q = tid; q < c; q += BS_NT) {
+            const uint64_t v = sck[q];
+            kb[q] = v;
+            if constexpr (VB != 0) vbk[q] = scv[q];
+            smn = v < smn ? v : smn;
+            smx = v > smx ? v : smx;
+        }
+        wg_minmax(smn, smx, sm);
+        if (smn != smx)
+            bucket_global_lsd<VB>(kb, vbk, sck, scv, c, smn, smx, sm.sk, sm.sidx, sm.wcnt, sm.loc, sm.wsum, sm.tot,
+                                  sm.run);
+        __syncthreads();
     }
 }
 
@@ -1231,7 +1311,7 @@ LearnOpts g_opts = {8, 1e-2f, 1, (int32_t)BS_CAP, -1, 0.25, 64, 64};
 
 struct LearnLayout {
     size_t off_state, off_sample, off_sorted, off_sample_ws, off_xs, off_ts, off_params, off_gbuf,
-        off_spl, off_top, off_knot, off_start, off_ovf, off_mid, off_bid0, off_big, total;
+        off_spl, off_top, off_task, off_knot, off_start, off_ovf, off_mid, off_bid0, off_big, total;
     LsdPlan sample_plan, pass_plan, fb_plan;
 };
 
@@ -1258,6 +1338,7 @@ bool learn_layout(size_t n, int vb, LearnLayout* L) {
     q.off_gbuf = take(4 * (size_t)GBUF * 3);
     q.off_spl = take(8 * (size_t)NB);
     q.off_top = take(8 * (size_t)TOP);
+    q.off_task = take(sizeof(uint2) * (size_t)TASK_CAP);
     q.off_knot = take(4 * (size_t)(KNOTS + 1));
     q.off_start = take(4 * ((size_t)NB + 1));
     q.off_ovf = take(4 * (size_t)NB);
@@ -1399,12 +1480,18 @@ rs_status learned_run(const void* kin, void* kout, const void* vin, void* vout, 
                                (uint64_t*)nullptr, start, cap, st, ovf, mid, spl);
         prof(s, KID_LEARN_BUCKET, 1);
         prof(s, KID_LEARN_MID, 0);
-        if (vb)
+        uint2* tasks = reinterpret_cast<uint2*>(ws + L.off_task);
+        if (vb) {
             hipLaunchKernelGGL(k_bucket_mid<8>, dim3(MID_GRID), dim3(BS_NT), 0, s, (uint64_t*)kout,
-                               (uint64_t*)vout, start, st, mid, scr_k, scr_v);
-        else
+                               (uint64_t*)vout, start, st, mid, scr_k, scr_v, tasks);
+            hipLaunchKernelGGL(k_bucket_sub<8>, dim3(MID_GRID), dim3(BS_NT), 0, s, (uint64_t*)kout,
+                               (uint64_t*)vout, st, tasks, scr_k, scr_v);
+        } else {
             hipLaunchKernelGGL(k_bucket_mid<0>, dim3(MID_GRID), dim3(BS_NT), 0, s, (uint64_t*)kout,
-                               (uint64_t*)nullptr, start, st, mid, scr_k, scr_v);
+                               (uint64_t*)nullptr, start, st, mid, scr_k, scr_v, tasks);
+            hipLaunchKernelGGL(k_bucket_sub<0>, dim3(MID_GRID), dim3(BS_NT), 0, s, (uint64_t*)kout,
+                               (uint64_t*)nullptr, st, tasks, scr_k, scr_v);
+        }
         prof(s, KID_LEARN_MID, 1);
         if ((rc = launch_status()) != RS_OK) return rc;
     }
