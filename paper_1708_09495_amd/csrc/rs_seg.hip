@@ -93,8 +93,19 @@ __device__ void seg_large(const uint32_t* __restrict__ in, uint32_t* __restrict_
     }
     for (int i = tid; i < SG_P * SG_R; i += SG_NT) hist[i] = 0;
     __syncthreads();
-    // one read counts the digits of all four rounds
-    for (uint32_t q = tid; q < L; q += SG_NT) {
+    // one read counts the digits of all four rounds (four loads in flight)
+    uint32_t q = tid;
+    for (; q + 3 * SG_NT < L; q += 4 * SG_NT) {
+        const uint32_t k0 = in[q], k1 = in[q + SG_NT], k2 = in[q + 2 * SG_NT], k3 = in[q + 3 * SG_NT];
+#pragma unroll
+        for (int p = 0; p < SG_P; ++p) {
+            atomicAdd(&hist[p * SG_R + ((k0 >> (8 * p)) & 255u)], 1u);
+            atomicAdd(&hist[p * SG_R + ((k1 >> (8 * p)) & 255u)], 1u);
+            atomicAdd(&hist[p * SG_R + ((k2 >> (8 * p)) & 255u)], 1u);
+            atomicAdd(&hist[p * SG_R + ((k3 >> (8 * p)) & 255u)], 1u);
+        }
+    }
+    for (; q < L; q += SG_NT) {
         const uint32_t k = in[q];
 #pragma unroll
         for (int p = 0; p < SG_P; ++p) atomicAdd(&hist[p * SG_R + ((k >> (8 * p)) & 255u)], 1u);
@@ -112,15 +123,24 @@ __device__ void seg_large(const uint32_t* __restrict__ in, uint32_t* __restrict_
             const uint32_t ex = block_excl_scan<SG_NT>(v, wsum, &total);
             if (tid < (uint32_t)SG_R) run[tid] = ex;
         }
-        for (uint32_t base = 0; base < L; base += SG_T) {
-            const uint32_t nvalid = (L - base) < (uint32_t)SG_T ? (L - base) : (uint32_t)SG_T;
-            const uint32_t wb = wave * (SG_ITEMS * WAVE) + lane;
-            uint32_t k[SG_ITEMS];
+        // keys of the tile at b (past the end: the largest key); the next
+        // tile of the round loads while the current one is written out
+        const uint32_t wb = wave * (SG_ITEMS * WAVE) + lane;
+        auto load_tile = [&](uint32_t b, uint32_t (&kt)[SG_ITEMS]) {
+            const uint32_t nv = b < L ? ((L - b) < (uint32_t)SG_T ? (L - b) : (uint32_t)SG_T) : 0u;
 #pragma unroll
             for (int i = 0; i < SG_ITEMS; ++i) {
                 const uint32_t j = wb + i * WAVE;
-                k[i] = j < nvalid ? src[base + j] : 0xFFFFFFFFu;
+                kt[i] = j < nv ? src[b + j] : 0xFFFFFFFFu;
             }
+        };
+        uint32_t kn[SG_ITEMS];
+        load_tile(0, kn);
+        for (uint32_t base = 0; base < L; base += SG_T) {
+            const uint32_t nvalid = (L - base) < (uint32_t)SG_T ? (L - base) : (uint32_t)SG_T;
+            uint32_t k[SG_ITEMS];
+#pragma unroll
+            for (int i = 0; i < SG_ITEMS; ++i) k[i] = kn[i];
             __syncthreads();  // run[] set; previous tile finished with wcnt/skeys
             uint32_t dr[SG_ITEMS];
             {
@@ -167,6 +187,7 @@ __device__ void seg_large(const uint32_t* __restrict__ in, uint32_t* __restrict_
                 skeys[loc[d] + wcnt[wave * SG_R + d] + (dr[i] >> 16)] = k[i];
             }
             __syncthreads();
+            load_tile(base + SG_T, kn);
             // each digit's run of this tile lands at the digit's running offset
 #pragma unroll
             for (int q = 0; q < SG_ITEMS; ++q) {
