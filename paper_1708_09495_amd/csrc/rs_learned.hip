@@ -663,9 +663,31 @@ __global__ __launch_bounds__(AS_NT) void k_assign(const uint64_t* __restrict__ k
 
 // ---- 6. buckets ----------------------------------------------------------------------
 
+// start[b] = first position of bucket b in the sorted ids.  Each thread
+// takes 8 consecutive ids with one 16-byte load, plus the id just before
+// them (in the neighbouring thread's cache line); the array's ragged end and
+// a base not 16-byte aligned take the one-id loop.
 __global__ void k_bucket_first(const uint16_t* __restrict__ bid, uint64_t n, uint32_t* __restrict__ start) {
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+    const uint64_t t0 = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint64_t done = 0;
+    if ((reinterpret_cast<uintptr_t>(bid) & 15u) == 0) {
+        const uint64_t groups = n / 8;
+        const uint4* b8 = reinterpret_cast<const uint4*>(bid);
+        for (uint64_t g = t0; g < groups; g += stride) {
+            const uint4 v = b8[g];
+            uint32_t id[8] = {v.x & 0xFFFFu, v.x >> 16, v.y & 0xFFFFu, v.y >> 16,
+                              v.z & 0xFFFFu, v.z >> 16, v.w & 0xFFFFu, v.w >> 16};
+            const uint64_t i = g * 8;
+            const uint32_t prev = i ? bid[i - 1] : 0xFFFFFFFFu;
+            if (id[0] != prev) start[id[0]] = (uint32_t)i;
+#pragma unroll
+            for (int r = 1; r < 8; ++r)
+                if (id[r] != id[r - 1]) start[id[r]] = (uint32_t)(i + r);
+        }
+        done = groups * 8;
+    }
+    for (uint64_t i = done + t0; i < n; i += stride)
         if (i == 0 || bid[i] != bid[i - 1]) start[bid[i]] = (uint32_t)i;
 }
 
