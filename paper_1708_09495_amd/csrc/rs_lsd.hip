@@ -47,7 +47,7 @@ template <> struct LBW<uint64_t> {
 };
 
 // keys per thread of a onesweep tile
-constexpr int lsd_items(int kb, int vb) { return kb == 4 ? (vb == 0 ? 24 : 16) : 8; }
+constexpr int lsd_items(int kb, int vb) { return kb == 4 ? (vb == 0 ? 28 : 16) : 8; }
 // 16-bit digit keys carry up to two 8-byte payloads (the learned path moves
 // bucket ids with their keys and values)
 
@@ -205,11 +205,11 @@ __global__ __launch_bounds__(HIST_NT) void k_hist(const K* __restrict__ keys, ui
 // wave is the wave's running count for the digit plus the number of peer
 // lanes below it; the highest peer lane advances the running count and
 // clears the slot.
-// The two-payload form is held to 128 registers, so that two workgroups
-// share a compute unit (four spilled registers cost less than half the
-// occupancy).
+// Keys-only rounds (28 keys per thread for uint32) and the two-payload form
+// are held to 128 registers, so that two workgroups share a compute unit
+// (a few spilled registers cost less than half the occupancy).
 template <typename K, int VB, int MAXB, int ITEMS, typename LB, typename OFF, int VB2 = 0>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(VB2 != 0 ? 4 : 1))) void k_onesweep(
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu((VB2 != 0 || VB == 0) ? 4 : 1))) void k_onesweep(
     const K* __restrict__ kin0, K* __restrict__ kout0, const void* __restrict__ vin0,
     void* __restrict__ vout0, uint64_t n, int shift, int bits, uint32_t* __restrict__ tile_ctr,
     LB* __restrict__ lb, const uint32_t* __restrict__ ghist, uint32_t* __restrict__ status,
