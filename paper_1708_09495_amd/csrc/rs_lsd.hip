@@ -46,8 +46,14 @@ template <> struct LBW<uint64_t> {
     static constexpr uint64_t MASK = (1ull << 62) - 1;
 };
 
-// keys per thread of a onesweep tile
-constexpr int lsd_items(int kb, int vb) { return kb == 4 ? (vb == 0 ? 28 : 16) : 8; }
+// keys per thread of a onesweep tile, by key and value bytes and the digit
+// width the LDS arrays are sized for (measured at 2^28 keys; radix 2^11
+// tiles stay smaller so that two workgroups still share a compute unit)
+constexpr int lsd_items(int kb, int vb, int maxb) {
+    if (maxb > 8) return kb == 4 ? (vb == 0 ? 24 : 16) : 8;
+    if (kb == 4) return vb == 0 ? 28 : (vb == 4 ? 20 : 16);
+    return vb == 0 ? 16 : (vb == 8 ? 12 : 8);
+}
 // 16-bit digit keys carry up to two 8-byte payloads (the learned path moves
 // bucket ids with their keys and values)
 
@@ -205,11 +211,11 @@ __global__ __launch_bounds__(HIST_NT) void k_hist(const K* __restrict__ keys, ui
 // wave is the wave's running count for the digit plus the number of peer
 // lanes below it; the highest peer lane advances the running count and
 // clears the slot.
-// Keys-only rounds (28 keys per thread for uint32) and the two-payload form
-// are held to 128 registers, so that two workgroups share a compute unit
-// (a few spilled registers cost less than half the occupancy).
+// Held to 128 registers, so that two workgroups share a compute unit (at
+// the tile sizes above a few spilled registers cost less than half the
+// occupancy).
 template <typename K, int VB, int MAXB, int ITEMS, typename LB, typename OFF, int VB2 = 0>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu((VB2 != 0 || VB == 0) ? 4 : 1))) void k_onesweep(
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_onesweep(
     const K* __restrict__ kin0, K* __restrict__ kout0, const void* __restrict__ vin0,
     void* __restrict__ vout0, uint64_t n, int shift, int bits, uint32_t* __restrict__ tile_ctr,
     LB* __restrict__ lb, const uint32_t* __restrict__ ghist, uint32_t* __restrict__ status,
@@ -554,9 +560,9 @@ hipError_t launch_pass_lb(const LsdPlan& p, const void* src, void* dst, const vo
 template <typename K, int VB>
 hipError_t launch_pass_k(const LsdPlan& p, const void* src, void* dst, const void* vsrc,
                          void* vdst, int pass, unsigned char* ws, hipStream_t st, const Route* route) {
-    constexpr int ITEMS = lsd_items(sizeof(K), VB);
-    if (p.bits <= 8) return launch_pass_lb<K, VB, 8, ITEMS>(p, src, dst, vsrc, vdst, pass, ws, st, route);
-    return launch_pass_lb<K, VB, 11, ITEMS>(p, src, dst, vsrc, vdst, pass, ws, st, route);
+    if (p.bits <= 8)
+        return launch_pass_lb<K, VB, 8, lsd_items(sizeof(K), VB, 8)>(p, src, dst, vsrc, vdst, pass, ws, st, route);
+    return launch_pass_lb<K, VB, 11, lsd_items(sizeof(K), VB, 11)>(p, src, dst, vsrc, vdst, pass, ws, st, route);
 }
 
 // 16-bit digit keys with an 8-byte payload and an optional second one
@@ -613,7 +619,7 @@ bool lsd_plan(size_t n, int kb, int vb, int bits, LsdPlan* p, int vb2) {
     q.passes = (8 * kb + bits - 1) / bits;
     q.R = 1 << bits;
     q.vb2 = vb2;
-    q.tile = NT * (kb == 2 ? 16 : lsd_items(kb, vb));
+    q.tile = NT * (kb == 2 ? 16 : lsd_items(kb, vb, bits <= 8 ? 8 : 11));
     q.tiles = n ? (n + q.tile - 1) / q.tile : 0;
     q.lb64 = n >= (1ull << 30);
     q.lb_words = q.tiles * (size_t)q.R;
