@@ -54,6 +54,11 @@ constexpr int lsd_items(int kb, int vb, int maxb) {
     if (kb == 4) return vb == 0 ? 28 : (vb == 4 ? 20 : 16);
     return vb == 0 ? 16 : (vb == 8 ? 12 : 8);
 }
+// below this many uint32 keys (keys only) the radix-2^8 rounds take smaller
+// tiles, so that the tiles still outnumber the workgroups the chip holds at
+// once (measured: at 2^20 keys 0.120 ms per sort against 0.142)
+constexpr size_t LSD_SMALL_N = size_t(1) << 23;
+constexpr int LSD_ITEMS_SMALL = 16;
 // 16-bit digit keys carry up to two 8-byte payloads (the learned path moves
 // bucket ids with their keys and values)
 
@@ -560,6 +565,10 @@ hipError_t launch_pass_lb(const LsdPlan& p, const void* src, void* dst, const vo
 template <typename K, int VB>
 hipError_t launch_pass_k(const LsdPlan& p, const void* src, void* dst, const void* vsrc,
                          void* vdst, int pass, unsigned char* ws, hipStream_t st, const Route* route) {
+    if constexpr (sizeof(K) == 4 && VB == 0) {
+        if (p.bits <= 8 && p.tile == NT * LSD_ITEMS_SMALL)
+            return launch_pass_lb<K, VB, 8, LSD_ITEMS_SMALL>(p, src, dst, vsrc, vdst, pass, ws, st, route);
+    }
     if (p.bits <= 8)
         return launch_pass_lb<K, VB, 8, lsd_items(sizeof(K), VB, 8)>(p, src, dst, vsrc, vdst, pass, ws, st, route);
     return launch_pass_lb<K, VB, 11, lsd_items(sizeof(K), VB, 11)>(p, src, dst, vsrc, vdst, pass, ws, st, route);
@@ -619,7 +628,10 @@ bool lsd_plan(size_t n, int kb, int vb, int bits, LsdPlan* p, int vb2) {
     q.passes = (8 * kb + bits - 1) / bits;
     q.R = 1 << bits;
     q.vb2 = vb2;
-    q.tile = NT * (kb == 2 ? 16 : lsd_items(kb, vb, bits <= 8 ? 8 : 11));
+    q.tile = NT * (kb == 2 ? 16
+                           : (kb == 4 && vb == 0 && bits <= 8 && n < LSD_SMALL_N)
+                                 ? LSD_ITEMS_SMALL
+                                 : lsd_items(kb, vb, bits <= 8 ? 8 : 11));
     q.tiles = n ? (n + q.tile - 1) / q.tile : 0;
     q.lb64 = n >= (1ull << 30);
     q.lb_words = q.tiles * (size_t)q.R;
