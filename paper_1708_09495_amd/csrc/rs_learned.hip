@@ -1,25 +1,30 @@
 // rs_learned.hip -- learned-CDF bucket sort (an extension beyond the paper)
 // for uint64 keys with an optional uint64 payload, stable.
 //
-//   1. sample 2^16 keys (with replacement, seeded) and sort the sample with
-//      the LSD rounds; targets are mid-ranks (#{s < k} + #{s <= k}) / 2m;
+//   1. sample 2^18 keys (with replacement, seeded) and sort the sample with
+//      the LSD rounds; every 4th sorted key is a training point with the
+//      mid-rank target (#{s < k} + #{s <= k}) / 2m over the whole sample;
 //   2. train a monotone MLP 1 -> 32 -> 32 -> 1 (weights = softplus of free
 //      parameters, tanh hidden units, sigmoid output) on (feature, target)
-//      with Adam, all steps in one cooperative launch;
-//   3. invert the network into 65535 key splitters: s_j = the least key whose
-//      bucket floor(f(x(key)) * 65536) is at least j (binary search over
-//      keys); a prefix max makes them non-decreasing, so bucket(key) =
-//      #{j : s_j <= key} is monotone in the key by construction;
-//   4. bucket id of every key by a two-level search of the splitters;
+//      with Adam, all steps in one cooperative launch; the feature is by
+//      default the key's place among 4,096 sample quantiles;
+//   3. calibrate the output against the sample at 1,025 knots and invert it
+//      into 65535 key splitters: s_j = the least key whose bucket is at
+//      least j (bisection over keys); a prefix max makes them non-decreasing,
+//      so bucket(key) = #{j : s_j <= key} is monotone in the key by
+//      construction;
+//   4. bucket id of every key: a search tree over the last splitter of every
+//      group of four, breadth-first in LDS, then the group in two loads;
 //   5. two stable radix-2^8 rounds on the 16-bit bucket id carry each key
 //      and value into its bucket, in input order within the bucket;
-//   6. every bucket is sorted stably in LDS (on key - bucket minimum, only
-//      as many 8-bit rounds as the bucket's key range needs); a bucket whose
-//      keys are all equal is already in order; a bucket above the LDS
-//      capacity is recorded as overflowed;
-//   7. overflowed buckets are sorted by the LSD rounds in place; if too many
-//      keys overflowed, or a final check finds the output unsorted, the
-//      whole array is sorted by the LSD rounds from the untouched input.
+//   6. every bucket of up to 6,144 pairs is sorted stably in LDS (on the top
+//      16 bits of key - bucket start, runs tied there by insertion); a bucket
+//      of one key is already in order; crowded and larger buckets are listed;
+//   7. listed buckets: crowded ones ranked on every bit, mid-size ones split
+//      into sub-ranges sorted in LDS by any workgroup, the largest by the LSD
+//      rounds; if too many keys need that, or a final check finds the output
+//      unsorted, the whole array is sorted by the LSD rounds from the
+//      untouched input.
 // Every path ends in the stable sort of the input, so the output does not
 // depend on how well the network fits; the fit only decides the speed.
 #include <math.h>
