@@ -98,11 +98,40 @@ __device__ __forceinline__ uint32_t lane_from(uint32_t v, int src) {
     return (uint32_t)__shfl((int)v, src, WAVE);
 }
 
-// Partner's run, reversed, from a lane of this wave.
+// v of lane (lane ^ J), J known at compile time: DPP quad permutations for
+// J = 1, 2 (no LDS traffic), a swizzle within 32 lanes for J = 4..16, the
+// LDS permute for J = 32.
+template <int J>
+__device__ __forceinline__ uint32_t lane_xor_c(uint32_t v) {
+    if constexpr (J == 1) {
+        return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, false);  // quad_perm 1,0,3,2
+    } else if constexpr (J == 2) {
+        return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xF, 0xF, false);  // quad_perm 2,3,0,1
+    } else if constexpr (J < 32) {
+        return (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, (J << 10) | 0x1F);   // xor J, 32-lane groups
+    } else {
+        return lane_xor(v, J);
+    }
+}
+
+// Partner's run, reversed, from lane (lane ^ J) of this wave.
+template <int N, int J>
+__device__ __forceinline__ void fetch_rev_xor_c(const uint32_t (&a)[N], uint32_t (&b)[N]) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) b[i] = lane_xor_c<J>(a[N - 1 - i]);
+}
+
+// Partner's run, reversed, from a lane of this wave (j < 64, uniform).
 template <int N>
 __device__ __forceinline__ void fetch_rev_xor(const uint32_t (&a)[N], uint32_t (&b)[N], int j) {
-#pragma unroll
-    for (int i = 0; i < N; ++i) b[i] = lane_xor(a[N - 1 - i], j);
+    switch (j) {
+        case 1: fetch_rev_xor_c<N, 1>(a, b); break;
+        case 2: fetch_rev_xor_c<N, 2>(a, b); break;
+        case 4: fetch_rev_xor_c<N, 4>(a, b); break;
+        case 8: fetch_rev_xor_c<N, 8>(a, b); break;
+        case 16: fetch_rev_xor_c<N, 16>(a, b); break;
+        default: fetch_rev_xor_c<N, 32>(a, b); break;
+    }
 }
 
 // Padded blocked layout of the runs in LDS: run t starts at t*(N+1), so that
@@ -190,8 +219,13 @@ __device__ __forceinline__ void oet_sort(const uint32_t* __restrict__ src, uint3
         const int partner = even ? (t ^ 1) : ((t & 1) ? t + 1 : t - 1);
         const bool has = active && partner >= 0 && partner < p;
         const int src_lane = even ? (lane ^ 1) : (((lane & 1) ? lane + 1 : lane - 1) & (WAVE - 1));
+        if (even) {
 #pragma unroll
-        for (int i = 0; i < N; ++i) b[i] = lane_from(a[N - 1 - i], src_lane);
+            for (int i = 0; i < N; ++i) b[i] = lane_xor_c<1>(a[N - 1 - i]);
+        } else {
+#pragma unroll
+            for (int i = 0; i < N; ++i) b[i] = lane_from(a[N - 1 - i], src_lane);
+        }
         if (!even && multiwave) {
             // odd rounds: lanes 63 and 0 pair with the neighbouring wave
             __syncthreads();
