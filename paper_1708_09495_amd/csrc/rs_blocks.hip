@@ -104,8 +104,20 @@ __global__ __launch_bounds__(MS_NT) void k_merge_split(const uint32_t* __restric
     const uint32_t la = x1 - x0, lb = (d1 - x1) - (d0 - x0), L = d1 - d0;
     const uint32_t* __restrict__ A = src + (size_t)a * N + x0;
     const uint32_t* __restrict__ B = src + (size_t)b * N + (d0 - x0);
-    for (uint32_t i = tid; i < la; i += MS_NT) sm[i] = A[i];
-    for (uint32_t i = tid; i < lb; i += MS_NT) sm[la + i] = B[i];
+    // the chunk's L = la + lb inputs, A's slice then B's, all loads in flight
+    {
+        uint32_t v[MS_ITEMS];
+#pragma unroll
+        for (int r = 0; r < MS_ITEMS; ++r) {
+            const uint32_t i = r * MS_NT + tid;
+            v[r] = i < la ? A[i] : (i < L ? B[i - la] : 0u);
+        }
+#pragma unroll
+        for (int r = 0; r < MS_ITEMS; ++r) {
+            const uint32_t i = r * MS_NT + tid;
+            if (i < L) sm[i] = v[r];
+        }
+    }
     __syncthreads();
     uint32_t v[MS_ITEMS];
     const uint32_t dt = tid * MS_ITEMS;
