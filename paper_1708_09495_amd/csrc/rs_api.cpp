@@ -512,13 +512,19 @@ void prof_record(hipStream_t st, int kid, int phase) {
     std::lock_guard<std::mutex> g(g_prof_mu);
     if (phase == 0) {
         Mark m{kid, take_event(), nullptr};
-        if (m.b) hipEventRecord(m.b, st);
+        if (m.b && hipEventRecord(m.b, st) != hipSuccess) {  // left out of the timings
+            g_free_events.push_back(m.b);
+            m.b = nullptr;
+        }
         g_marks.push_back(m);
     } else {
         for (auto it = g_marks.rbegin(); it != g_marks.rend(); ++it) {
             if (it->kid == kid && it->e == nullptr) {
                 it->e = take_event();
-                if (it->e) hipEventRecord(it->e, st);
+                if (it->e && hipEventRecord(it->e, st) != hipSuccess) {
+                    g_free_events.push_back(it->e);
+                    it->e = nullptr;
+                }
                 break;
             }
         }

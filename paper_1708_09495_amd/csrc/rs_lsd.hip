@@ -216,11 +216,12 @@ __global__ __launch_bounds__(HIST_NT) void k_hist(const K* __restrict__ keys, ui
 // wave is the wave's running count for the digit plus the number of peer
 // lanes below it; the highest peer lane advances the running count and
 // clears the slot.
-// Held to 128 registers, so that two workgroups share a compute unit (at
-// the tile sizes above a few spilled registers cost less than half the
-// occupancy).
+// Radix-2^8 rounds are held to 128 registers, so that two workgroups share
+// a compute unit (at the tile sizes above a few spilled registers cost less
+// than half the occupancy); radix-2^11 tiles are held to two workgroups by
+// their LDS anyway.
 template <typename K, int VB, int MAXB, int ITEMS, typename LB, typename OFF, int VB2 = 0>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_onesweep(
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MAXB <= 8 ? 4 : 1))) void k_onesweep(
     const K* __restrict__ kin0, K* __restrict__ kout0, const void* __restrict__ vin0,
     void* __restrict__ vout0, uint64_t n, int shift, int bits, uint32_t* __restrict__ tile_ctr,
     LB* __restrict__ lb, const uint32_t* __restrict__ ghist, uint32_t* __restrict__ status,

@@ -25,13 +25,11 @@ __global__ void k_fill_hash(uint32_t* __restrict__ p, uint64_t n, uint64_t seed)
 
 struct Timer {
     hipEvent_t a = nullptr, b = nullptr;
-    Timer() {
-        hipEventCreate(&a);
-        hipEventCreate(&b);
-    }
+    bool ok = false;
+    Timer() { ok = hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess; }
     ~Timer() {
-        hipEventDestroy(a);
-        hipEventDestroy(b);
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
     }
 };
 
@@ -67,12 +65,11 @@ extern "C" int rs_tune_run(void* ws, size_t ws_bytes, int instances, void* strea
     SegTable& table = tune_table();
     auto time_ms = [&](auto&& launch, int reps) -> double {
         launch();  // warm-up
-        hipEventRecord(tm.a, st);
+        if (!tm.ok || hipEventRecord(tm.a, st) != hipSuccess) return (double)NAN;
         for (int r = 0; r < reps; ++r) launch();
-        hipEventRecord(tm.b, st);
-        if (hipEventSynchronize(tm.b) != hipSuccess) return NAN;
+        if (hipEventRecord(tm.b, st) != hipSuccess || hipEventSynchronize(tm.b) != hipSuccess) return (double)NAN;
         float ms = 0.f;
-        hipEventElapsedTime(&ms, tm.a, tm.b);
+        if (hipEventElapsedTime(&ms, tm.a, tm.b) != hipSuccess) return (double)NAN;
         return (double)ms / reps;
     };
     for (int c = 1; c <= 14; ++c) {
