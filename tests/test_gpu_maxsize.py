@@ -1,0 +1,87 @@
+"""The largest sizes the LSD rounds plan for: 64-bit look-back words (2^30
+keys and up) and 64-bit destinations (2^31 keys and up).  The checks run on
+the device, in chunks, and hold at any size: sorted order; the same multiset
+(a 65,536-bin histogram of the top 16 bits, the sum and the sum of squares
+of the keys modulo 2^64); and, at sampled output positions q,
+#{input < out[q]} <= q < #{input <= out[q]}, which fixes out[q] as the q-th
+smallest key."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+CHUNK = 1 << 27
+
+
+@pytest.fixture(scope="module")
+def rs():
+    import paper_1708_09495_amd as rs
+    rs.lib()
+    return rs
+
+
+def _u(t):
+    """int64 values with the order of the unsigned keys in t (uint32 values,
+    or uint64 bit patterns with the sign bit flipped)."""
+    import torch
+    if t.dtype == torch.int32:
+        return t.to(torch.int64) & 0xFFFFFFFF
+    return t ^ torch.iinfo(torch.int64).min
+
+
+def _chunks(n):
+    return [(s, min(n, s + CHUNK)) for s in range(0, n, CHUNK)]
+
+
+def _sorted(out):
+    n = out.numel()
+    for s, e in _chunks(n):
+        o = _u(out[max(0, s - 1):e])
+        if not bool((o[1:] >= o[:-1]).all()):
+            return False
+    return True
+
+
+def _fingerprint(t, kbits):
+    import torch
+    h = torch.zeros(65536, dtype=torch.int64, device=t.device)
+    s1 = torch.zeros((), dtype=torch.int64, device=t.device)
+    s2 = torch.zeros((), dtype=torch.int64, device=t.device)
+    for s, e in _chunks(t.numel()):
+        u = _u(t[s:e])
+        h += torch.bincount((u >> (kbits - 16)) & 0xFFFF, minlength=65536)
+        v = t[s:e].to(torch.int64)
+        s1 += v.sum()          # int64 sums wrap: modulo 2^64
+        s2 += (v * v).sum()
+    return h, int(s1), int(s2)
+
+
+def _rank_bounds(a, key):
+    lt = le = 0
+    for s, e in _chunks(a.numel()):
+        u = _u(a[s:e])
+        lt += int((u < key).sum())
+        le += int((u <= key).sum())
+    return lt, le
+
+
+@pytest.mark.parametrize("kb,n", [(8, (1 << 30) + 777), (4, (1 << 31) + 12_345)])
+def test_largest_plans(rs, kb, n):
+    import gen
+    import torch
+    print("case max size kb=%d n=%d" % (kb, n), flush=True)
+    a = torch.empty(n, dtype=torch.int32 if kb == 4 else torch.int64, device="cuda")
+    (gen.uniform_u32_dev if kb == 4 else gen.uniform_u64_dev)(gen.S0 + 41, a)
+    sort = rs.rs_sort_u32 if kb == 4 else rs.rs_sort_u64
+    out = sort(a, algo=rs.RS_ALGO_LSD)
+    st = rs.rs_get_stats()
+    assert st.device_error == 0 and st.passes == kb
+    assert _sorted(out)
+    ha, s1a, s2a = _fingerprint(a, 8 * kb)
+    ho, s1o, s2o = _fingerprint(out, 8 * kb)
+    assert torch.equal(ha, ho) and s1a == s1o and s2a == s2o
+    for q in [0, n - 1] + [int(x) for x in np.random.default_rng(41).integers(0, n, 8)]:
+        lt, le = _rank_bounds(a, _u(out[q:q + 1])[0])
+        assert lt <= q < le, q
+    del a, out
+    torch.cuda.empty_cache()
