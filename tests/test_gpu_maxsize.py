@@ -85,3 +85,35 @@ def test_largest_plans(rs, kb, n):
         assert lt <= q < le, q
     del a, out
     torch.cuda.empty_cache()
+
+
+def test_largest_kv_plan(rs):
+    """Key-value at 2^31 + 4,321 uint32 keys with the index as uint32 payload:
+    keys sorted, payload a permutation of 0..n-1, out key == in key at the
+    payload, payload increasing inside each run of equal keys -- together the
+    stable sort."""
+    import gen
+    import torch
+    n = (1 << 31) + 4_321
+    print("case max size kv n=%d" % n, flush=True)
+    k = torch.empty(n, dtype=torch.int32, device="cuda")
+    gen.uniform_u32_dev(gen.S0 + 42, k)
+    k &= 0x00FFFFFF                       # many equal keys, so tie order matters
+    v = torch.empty(n, dtype=torch.int32, device="cuda")
+    gen.iota_dev(v)
+    ko, vo = rs.rs_sort_kv(k, v, algo=rs.RS_ALGO_LSD)
+    st = rs.rs_get_stats()
+    assert st.device_error == 0
+    assert _sorted(ko)
+    seen = torch.zeros(n, dtype=torch.bool, device="cuda")
+    for s, e in _chunks(n):
+        idx = vo[s:e].to(torch.int64) & 0xFFFFFFFF
+        seen[idx] = True
+        assert torch.equal(k[idx], ko[s:e])
+        e2 = min(n, e + 1)
+        kk, vv = _u(ko[s:e2]), vo[s:e2].to(torch.int64) & 0xFFFFFFFF
+        tie = kk[1:] == kk[:-1]
+        assert bool((vv[1:][tie] > vv[:-1][tie]).all())
+    assert bool(seen.all())
+    del k, v, ko, vo, seen
+    torch.cuda.empty_cache()
