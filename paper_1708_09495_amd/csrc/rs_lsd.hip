@@ -35,6 +35,7 @@ constexpr int NW = NT / WAVE;    // waves per workgroup
 constexpr int HIST_NT = 256;
 constexpr uint32_t FLAG_AGG = 1, FLAG_PRE = 2;
 constexpr int LBWIN = 4;         // predecessors read per look-back step
+constexpr int RANK_GL = 16;      // lanes per ranking group at radix <= 2^8 (16 or 32)
 
 template <typename LB> struct LBW;
 template <> struct LBW<uint32_t> {
@@ -206,16 +207,21 @@ __global__ __launch_bounds__(HIST_NT) void k_hist(const K* __restrict__ keys, ui
 //   LB    : look-back word type (32-bit while n < 2^30)
 //   OFF   : int32_t destinations while n < 2^31, else int64_t
 //
-// Ranking.  Keys are visited in input order: item i of lane l of wave w is
-// tile position w*64*ITEMS + i*64 + l.  For each item the lanes holding the
-// same digit are found with an LDS match: every lane ORs its lane bit into
-// its wave's slot for the low 8 digit bits, then reads the slot back; OR is
-// order-independent, so the mask is exact and the ranking stable whatever
-// order the LDS serves the atomics in.  Digit bits above the low 8 (b > 8)
-// are matched with one ballot each.  A key's rank among equal digits of its
-// wave is the wave's running count for the digit plus the number of peer
-// lanes below it; the highest peer lane advances the running count and
-// clears the slot.
+// Ranking.  Keys are visited in input order within ranking groups of GL
+// lanes: item i of lane l of group g is tile position g*GL*ITEMS + i*GL + l.
+// For each item the lanes holding the same digit are found with an LDS
+// match: every lane ORs its lane bit into its group's slot for the digit,
+// then reads the slot back; OR is order-independent, so the mask is exact
+// and the ranking stable whatever order the LDS serves the atomics in.  A
+// key's rank among equal digits of its group is the group's running count
+// for the digit plus the number of peer lanes below it; the highest peer
+// lane stores the advanced count and a cleared mask.
+//   radix <= 2^8: groups of RANK_GL = 16 lanes; a slot is one 32-bit word,
+//     mask in the low half and running count in the high half, so each item
+//     costs one OR, one read and one store of 4 bytes per lane.
+//   radix 2^9..2^11: whole waves; 64-bit masks for the low 8 digit bits,
+//     the bits above matched with one ballot each, and 16-bit counters per
+//     wave and digit.
 // Radix-2^8 rounds are held to 128 registers, so that two workgroups share
 // a compute unit (at the tile sizes above a few spilled registers cost less
 // than half the occupancy); radix-2^11 tiles are held to two workgroups by
@@ -232,10 +238,19 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MAXB <= 8 ? 
     constexpr int RLO = RMAX < 256 ? RMAX : 256;      // slots of the LDS match
     constexpr int T = NT * ITEMS;
     constexpr int PER = (RMAX + NT - 1) / NT;  // digits per thread in the digit scans
+    // Radix <= 2^8: keys are ranked in groups of 32 lanes (half a wave), and
+    // a digit's slot holds the group's 32-lane match mask in its low word and
+    // the group's running count of the digit in its high word.  Wider radices
+    // rank whole waves, with 16-bit counters beside the 64-lane masks.
+    constexpr bool HALF = MAXB <= 8;
+    constexpr int GL = HALF ? RANK_GL : WAVE;  // lanes per ranking group
+    constexpr int NG = NT / GL;                // ranking groups per workgroup
+    using Slot = typename std::conditional<(HALF && GL <= 16), uint32_t, uint64_t>::type;
+    constexpr int CSH = (int)sizeof(Slot) * 4;  // count field of a slot
     constexpr size_t KEYB = (size_t)T * sizeof(K);
     constexpr size_t VALB = (size_t)T * (VB > VB2 ? VB : VB2);
-    constexpr size_t CNTB = (size_t)NW * RMAX * sizeof(uint16_t);
-    constexpr size_t MSKB = (size_t)NW * RLO * sizeof(uint64_t);
+    constexpr size_t CNTB = HALF ? 0 : (size_t)NW * RMAX * sizeof(uint16_t);
+    constexpr size_t MSKB = (size_t)NG * RLO * sizeof(Slot);
     constexpr size_t RANKB = CNTB + MSKB;
     // values get an LDS buffer of their own (and are placed before the
     // look-back) when keys and values fit in 64 KiB together; otherwise
@@ -253,8 +268,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MAXB <= 8 ? 
     __shared__ uint32_t wsum[NW + 1];
     __shared__ uint32_t s_tile;
 
-    uint64_t* wmask = reinterpret_cast<uint64_t*>(u_raw);          // [NW][RLO]
-    uint16_t* wcnt = reinterpret_cast<uint16_t*>(u_raw + MSKB);    // [NW][R]
+    uint64_t* wmask = reinterpret_cast<uint64_t*>(u_raw);          // [NG][RLO]
+    uint16_t* wcnt = reinterpret_cast<uint16_t*>(u_raw + MSKB);    // [NW][R] (wide radices)
+    Slot* gslot = reinterpret_cast<Slot*>(u_raw);                 // [NG][RLO] (radix <= 2^8)
     K* skeys = reinterpret_cast<K*>(u_raw);
     V* svals = reinterpret_cast<V*>(SEPV ? v_raw : u_raw);
 
@@ -290,8 +306,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MAXB <= 8 ? 
     const uint32_t lomask = (1u << lob) - 1;
 
     if (tid == 0) s_tile = atomicAdd(tile_ctr, 1u);
-    for (int i = tid; i < NW * R; i += NT) wcnt[i] = 0;
-    for (int i = tid; i < NW * RLO; i += NT) wmask[i] = 0;
+    if constexpr (!HALF)
+        for (int i = tid; i < NW * R; i += NT) wcnt[i] = 0;
+    for (int i = tid; i < (int)(MSKB / 8); i += NT) wmask[i] = 0;
     __syncthreads();
     const uint32_t tile = s_tile;
     const uint64_t base = (uint64_t)tile * T;
@@ -304,14 +321,16 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MAXB <= 8 ? 
     //      the last LDS slots and never shifts a real key)
     K k[ITEMS];
     V v[VB ? ITEMS : 1];
-    const uint32_t wb = wave * (ITEMS * WAVE) + lane;
+    // item i of lane l of ranking group g is tile position g*GL*ITEMS + i*GL + l
+    const uint32_t grp = tid / GL, gl = tid % GL;
+    const uint32_t wb = grp * (ITEMS * GL) + gl;
     if (full) {
 #pragma unroll
-        for (int i = 0; i < ITEMS; ++i) k[i] = tin[wb + i * WAVE];
+        for (int i = 0; i < ITEMS; ++i) k[i] = tin[wb + i * GL];
     } else {
 #pragma unroll
         for (int i = 0; i < ITEMS; ++i) {
-            const uint32_t j = wb + i * WAVE;
+            const uint32_t j = wb + i * GL;
             k[i] = j < nvalid ? tin[j] : KeyMax<K>::v;
         }
     }
@@ -319,14 +338,36 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MAXB <= 8 ? 
         const V* __restrict__ vtin = vin + base;
 #pragma unroll
         for (int i = 0; i < ITEMS; ++i) {
-            const uint32_t j = wb + i * WAVE;
+            const uint32_t j = wb + i * GL;
             v[i] = (full || j < nvalid) ? vtin[j] : V(0);
         }
     }
 
     // ---- rank
-    uint32_t dr[ITEMS];  // digit | rank-in-wave << 16
-    {
+    uint32_t dr[ITEMS];  // digit | rank-in-group << 16
+    if constexpr (HALF) {
+        Slot* wm = gslot + grp * RLO;
+        const uint32_t mybit = 1u << gl;
+        const uint32_t below = mybit - 1u;
+        constexpr uint32_t MMASK = GL >= 32 ? ~0u : (1u << GL) - 1u;
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+            const uint32_t d = (uint32_t)(k[i] >> shift) & dmask;
+            Slot* slot = wm + d;
+            // the mask field is the slot's low 32-bit word (the whole slot
+            // when slots are 32-bit)
+            atomicOr(reinterpret_cast<uint32_t*>(slot), mybit);
+            const Slot sv = __hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            const uint32_t m = (uint32_t)sv & MMASK;
+            const uint32_t c = (uint32_t)(sv >> CSH);
+            const uint32_t lt = (uint32_t)__popc(m & below);
+            const uint32_t cnt = (uint32_t)__popc(m);
+            if (lt + 1 == cnt)
+                __hip_atomic_store(slot, (Slot)((Slot)(c + cnt) << CSH), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_WORKGROUP);
+            dr[i] = d | ((c + lt) << 16);
+        }
+    } else {
         uint16_t* wc = wcnt + wave * R;
         uint64_t* wm = wmask + wave * RLO;
         const uint64_t mybit = 1ull << lane;
@@ -360,8 +401,13 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MAXB <= 8 ? 
             const int d = tid * PER + q;
             uint32_t t = 0;
             if (d < R) {
+                if constexpr (HALF) {
 #pragma unroll
-                for (int w = 0; w < NW; ++w) t += wcnt[w * R + d];
+                    for (int g = 0; g < NG; ++g) t += (uint32_t)(gslot[g * RLO + d] >> CSH);
+                } else {
+#pragma unroll
+                    for (int w = 0; w < NW; ++w) t += wcnt[w * R + d];
+                }
                 tot[d] = t;
                 if (tile != 0)
                     st_agent(&lb[(size_t)tile * R + d], (LB)(((LB)FLAG_AGG << LBW<LB>::SH) | (LB)t));
@@ -377,11 +423,20 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MAXB <= 8 ? 
             if (d < R) {
                 loc[d] = ex;
                 uint32_t run = ex;
+                if constexpr (HALF) {
 #pragma unroll
-                for (int w = 0; w < NW; ++w) {
-                    const uint32_t c = wcnt[w * R + d];
-                    wcnt[w * R + d] = (uint16_t)run;
-                    run += c;
+                    for (int g = 0; g < NG; ++g) {
+                        const uint32_t c = (uint32_t)(gslot[g * RLO + d] >> CSH);
+                        gslot[g * RLO + d] = (Slot)((Slot)run << CSH);
+                        run += c;
+                    }
+                } else {
+#pragma unroll
+                    for (int w = 0; w < NW; ++w) {
+                        const uint32_t c = wcnt[w * R + d];
+                        wcnt[w * R + d] = (uint16_t)run;
+                        run += c;
+                    }
                 }
             }
             ex += part[q];
@@ -394,7 +449,10 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MAXB <= 8 ? 
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
         const uint32_t d = dr[i] & 0xFFFFu;
-        dr[i] = wcnt[wave * R + d] + (dr[i] >> 16);
+        if constexpr (HALF)
+            dr[i] = (uint32_t)(gslot[grp * RLO + d] >> CSH) + (dr[i] >> 16);
+        else
+            dr[i] = wcnt[wave * R + d] + (dr[i] >> 16);
     }
     __syncthreads();  // the counters share LDS with the key buffer
 #pragma unroll
@@ -522,7 +580,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MAXB <= 8 ? 
         V2 w[ITEMS];
 #pragma unroll
         for (int i = 0; i < ITEMS; ++i) {
-            const uint32_t j = wb + i * WAVE;
+            const uint32_t j = wb + i * GL;
             w[i] = (full || j < nvalid) ? v2in[j] : V2(0);
         }
         __syncthreads();
