@@ -11,7 +11,7 @@ by SplitMix64, radix 2^8, with the input already resident in HBM.
                   [--workload lsd|small|segmented|learned|blocks]
                   lsd:       [--log2n 28] [--radix-bits 8|11|16] [--key-bytes 4|8] [--kv]
                   small:     [--small-n 4096] [--algo btn|oet|lds_radix|auto] [--p P]
-                  blocks:    [--log2n 27] [--algo btn|oet] [--p 256]
+                  blocks:    [--log2n 27] [--algo btn|oet] [--p P] (0: the MBSP model's p)
                   learned:   [--dist zipf|lognormal|mixture]
 
 The roofline object covers the dominant kernel of the workload: its
@@ -498,7 +498,7 @@ def bench_blocks(args, torch, rs, gen, np):
     n = 1 << args.log2n
     name = "oet" if args.algo == "oet" else "btn"
     algo = rs.RS_ALGO_OET if name == "oet" else rs.RS_ALGO_BTN
-    p = args.p if args.p else 256
+    p = args.p if args.p else rs.rs_blocks_default_p(n, algo)  # the MBSP model's p
     keys = torch.empty(n, dtype=torch.int32, device="cuda")
     gen.uniform_u32_dev(gen.S0 + 2, keys)
     out = torch.empty_like(keys)

@@ -136,12 +136,42 @@ rs_status rs_sort_segmented(const uint32_t* in, uint32_t* out, const int64_t* of
  * ties taken from the lower-indexed run) and each stage one pass over all
  * keys in device memory.  The first n keys of the result are written to
  * `out`.  algo RS_ALGO_BTN (p a power of two) or RS_ALGO_OET; p in
- * [2, 4096] with p * N < 2^32, 0 = default (256, fewer for n < 16,384).
+ * [2, 4096] with p * N < 2^32, 0 = rs_blocks_default_p(n, algo).
  * Layout: dense arrays of n keys; `in == out` is allowed.  Workspace:
  * rs_workspace_bytes(RS_OP_BLOCKS, n, 4, 0, 0, algo, p) (two padded copies
  * of the keys).  rs_get_stats reports p and the stage count. */
 rs_status rs_sort_blocks_u32(const uint32_t* in, uint32_t* out, size_t n, rs_algo algo, int p,
                              void* ws, size_t ws_bytes, void* stream);
+
+/* The MBSP cost model that picks p for the block networks at device scale
+ * (Section 3, Eqs. TbG and ToG, with a processor read as a workgroup).  For
+ * n keys on p runs of N = ceil(n/p) keys, in nanoseconds:
+ *   T(p) = local_ns_per_key * N * ceil(p / resident_runs)
+ *        + stages(p) * (stage_ps_per_key * 1e-3 * p * N + stage_fixed_us * 1e3)
+ * with stages(p) = lg p (lg p + 1)/2 (BTN) or p (OET).  local_ns_per_key is
+ * the paper's 68 G, one workgroup's radix sort of its run; unlike the
+ * paper's 4 (n/p) g, a merge-split stage runs on every compute unit, so it
+ * costs per key of the whole array.  The defaults are one MI355X's
+ * calibration (local 3.74 ns, stage 1.88 ps per key + 28 us, 512 resident
+ * workgroups); `bench.py --workload blocks --mbsp` measures G and g. */
+typedef struct {
+    double local_ns_per_key;   /* > 0                                        */
+    double stage_ps_per_key;   /* >= 0                                       */
+    double stage_fixed_us;     /* >= 0                                       */
+    int32_t resident_runs;     /* >= 1: runs sorted at once                  */
+} rs_block_model;
+
+/* Replaces the model (host, process-wide, not thread-safe against
+ * concurrent sorts); RS_ERR_INVALID for NULL or values out of range. */
+rs_status rs_blocks_set_model(const rs_block_model* m);
+
+/* Copies the current model to `out` (host); RS_ERR_INVALID for NULL. */
+rs_status rs_blocks_get_model(rs_block_model* out);
+
+/* The p that p = 0 selects for n keys: the p minimising T(p) among
+ * 2 <= p <= min(4096, n/64) (p = 2 when n < 128), powers of two only for
+ * BTN, the smaller on a tie.  0 for n = 0 or an algo other than BTN/OET. */
+int32_t rs_blocks_default_p(size_t n, rs_algo algo);
 
 /* Bytes of workspace the call (op, n, ...) needs.  For RS_OP_BATCH, n is
  * the array length and num_segments the count; for RS_OP_SEGMENTED, n is

@@ -18,7 +18,7 @@ RS_ALGO_AUTO, RS_ALGO_LSD, RS_ALGO_BTN, RS_ALGO_OET, RS_ALGO_LEARNED, RS_ALGO_LD
 RS_OP_SORT, RS_OP_SORT_KV, RS_OP_BATCH, RS_OP_SEGMENTED, RS_OP_TUNE, RS_OP_BLOCKS = range(6)
 
 EXPORTS = ["rs_sort_u32", "rs_sort_u64", "rs_sort_kv", "rs_sort_batch_u32", "rs_sort_segmented",
-           "rs_sort_blocks_u32",
+           "rs_sort_blocks_u32", "rs_blocks_set_model", "rs_blocks_get_model", "rs_blocks_default_p",
            "rs_workspace_bytes", "rs_small_capacity", "rs_status_string", "rs_get_stats",
            "rs_tune_set", "rs_tune_get", "rs_tune_run", "rs_profile_enable", "rs_profile_read",
            "rs_learned_set_opts", "rs_learned_get_opts", "rs_mlp_num_params", "rs_mlp_forward",
@@ -45,6 +45,11 @@ class rs_stats(ctypes.Structure):
                 ("keys_overflowed", ctypes.c_int64), ("train_loss", ctypes.c_double),
                 ("device_error", ctypes.c_uint32), ("hip_error", ctypes.c_int32),
                 ("passes_skipped", ctypes.c_int32)]
+
+
+class rs_block_model(ctypes.Structure):
+    _fields_ = [("local_ns_per_key", ctypes.c_double), ("stage_ps_per_key", ctypes.c_double),
+                ("stage_fixed_us", ctypes.c_double), ("resident_runs", ctypes.c_int32)]
 
 
 class rs_tune_entry(ctypes.Structure):
@@ -91,6 +96,10 @@ def lib():
         L.rs_sort_batch_u32.argtypes = [vp, vp, sz, sz, i, i, vp, sz, vp]
         L.rs_sort_segmented.argtypes = [vp, vp, vp, sz, ctypes.c_int64, i, vp, sz, vp]
         L.rs_sort_blocks_u32.argtypes = [vp, vp, sz, i, i, vp, sz, vp]
+        L.rs_blocks_set_model.argtypes = [ctypes.POINTER(rs_block_model)]
+        L.rs_blocks_get_model.argtypes = [ctypes.POINTER(rs_block_model)]
+        L.rs_blocks_default_p.argtypes = [sz, i]
+        L.rs_blocks_default_p.restype = ctypes.c_int32
         L.rs_workspace_bytes.argtypes = [i, sz, i, i, i, i, sz]
         L.rs_workspace_bytes.restype = sz
         L.rs_small_capacity.argtypes = [i]
@@ -185,6 +194,23 @@ def rs_tune_set(entries):
     for k, (c, a, p) in enumerate(entries):
         arr[k].size_log2, arr[k].algo, arr[k].p = c, a, p
     _call(lib().rs_tune_set(arr, len(entries)), "rs_tune_set")
+
+
+def rs_blocks_get_model():
+    """The MBSP cost model that picks p for the device-scale networks, as a dict."""
+    m = rs_block_model()
+    _call(lib().rs_blocks_get_model(ctypes.byref(m)), "rs_blocks_get_model")
+    return {k: getattr(m, k) for k, _ in rs_block_model._fields_}
+
+
+def rs_blocks_set_model(local_ns_per_key, stage_ps_per_key, stage_fixed_us, resident_runs):
+    m = rs_block_model(local_ns_per_key, stage_ps_per_key, stage_fixed_us, resident_runs)
+    _call(lib().rs_blocks_set_model(ctypes.byref(m)), "rs_blocks_set_model")
+
+
+def rs_blocks_default_p(n, algo):
+    """The p that p = 0 selects for n keys (0 for n = 0 or an algo other than BTN/OET)."""
+    return int(lib().rs_blocks_default_p(n, algo))
 
 
 def rs_tune_get():

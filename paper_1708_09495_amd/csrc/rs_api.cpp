@@ -2,6 +2,7 @@
 // include/rs.h): argument checks, planning, workspace checks and dispatch to
 // the kernels' launchers.  Nothing here waits on the device except
 // rs_get_stats.
+#include <cmath>
 #include <string.h>
 
 #include "../../include/rs_learned.h"
@@ -201,7 +202,7 @@ rs_status sort_keys_common(const void* kin, void* kout, const void* vin, void* v
             if (kb != 4 || vb != 0) return RS_ERR_UNSUPPORTED;
             if (algo != RS_ALGO_LDS_RADIX && n > SMALL_CAP_U32)
                 return sort_blocks(static_cast<const uint32_t*>(kin), static_cast<uint32_t*>(kout), n, algo,
-                                   block_default_p(n), ws, ws_bytes, st);
+                                   block_default_p(n, algo), ws, ws_bytes, st);
             return sort_small(static_cast<const uint32_t*>(kin), static_cast<uint32_t*>(kout), n, 1,
                               algo, 0, st);
         default:
@@ -253,8 +254,29 @@ rs_status rs_sort_blocks_u32(const uint32_t* in, uint32_t* out, size_t n, rs_alg
         begin_call(algo);
         return RS_OK;
     }
-    const uint32_t pp = p ? (uint32_t)p : block_default_p(n);
+    const uint32_t pp = p ? (uint32_t)p : block_default_p(n, algo);
     return sort_blocks(in, out, n, algo, pp, ws, ws_bytes, static_cast<hipStream_t>(stream));
+}
+
+rs_status rs_blocks_set_model(const rs_block_model* m) {
+    if (!m) return RS_ERR_INVALID;
+    const bool ok = std::isfinite(m->local_ns_per_key) && std::isfinite(m->stage_ps_per_key) &&
+                    std::isfinite(m->stage_fixed_us) && m->local_ns_per_key > 0.0 &&
+                    m->stage_ps_per_key >= 0.0 && m->stage_fixed_us >= 0.0 && m->resident_runs >= 1;
+    if (!ok) return RS_ERR_INVALID;
+    block_model_set(*m);
+    return RS_OK;
+}
+
+rs_status rs_blocks_get_model(rs_block_model* out) {
+    if (!out) return RS_ERR_INVALID;
+    *out = block_model();
+    return RS_OK;
+}
+
+int32_t rs_blocks_default_p(size_t n, rs_algo algo) {
+    if ((algo != RS_ALGO_BTN && algo != RS_ALGO_OET) || n == 0) return 0;
+    return (int32_t)block_default_p(n, algo);
 }
 
 rs_status rs_sort_batch_u32(const uint32_t* in, uint32_t* out, size_t n, size_t count, rs_algo algo,
@@ -314,7 +336,7 @@ size_t rs_workspace_bytes(int op, size_t n, int key_bytes, int val_bytes, int ra
         if ((algo == RS_ALGO_BTN || algo == RS_ALGO_OET) && op == RS_OP_SORT && key_bytes == 4 &&
             n > SMALL_CAP_U32) {
             BlockPlan bp;
-            return block_plan(n, algo, block_default_p(n), &bp) ? bp.total : 0;
+            return block_plan(n, algo, block_default_p(n, algo), &bp) ? bp.total : 0;
         }
         if (algo == RS_ALGO_BTN || algo == RS_ALGO_OET || algo == RS_ALGO_LDS_RADIX) return ALIGN;
         if (algo == RS_ALGO_LEARNED && key_bytes == 8) {
@@ -337,7 +359,7 @@ size_t rs_workspace_bytes(int op, size_t n, int key_bytes, int val_bytes, int ra
     if (op == RS_OP_TUNE) return (n >= 1 && n <= 65536) ? tune_ws_bytes((int)n) : 0;
     if (op == RS_OP_BLOCKS) {
         if (key_bytes != 4 || n == 0 || num_segments > 4096) return n == 0 ? ALIGN : 0;
-        const uint32_t p = num_segments ? (uint32_t)num_segments : block_default_p(n);
+        const uint32_t p = num_segments ? (uint32_t)num_segments : block_default_p(n, algo);
         BlockPlan bp;
         return block_plan(n, algo, p, &bp) ? bp.total : 0;
     }

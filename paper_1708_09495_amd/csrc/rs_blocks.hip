@@ -153,11 +153,43 @@ uint32_t log2u(uint32_t p) {
 
 }  // namespace
 
-uint32_t block_default_p(size_t n) {
-    // one run per compute unit, but at least 64 keys per run
-    uint32_t p = 256;
-    while (p > 2 && (uint64_t)p * 64 > n) p >>= 1;
-    return p;
+// The MBSP cost model of the device-scale networks (Section 3, Eqs. TbG and
+// ToG, a processor read as a workgroup).  Defaults: the calibration on one
+// MI355X by the BTN runs themselves -- a run's radix sort costs 68 G per key
+// with G = 55 ps (stable for runs of 2^19 to 2^23 keys), and a merge-split
+// stage, spread over the whole device, 1.88 ps per key of the array plus
+// 28 us (fitted on 2^23, 2^25 and 2^27 keys); 512 workgroups resident.
+static rs_block_model g_block_model = {3.74, 1.88, 28.0, 512};
+
+const rs_block_model& block_model() { return g_block_model; }
+void block_model_set(const rs_block_model& m) { g_block_model = m; }
+
+double block_model_ns(const rs_block_model& m, size_t n, int algo, uint32_t p) {
+    const double N = (double)((n + p - 1) / p);
+    const double waves = (double)((p + (uint32_t)m.resident_runs - 1) / (uint32_t)m.resident_runs);
+    const double local = m.local_ns_per_key * N * waves;
+    const double stage = m.stage_ps_per_key * 1e-3 * (double)p * N + m.stage_fixed_us * 1e3;
+    return local + (double)block_stages(algo, p) * stage;
+}
+
+uint32_t block_default_p(size_t n, int algo) {
+    // candidates: 2 <= p <= 4096, at least 64 keys per run (p = 2 always),
+    // powers of two for BTN; the model's minimum, the smaller p on a tie
+    uint64_t pmax = n / 64;
+    if (pmax > 4096) pmax = 4096;
+    if (pmax < 2) pmax = 2;
+    const rs_block_model& m = block_model();
+    uint32_t best = 2;
+    double tbest = block_model_ns(m, n, algo, 2);
+    for (uint32_t p = 3; p <= pmax; ++p) {
+        if (algo == RS_ALGO_BTN && (p & (p - 1))) continue;
+        const double t = block_model_ns(m, n, algo, p);
+        if (t < tbest) {
+            tbest = t;
+            best = p;
+        }
+    }
+    return best;
 }
 
 bool block_plan(size_t n, int algo, uint32_t p, BlockPlan* bp) {

@@ -139,7 +139,11 @@ struct BlockPlan {
     SegPlan seg;        // the runs' local sorts
     size_t off_seg = 0, off_off = 0, off_x = 0, off_y = 0, off_cr = 0, total = 0;
 };
-uint32_t block_default_p(size_t n);
+// p for p = 0: the minimum of the MBSP cost model over the valid p
+uint32_t block_default_p(size_t n, int algo);
+const rs_block_model& block_model();
+void block_model_set(const rs_block_model& m);
+double block_model_ns(const rs_block_model& m, size_t n, int algo, uint32_t p);
 bool block_plan(size_t n, int algo, uint32_t p, BlockPlan* bp);
 int64_t block_stages(int algo, uint32_t p);
 rs_status block_run(const BlockPlan& bp, int algo, const uint32_t* in, uint32_t* out, size_t n,

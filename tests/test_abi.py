@@ -90,7 +90,10 @@ def test_block_network_queries_and_errors(lib):
     assert lib.rs_workspace_bytes(5, n, 4, 0, 0, 2, 8192) == 0    # p above 4096
     assert lib.rs_workspace_bytes(5, n, 8, 0, 0, 2, 256) == 0     # uint32 keys only
     assert lib.rs_workspace_bytes(5, n, 4, 0, 0, 1, 256) == 0     # BTN or OET only
-    assert lib.rs_workspace_bytes(5, n, 4, 0, 0, 2, 0) == lib.rs_workspace_bytes(5, n, 4, 0, 0, 2, 256)
+    lib.rs_blocks_default_p.restype = ctypes.c_int32
+    lib.rs_blocks_default_p.argtypes = [sz, ctypes.c_int]
+    pd = lib.rs_blocks_default_p(n, 2)
+    assert lib.rs_workspace_bytes(5, n, 4, 0, 0, 2, 0) == lib.rs_workspace_bytes(5, n, 4, 0, 0, 2, pd)
     # rs_sort_u32 with BTN above one workgroup's capacity takes the same path
     assert lib.rs_workspace_bytes(0, n, 4, 0, 0, 2, 0) == lib.rs_workspace_bytes(5, n, 4, 0, 0, 2, 0)
     assert lib.rs_workspace_bytes(0, 1000, 4, 0, 0, 2, 0) == 256
@@ -101,3 +104,67 @@ def test_block_network_queries_and_errors(lib):
     assert lib.rs_sort_blocks_u32(vp(256), vp(4096), 10, 3, 5000, None, 0, None) == 1
     assert lib.rs_sort_blocks_u32(vp(256), vp(4096), 10, 1, 4, None, 0, None) == 2  # LSD
     assert lib.rs_sort_blocks_u32(None, None, 0, 2, 0, None, 0, None) == 0
+
+
+class _Model(ctypes.Structure):
+    _fields_ = [("local_ns_per_key", ctypes.c_double), ("stage_ps_per_key", ctypes.c_double),
+                ("stage_fixed_us", ctypes.c_double), ("resident_runs", ctypes.c_int32)]
+
+
+def _model_ns(m, n, algo, p):
+    """T(p) as include/rs.h states it (ns)."""
+    N = -(-n // p)
+    waves = -(-p // m.resident_runs)
+    lg = p.bit_length() - 1
+    stages = lg * (lg + 1) // 2 if algo == 2 else p
+    return (m.local_ns_per_key * N * waves
+            + stages * (m.stage_ps_per_key * 1e-3 * p * N + m.stage_fixed_us * 1e3))
+
+
+def test_block_model_default_p(lib):
+    """p = 0 of the device-scale networks: the minimum of the MBSP cost model
+    (Section 3, Eqs. TbG and ToG) over the valid p, by brute force here."""
+    lib.rs_blocks_default_p.restype = ctypes.c_int32
+    lib.rs_blocks_default_p.argtypes = [ctypes.c_size_t, ctypes.c_int]
+    lib.rs_blocks_get_model.argtypes = [ctypes.POINTER(_Model)]
+    lib.rs_blocks_set_model.argtypes = [ctypes.POINTER(_Model)]
+    dflt = _Model()
+    assert lib.rs_blocks_get_model(ctypes.byref(dflt)) == 0
+    assert (dflt.local_ns_per_key, dflt.stage_ps_per_key, dflt.stage_fixed_us, dflt.resident_runs) == \
+        (3.74, 1.88, 28.0, 512)
+    BTN, OET = 2, 3
+    try:
+        models = [dflt, _Model(10.0, 0.5, 5.0, 64), _Model(1.0, 20.0, 100.0, 4096)]
+        for m in models:
+            assert lib.rs_blocks_set_model(ctypes.byref(m)) == 0
+            for n in (100, 1000, 70_001, 1 << 20, 12_345_678, 1 << 27, 3 << 29):
+                for algo in (BTN, OET):
+                    p = lib.rs_blocks_default_p(n, algo)
+                    pmax = max(2, min(4096, n // 64))
+                    cands = [q for q in range(2, pmax + 1) if algo == OET or q & (q - 1) == 0]
+                    assert p in cands, (n, algo, p)
+                    t = [_model_ns(m, n, algo, q) for q in cands]
+                    best = cands[min(range(len(cands)), key=lambda i: (t[i], cands[i]))]
+                    assert abs(_model_ns(m, n, algo, p) - t[cands.index(best)]) <= 1e-9 * t[cands.index(best)], \
+                        (n, algo, p, best)
+        # the balance the model strikes: OET's optimum grows like sqrt(local / stage)
+        assert lib.rs_blocks_set_model(ctypes.byref(_Model(1.0, 1e6, 0.0, 512))) == 0
+        assert lib.rs_blocks_default_p(1 << 24, OET) == 2 and lib.rs_blocks_default_p(1 << 24, BTN) == 2
+        assert lib.rs_blocks_set_model(ctypes.byref(_Model(1e6, 0.0, 0.0, 1 << 30))) == 0
+        assert lib.rs_blocks_default_p(1 << 24, OET) == 4096 and lib.rs_blocks_default_p(1 << 24, BTN) == 4096
+        # ceil(10000/p) = 65 for p = 154..156: the smaller p of a tie
+        assert lib.rs_blocks_default_p(10_000, OET) == 154 and lib.rs_blocks_default_p(10_000, BTN) == 128
+        # out-of-range models are refused and leave the model as it was
+        cur = _Model()
+        lib.rs_blocks_get_model(ctypes.byref(cur))
+        for bad in (_Model(0.0, 1.0, 1.0, 1), _Model(1.0, -1.0, 1.0, 1), _Model(1.0, 1.0, -1.0, 1),
+                    _Model(float("nan"), 1.0, 1.0, 1), _Model(1.0, float("inf"), 1.0, 1),
+                    _Model(1.0, 1.0, 1.0, 0)):
+            assert lib.rs_blocks_set_model(ctypes.byref(bad)) == 1
+        assert lib.rs_blocks_set_model(None) == 1 and lib.rs_blocks_get_model(None) == 1
+        after = _Model()
+        lib.rs_blocks_get_model(ctypes.byref(after))
+        assert bytes(after) == bytes(cur)
+        assert lib.rs_blocks_default_p(0, OET) == 0 and lib.rs_blocks_default_p(1000, 1) == 0
+    finally:
+        assert lib.rs_blocks_set_model(ctypes.byref(dflt)) == 0

@@ -68,21 +68,25 @@ def test_structured(rs, orc, case):
         _check(out, ref, "%s %s" % (case, algo))
 
 
-def test_default_p_and_sort_entry(rs, orc):
+@pytest.mark.parametrize("n", [500_000, (1 << 23) + 5])
+def test_default_p_and_sort_entry(rs, orc, n):
+    """p = 0 takes the MBSP model's p (OET's is not a power of two here)."""
     import gen
-    n = 500_000
     a = gen.uniform_u32(gen.S0 + 33, n)
     ref = orc.lsd(a, 8)
     for algo in ("BTN", "OET"):
         code = getattr(rs, "RS_ALGO_" + algo)
-        print("case blocks default p %s" % algo, flush=True)
+        p = rs.rs_blocks_default_p(n, code)
+        assert 2 <= p <= 4096
+        print("case blocks default p %s n=%d p=%d" % (algo, n, p), flush=True)
         out = to_host(rs.rs_sort_blocks_u32(to_dev(a), algo=code), np.uint32)
-        assert rs.rs_get_stats().runs_p == 256
+        assert rs.rs_get_stats().runs_p == p
         _check(out, ref, "blocks default " + algo)
         # rs_sort_u32 with BTN / OET above one workgroup's capacity
         out = to_host(rs.rs_sort_u32(to_dev(a), algo=code), np.uint32)
         st = rs.rs_get_stats()
-        assert st.runs_p == 256 and st.network_stages == _stages(algo, 256)
+        assert st.runs_p == p and st.network_stages == _stages(algo, p)
+        assert st.device_error == 0
         _check(out, ref, "sort_u32 " + algo)
 
 
