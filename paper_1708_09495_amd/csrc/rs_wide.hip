@@ -34,6 +34,7 @@ constexpr int WT_NW = WT_NT / WAVE;
 constexpr int WT_ITEMS = 8;
 constexpr uint32_t WT_SUB = WT_NT * WT_ITEMS;  // keys per sub-tile (4096)
 constexpr uint32_t WIDE_MAX_TILES = 512;
+constexpr int WIDE_PREFETCH_BITS = 14;
 
 template <typename K>
 __global__ __launch_bounds__(WC_NT) void k_wide_count(const K* __restrict__ keys, uint64_t n, int shift,
@@ -128,7 +129,9 @@ __device__ __forceinline__ uint32_t block_excl_max(uint32_t v, uint32_t* wmax) {
     return ex > before ? ex : before;
 }
 
-template <typename K, int VB>
+// PF: the next sub-tile's keys are loaded while the current one is written
+// (pays where the writes are most scattered, b >= WIDE_PREFETCH_BITS)
+template <typename K, int VB, bool PF>
 __global__ __launch_bounds__(WT_NT) void k_wide_scatter(const K* __restrict__ kin, K* __restrict__ kout,
                                                         const void* __restrict__ vin_, void* __restrict__ vout_,
                                                         uint64_t n, int shift, int bits, uint64_t tile_keys,
@@ -158,15 +161,26 @@ __global__ __launch_bounds__(WT_NT) void k_wide_scatter(const K* __restrict__ ki
     const uint32_t wb = wave * (WT_ITEMS * WAVE) + lane;
     uint16_t* wc = wcnt + wave * R8;
     uint64_t* wm = wmask + wave * R8;
+    // keys of the sub-tile at s (past the tile's end: the largest key)
+    K kn[WT_ITEMS];
+    auto load_sub = [&](uint64_t s) {
+        const uint32_t nv = s < e0 ? ((e0 - s) < (uint64_t)WT_SUB ? (uint32_t)(e0 - s) : WT_SUB) : 0u;
+#pragma unroll
+        for (int i = 0; i < WT_ITEMS; ++i) {
+            const uint32_t j = wb + i * WAVE;
+            kn[i] = j < nv ? kin[s + j] : KeyMax<K>::v;
+        }
+    };
+    if constexpr (PF) load_sub(b0);
     for (uint64_t s0 = b0; s0 < e0; s0 += WT_SUB) {
         const uint32_t nvalid = (e0 - s0) < (uint64_t)WT_SUB ? (uint32_t)(e0 - s0) : WT_SUB;
+        if constexpr (!PF) load_sub(s0);
         K k[WT_ITEMS];
         uint32_t ix[WT_ITEMS];
 #pragma unroll
         for (int i = 0; i < WT_ITEMS; ++i) {
-            const uint32_t j = wb + i * WAVE;
-            k[i] = j < nvalid ? kin[s0 + j] : KeyMax<K>::v;
-            ix[i] = j;
+            k[i] = kn[i];
+            ix[i] = wb + i * WAVE;
         }
         // two stable 8-bit LDS rounds order the sub-tile by its b-bit digit;
         // padding takes the largest digit and, coming last, stays last
@@ -222,6 +236,7 @@ __global__ __launch_bounds__(WT_NT) void k_wide_scatter(const K* __restrict__ ki
                 }
             }
         }
+        if constexpr (PF) load_sub(s0 + WT_SUB);
         // runs of equal digits among the nvalid sorted keys: thread tid owns
         // positions [tid*ITEMS, tid*ITEMS + ITEMS); a key's run head is the
         // last head position at or before it
@@ -237,6 +252,11 @@ __global__ __launch_bounds__(WT_NT) void k_wide_scatter(const K* __restrict__ ki
         }
         const uint32_t head_in = block_excl_max(last_head, wsum);
         uint32_t h = head_in;
+        // Run tails take their digit's cursor and advance it.  The sub-tile
+        // is sorted by digit, so each digit has one run here and the tails'
+        // cursors are distinct: every load is issued before any store.
+        uint32_t hq[WT_ITEMS], c0[WT_ITEMS], bq[WT_ITEMS];
+        uint32_t tails = 0;
 #pragma unroll
         for (int q = 0; q < WT_ITEMS; ++q) {
             const uint32_t j = j0 + q;
@@ -246,11 +266,22 @@ __global__ __launch_bounds__(WT_NT) void k_wide_scatter(const K* __restrict__ ki
                 if (dg[q] != prev) h = j;
                 const uint32_t next = q + 1 < WT_ITEMS ? dg[q + 1]
                                       : (j + 1 < nvalid ? ((uint32_t)(sk[j + 1] >> shift) & mask) : R);
-                if (dg[q] != next) {  // run tail: take the cursor and advance it
-                    const uint32_t c0 = cur[dg[q]];
-                    cur[dg[q]] = c0 + (j - h + 1);
-                    runbase[h] = base[dg[q]] + c0;
-                }
+                if (dg[q] != next) tails |= 1u << q;
+            }
+            hq[q] = h;
+        }
+#pragma unroll
+        for (int q = 0; q < WT_ITEMS; ++q) {
+            if (tails & (1u << q)) {
+                c0[q] = cur[dg[q]];
+                bq[q] = base[dg[q]];
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < WT_ITEMS; ++q) {
+            if (tails & (1u << q)) {
+                cur[dg[q]] = c0[q] + (j0 + q - hq[q] + 1);
+                runbase[hq[q]] = bq[q] + c0[q];
             }
         }
         __syncthreads();
@@ -325,8 +356,14 @@ static rs_status wide_pass(const WidePlan& p, const void* src, void* dst, const 
     rs_status rc = launch_status();
     if (rc != RS_OK) return rc;
     prof(st, KID_WIDE_SCATTER, 0);
-    hipLaunchKernelGGL((k_wide_scatter<K, VB>), dim3(p.tiles), dim3(WT_NT), 0, st, (const K*)src, (K*)dst, vsrc,
-                       vdst, (uint64_t)p.n, shift, p.bits, (uint64_t)p.tile_keys, table, base, status);
+    if (p.bits >= WIDE_PREFETCH_BITS)
+        hipLaunchKernelGGL((k_wide_scatter<K, VB, true>), dim3(p.tiles), dim3(WT_NT), 0, st, (const K*)src,
+                           (K*)dst, vsrc, vdst, (uint64_t)p.n, shift, p.bits, (uint64_t)p.tile_keys, table, base,
+                           status);
+    else
+        hipLaunchKernelGGL((k_wide_scatter<K, VB, false>), dim3(p.tiles), dim3(WT_NT), 0, st, (const K*)src,
+                           (K*)dst, vsrc, vdst, (uint64_t)p.n, shift, p.bits, (uint64_t)p.tile_keys, table, base,
+                           status);
     prof(st, KID_WIDE_SCATTER, 1);
     return launch_status();
 }

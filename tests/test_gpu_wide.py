@@ -27,7 +27,7 @@ def _check(out, ref, what):
     assert i is None, "%s: first mismatch at %d: got %d want %d" % (what, i, out[i], ref[i])
 
 
-@pytest.mark.parametrize("bits", [16, 12, 13])
+@pytest.mark.parametrize("bits", [16, 12, 13, 14])
 def test_u32_uniform(rs, orc, bits):
     import gen
     for n in SIZES:
