@@ -33,6 +33,7 @@ namespace {
 constexpr int NT = 512;          // threads per onesweep workgroup
 constexpr int NW = NT / WAVE;    // waves per workgroup
 constexpr int HIST_NT = 256;
+constexpr uint32_t HIST_HOT = 8;  // lanes on lane 0's digit worth one aggregated add
 constexpr uint32_t FLAG_AGG = 1, FLAG_PRE = 2;
 constexpr int LBWIN = 4;         // predecessors read per look-back step
 constexpr int RANK_GL = 16;      // lanes per ranking group at radix <= 2^8 (16 or 32)
@@ -153,20 +154,28 @@ __global__ __launch_bounds__(HIST_NT) void k_hist(const K* __restrict__ keys, ui
     __syncthreads();
     const uint64_t stride = (uint64_t)gridDim.x * HIST_NT;
     uint64_t i = (uint64_t)blockIdx.x * HIST_NT + threadIdx.x;
-    // Counting: when every lane of the wave holds the same digit (a common
-    // case for the high digits of skewed keys) one lane adds 64 instead of
-    // 64 lanes colliding on one counter.  The test costs instructions, so a
-    // round whose digits were not wave-uniform drops out of it until the
-    // next re-test (every 16 steps); the counts are exact either way.
-    uint32_t fast = (1u << passes) - 1;  // rounds tested for uniform digits (wave-uniform)
+    // Counting: the lanes whose digit equals lane 0's are added by one lane
+    // when there are at least HIST_HOT of them (skewed keys put most of a
+    // wave on one digit in the high rounds, and their atomics would
+    // serialise on one counter); the other lanes add one by one.  The test
+    // costs instructions, so a round that misses before it has hit in the
+    // current 16-step window drops out of the test until the window ends.
+    // The counts are exact either way.  (Wave-uniform masks, one bit per
+    // round: up to 64 rounds.)
+    const uint64_t all = passes >= 64 ? ~0ull : (1ull << passes) - 1;
+    uint64_t test = all, hit = 0;
     auto count = [&](uint32_t slot, int p) {
-        if (fast & (1u << p)) {
+        const uint64_t bit = 1ull << p;
+        if (test & bit) {
             const uint32_t first = __builtin_amdgcn_readfirstlane(slot);
-            if (ballot(slot != first) == 0) {
-                if ((threadIdx.x & 63) == 0) atomicAdd(&h[first], 64u);
+            const uint32_t c = (uint32_t)__popcll(ballot(slot == first));
+            if (c >= HIST_HOT) {
+                hit |= bit;
+                if ((threadIdx.x & 63) == 0) atomicAdd(&h[first], c);
+                if (slot != first) atomicAdd(&h[slot], 1u);
                 return;
             }
-            fast &= ~(1u << p);
+            if (!(hit & bit)) test &= ~bit;
         }
         atomicAdd(&h[slot], 1u);
     };
@@ -182,7 +191,10 @@ __global__ __launch_bounds__(HIST_NT) void k_hist(const K* __restrict__ keys, ui
             count(p * R + ((uint32_t)(k2 >> s) & mask), p);
             count(p * R + ((uint32_t)(k3 >> s) & mask), p);
         }
-        if ((step & 15) == 0) fast = (1u << passes) - 1;
+        if ((step & 15) == 0) {
+            test = all;
+            hit = 0;
+        }
     }
     for (; i < nfull; i += stride) {
         K k0 = keys[i];
