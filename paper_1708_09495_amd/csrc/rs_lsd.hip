@@ -12,12 +12,14 @@
 //               of the keys, so all rounds' counts come from the input) and
 //               zeroes the look-back words;
 //   k_onesweep  one launch per round: each workgroup takes the next tile id,
-//               ranks its keys stably by digit (wave64 ballot match plus
-//               per-wave LDS counters), publishes its per-digit counts,
-//               looks back over earlier tiles for their exclusive prefix
-//               (decoupled look-back, Merrill and Garland 2016, with flag and
-//               count packed in one word), reorders the tile by digit in LDS
-//               and writes each digit's run to HBM contiguously.
+//               ranks its keys stably by digit (an LDS match per group of
+//               16 lanes, the group's running count beside its mask; whole
+//               waves with ballots above 8 bits), publishes its per-digit
+//               counts, reorders the tile by digit in LDS, looks back over
+//               earlier tiles for their exclusive prefix (decoupled
+//               look-back, Merrill and Garland 2016, with flag and count
+//               packed in one word) and writes each digit's run to HBM
+//               contiguously.
 //
 // The paper's count exchange (2prg) is the look-back table: R words per
 // tile.  Per round HBM traffic is one read and one write of the keys (and
@@ -474,6 +476,11 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MAXB <= 8 ? 
         for (int i = 0; i < ITEMS; ++i) svals[dr[i]] = v[i];
     }
     __syncthreads();
+    // the sorted keys this thread writes out, read from LDS now: half of the
+    // workgroup has no look-back to do, and for the other half the reads
+    // are done before its wait on the predecessors
+#pragma unroll
+    for (int q = 0; q < ITEMS; ++q) k[q] = skeys[q * NT + tid];
 
     // ---- global position of each digit's first key in this tile.  Taken
     //      after the LDS reorder: by then the tiles before this one have
@@ -558,7 +565,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MAXB <= 8 ? 
     for (int q = 0; q < ITEMS; ++q) {
         const uint32_t j = q * NT + tid;
         if (full || j < nvalid) {
-            const K key = skeys[j];
+            const K key = k[q];
             const uint32_t d = (uint32_t)(key >> shift) & dmask;
             OFF o = goff[d] + (OFF)j;
             if ((uint64_t)(UOFF)o >= n) {

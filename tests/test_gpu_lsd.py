@@ -60,6 +60,28 @@ def test_u32_structured(rs, orc, case, bits):
     _check(out, orc.lsd(a, bits), case)
 
 
+@pytest.mark.parametrize("bits", [8, 11, 4])
+def test_skewed_histograms(rs, orc, bits):
+    """Digits shared by many lanes of a wave, which the histogram counts
+    with one add per wave: Zipf keys (the high bytes mostly zero, the low
+    ones crowded) and keys 90% equal to one value; every round run (LSD)
+    and with the identity rounds skipped (AUTO)."""
+    import gen
+    rng = np.random.default_rng(11)
+    n = (1 << 20) + 4099
+    z = gen.zipf_u64(gen.S0 + 44, n)
+    m = np.where(rng.random(n) < 0.9, 0x12345678, rng.integers(0, 2**32, n)).astype(np.uint32)
+    zref, mref = orc.lsd(z, bits), orc.lsd(m, bits)
+    for algo in (rs.RS_ALGO_LSD, rs.RS_ALGO_AUTO):
+        print("case skewed bits=%d algo=%d" % (bits, algo), flush=True)
+        out = to_host(rs.rs_sort_u64(to_dev(z), radix_bits=bits, algo=algo), np.uint64)
+        assert rs.rs_get_stats().device_error == 0
+        _check(out, zref, "zipf b=%d algo=%d" % (bits, algo))
+        out = to_host(rs.rs_sort_u32(to_dev(m), radix_bits=bits, algo=algo), np.uint32)
+        assert rs.rs_get_stats().device_error == 0
+        _check(out, mref, "90%% one value b=%d algo=%d" % (bits, algo))
+
+
 @pytest.mark.parametrize("bits", [8, 11])
 def test_u64_uniform(rs, orc, bits):
     import gen
