@@ -605,7 +605,7 @@ def mbsp_check(args, torch, rs, keys, n, p, name, ms, stages, prof):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(every sort runs on a single MI355X); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 

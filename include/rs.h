@@ -39,7 +39,7 @@ extern "C" {
 typedef enum {
     RS_OK = 0,
     RS_ERR_INVALID = 1,      /* bad argument (NULL pointer, bad width, ...)   */
-    RS_ERR_UNSUPPORTED = 2,  /* valid request this build cannot serve         */
+    RS_ERR_UNSUPPORTED = 2,  /* valid request the library does not serve     */
     RS_ERR_WORKSPACE = 3,    /* workspace NULL, too small or misaligned       */
     RS_ERR_HIP = 4           /* a HIP runtime call failed                     */
 } rs_status;
