@@ -181,8 +181,8 @@ __global__ __launch_bounds__(HIST_NT) void k_hist(const K* __restrict__ keys, ui
         }
         atomicAdd(&h[slot], 1u);
     };
-    // four independent loads in flight per thread; whole waves only, so the
-    // uniform-digit test sees 64 keys
+    // four independent loads in flight per thread; whole waves only, so
+    // lane 0 is active and the hot-digit test sees 64 keys
     const uint64_t nfull = n - n % ((uint64_t)HIST_NT * gridDim.x);
     for (uint32_t step = 1; i + 3 * stride < nfull; i += 4 * stride, ++step) {
         K k0 = keys[i], k1 = keys[i + stride], k2 = keys[i + 2 * stride], k3 = keys[i + 3 * stride];
