@@ -116,3 +116,20 @@ def test_bench_sizes(rs, orc):
             assert rs.rs_get_stats().device_error == 0
             _check(out, ref, "2^%d %s" % (lg, algo))
             assert multiset_hash(out) == multiset_hash(a)
+
+
+def test_bench_configuration(rs, orc):
+    """The launch configuration the bench times: 2^27 keys at the MBSP
+    model's p (BTN and OET), every output key against the oracle's sort."""
+    import gen
+    n = 1 << 27
+    a = gen.uniform_u32(gen.S0 + 2, n)
+    ref = orc.lsd(a, 8)
+    for algo in ("BTN", "OET"):
+        code = getattr(rs, "RS_ALGO_" + algo)
+        p = rs.rs_blocks_default_p(n, code)
+        print("case blocks bench configuration %s n=2^27 p=%d" % (algo, p), flush=True)
+        out = to_host(rs.rs_sort_blocks_u32(to_dev(a), algo=code), np.uint32)
+        st = rs.rs_get_stats()
+        assert st.device_error == 0 and st.runs_p == p and st.network_stages == _stages(algo, p)
+        _check(out, ref, "2^27 %s p=%d" % (algo, p))
