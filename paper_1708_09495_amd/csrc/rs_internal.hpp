@@ -158,7 +158,7 @@ struct LearnOpts {
     float lr;                     // Adam learning rate
     int32_t use_network;          // 0: bucket by the feature alone (no network)
     int32_t bucket_cap;           // LDS capacity of a bucket (<= 6144 pairs)
-    int32_t feature_mode;         // -1 automatic, 0 linear, 1 log-scaled
+    int32_t feature_mode;         // -1 automatic (2), 0 linear, 1 log-scaled, 2 sample quantiles
     double fallback_frac;         // overflowed-key share that sends the whole array to LSD
     int32_t train_blocks;         // workgroups of the training launch
     int32_t max_fallback_buckets; // more overflowed buckets than this: whole-array LSD
