@@ -56,7 +56,7 @@ template <> struct LBW<uint64_t> {
 constexpr int lsd_items(int kb, int vb, int maxb) {
     if (maxb > 8) return kb == 4 ? (vb == 0 ? 24 : 16) : 8;
     if (kb == 4) return vb == 0 ? 28 : (vb == 4 ? 22 : 16);
-    return vb == 0 ? 16 : (vb == 8 ? 12 : 8);
+    return vb == 0 ? 18 : (vb == 8 ? 12 : 8);
 }
 // below this many uint32 keys (keys only) the radix-2^8 rounds take smaller
 // tiles, so that the tiles still outnumber the workgroups the chip holds at
