@@ -22,7 +22,9 @@
  *     launch failure returns RS_ERR_HIP.  Device faults surface at the
  *     caller's next synchronisation, as for any HIP work.
  *   - `in == out` (and vals_in == vals_out) is allowed: the sort is then in
- *     place.  Other overlaps are not allowed.
+ *     place.  A key-value sort is in place for both arrays or for neither
+ *     (keys_in == keys_out exactly when vals_in == vals_out), else
+ *     RS_ERR_INVALID.  Other overlaps are not allowed.
  *   - n = 0 is valid and enqueues nothing.
  *   - The library never aborts the process.
  */
@@ -90,7 +92,9 @@ typedef struct {
  * histogram shows them, and the choice is made on the device --; LDS_RADIX
  * for n <= rs_small_capacity(4) (one workgroup); BTN/OET: one workgroup up
  * to that size, above it rs_sort_blocks_u32 with p = 0.
- * Layout: `in` and `out` are dense arrays of n keys. */
+ * Layout: `in` and `out` are dense arrays of n keys.  n < 2^32 (digit
+ * counts and prefixes are 32-bit words); larger n returns
+ * RS_ERR_UNSUPPORTED. */
 rs_status rs_sort_u32(const uint32_t* in, uint32_t* out, size_t n, int radix_bits,
                       rs_algo algo, void* ws, size_t ws_bytes, void* stream);
 

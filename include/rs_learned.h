@@ -52,6 +52,49 @@ rs_status rs_mlp_forward(const float* params, const float* x, float* y, size_t m
 rs_status rs_mlp_loss_grad(const float* params, const float* x, const float* t, size_t m,
                            float* grad, void* stream);
 
+/* One Adam step (Kingma and Ba 2015, bias-corrected) on the 1153 raw
+ * parameters, the update training applies after each gradient: with
+ * c1 = 1 - beta1^(step+1) and c2 = 1 - beta2^(step+1) (step counts from 0),
+ *   m1 = beta1 m1 + (1 - beta1) g,  m2 = beta2 m2 + (1 - beta2) g^2,
+ *   params -= lr (m1 / c1) / (sqrt(m2 / c2) + eps),
+ * in float32.  params, m1, m2 (updated) and grad (read only) are device
+ * arrays of 1153 floats.  Exposed for checking the update against a
+ * double-precision reference. */
+rs_status rs_mlp_adam_step(float* params, float* m1, float* m2, const float* grad, int32_t step,
+                           float lr, float beta1, float beta2, float eps, void* stream);
+
+/* Test hook: the following LEARNED sorts in this process skip training and
+ * use these raw parameters (HOST array of count = 1153 floats, copied
+ * here); params = NULL goes back to training.  The weights stay
+ * softplus(v) >= 0, so the network stays monotone.  RS_ERR_INVALID for a
+ * wrong count.  Not thread-safe against concurrent sorts. */
+rs_status rs_mlp_set_weights(const float* params, size_t count);
+
+/* Test hook (fault injection) for the following LEARNED sorts in this
+ * process (not thread-safe against concurrent sorts):
+ *   RS_LEARNED_FAULT_NONE       no fault (the default);
+ *   RS_LEARNED_FAULT_SPLITTERS  `splitters` (HOST array, count = 65535;
+ *                               bucket j holds the keys in [s[j-1], s[j]))
+ *                               replace the splitters derived from the
+ *                               network, as given, not made non-decreasing.
+ *                               The bucket search is a fixed binary decision
+ *                               tree, so the key-to-bucket map stays
+ *                               monotone whatever their order, and the
+ *                               output stays the stable sort;
+ *   RS_LEARNED_FAULT_SWAP       after the buckets are sorted, the first and
+ *                               last output pairs trade places (a planted
+ *                               bucket-sort error), which the final
+ *                               sortedness check must catch, sending the
+ *                               whole array through the LSD rounds.
+ * `splitters` and `count` are read only for RS_LEARNED_FAULT_SPLITTERS.
+ * RS_ERR_INVALID for an unknown kind or a wrong count. */
+enum {
+    RS_LEARNED_FAULT_NONE = 0,
+    RS_LEARNED_FAULT_SPLITTERS = 1,
+    RS_LEARNED_FAULT_SWAP = 2
+};
+rs_status rs_learned_debug_fault(int kind, const uint64_t* splitters, size_t count);
+
 #ifdef __cplusplus
 }
 #endif

@@ -22,7 +22,7 @@ EXPORTS = ["rs_sort_u32", "rs_sort_u64", "rs_sort_kv", "rs_sort_batch_u32", "rs_
            "rs_workspace_bytes", "rs_small_capacity", "rs_status_string", "rs_get_stats",
            "rs_tune_set", "rs_tune_get", "rs_tune_run", "rs_profile_enable", "rs_profile_read",
            "rs_learned_set_opts", "rs_learned_get_opts", "rs_mlp_num_params", "rs_mlp_forward",
-           "rs_mlp_loss_grad"]
+           "rs_mlp_loss_grad", "rs_mlp_adam_step", "rs_mlp_set_weights", "rs_learned_debug_fault"]
 
 
 class RsError(RuntimeError):
@@ -123,6 +123,13 @@ def lib():
         L.rs_mlp_forward.restype = i
         L.rs_mlp_loss_grad.argtypes = [vp, vp, vp, sz, vp, vp]
         L.rs_mlp_loss_grad.restype = i
+        f32 = ctypes.c_float
+        L.rs_mlp_adam_step.argtypes = [vp, vp, vp, vp, ctypes.c_int32, f32, f32, f32, f32, vp]
+        L.rs_mlp_adam_step.restype = i
+        L.rs_mlp_set_weights.argtypes = [vp, sz]
+        L.rs_mlp_set_weights.restype = i
+        L.rs_learned_debug_fault.argtypes = [i, vp, sz]
+        L.rs_learned_debug_fault.restype = i
         L.rs_profile_enable.argtypes = [i]
         L.rs_profile_read.argtypes = [ctypes.POINTER(rs_kernel_time), i]
         L.rs_profile_read.restype = i
@@ -271,6 +278,43 @@ def rs_mlp_loss_grad(params, x, t, grad=None, stream=None):
     _call(lib().rs_mlp_loss_grad(_ptr(params), _ptr(x), _ptr(t), x.numel(), _ptr(grad),
                                  _stream(stream)), "rs_mlp_loss_grad")
     return grad
+
+
+def rs_mlp_adam_step(params, m1, m2, grad, step, lr=1e-2, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    """One Adam step on device float32 tensors of 1153 (params, m1, m2 are
+    updated in place; grad is read)."""
+    np_ = rs_mlp_num_params()
+    for name, t in (("params", params), ("m1", m1), ("m2", m2), ("grad", grad)):
+        _check_dev(t, 4, name)
+        if t.numel() < np_:
+            raise ValueError("%s holds fewer than %d floats" % (name, np_))
+    _call(lib().rs_mlp_adam_step(_ptr(params), _ptr(m1), _ptr(m2), _ptr(grad), int(step), float(lr),
+                                 float(beta1), float(beta2), float(eps), _stream(stream)), "rs_mlp_adam_step")
+
+
+def rs_mlp_set_weights(params):
+    """Host float32 array of 1153 raw parameters the learned path uses
+    instead of training; None goes back to training."""
+    if params is None:
+        _call(lib().rs_mlp_set_weights(None, 0), "rs_mlp_set_weights")
+        return
+    import numpy as np
+    a = np.ascontiguousarray(params, dtype=np.float32)
+    _call(lib().rs_mlp_set_weights(a.ctypes.data, a.size), "rs_mlp_set_weights")
+
+
+RS_LEARNED_FAULT_NONE, RS_LEARNED_FAULT_SPLITTERS, RS_LEARNED_FAULT_SWAP = range(3)
+
+
+def rs_learned_debug_fault(kind, splitters=None):
+    """Plants a fault in the following learned sorts (RS_LEARNED_FAULT_*);
+    splitters: host uint64 array of 65,535 for RS_LEARNED_FAULT_SPLITTERS."""
+    if splitters is None:
+        _call(lib().rs_learned_debug_fault(int(kind), None, 0), "rs_learned_debug_fault")
+        return
+    import numpy as np
+    a = np.ascontiguousarray(splitters, dtype=np.uint64)
+    _call(lib().rs_learned_debug_fault(int(kind), a.ctypes.data, a.size), "rs_learned_debug_fault")
 
 
 def rs_profile_enable(on=True):

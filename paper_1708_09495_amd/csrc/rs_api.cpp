@@ -111,6 +111,13 @@ rs_status sort_learned(const void* kin, void* kout, const void* vin, void* vout,
     g_call.stats.train_loss = rep.train_loss;
     g_call.stats.device_error = rep.device_error;
     g_call.stats.passes = rep.fallback ? 8 : 2;
+    if (rc == RS_OK && rep.err_word) {
+        // rs_get_stats reads the word once the stream is done: it also holds
+        // the status of the LSD sorts enqueued after the host's last look
+        g_call.stream = st;
+        g_call.status = rep.err_word;
+        g_call.pending = true;
+    }
     return rc;
 }
 
@@ -185,7 +192,10 @@ rs_status sort_keys_common(const void* kin, void* kout, const void* vin, void* v
     if (vb && n > 0 && (!vin || !vout)) return RS_ERR_INVALID;
     if (n > 0 && kin != kout && overlaps(kin, n * kb, kout, n * kb)) return RS_ERR_INVALID;
     if (vb && n > 0 && vin != vout && overlaps(vin, n * vb, vout, n * vb)) return RS_ERR_INVALID;
-    if ((uint64_t)n >= (1ull << 40)) return RS_ERR_UNSUPPORTED;
+    // keys and values are either both sorted in place or both not: the
+    // rounds pick their buffers from the keys alone
+    if (vb && n > 0 && (kin == kout) != (vin == vout)) return RS_ERR_INVALID;
+    if ((uint64_t)n >= LSD_MAX_N) return RS_ERR_UNSUPPORTED;
     bits = default_bits(bits);
     hipStream_t st = static_cast<hipStream_t>(stream);
     switch (algo) {
@@ -452,6 +462,23 @@ extern "C" rs_status rs_mlp_loss_grad(const float* params, const float* x, const
     if (!m || !params || !x || !t || !grad) return RS_ERR_INVALID;
     (void)hipGetLastError();
     return rs::mlp_loss_grad(params, x, t, m, grad, static_cast<hipStream_t>(stream));
+}
+
+extern "C" rs_status rs_mlp_adam_step(float* params, float* m1, float* m2, const float* grad, int32_t step,
+                                      float lr, float beta1, float beta2, float eps, void* stream) {
+    if (!params || !m1 || !m2 || !grad || step < 0) return RS_ERR_INVALID;
+    if (!(lr > 0.f) || !(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f) || !(eps >= 0.f))
+        return RS_ERR_INVALID;
+    (void)hipGetLastError();
+    return rs::mlp_adam_step(params, m1, m2, grad, step, lr, beta1, beta2, eps, static_cast<hipStream_t>(stream));
+}
+
+extern "C" rs_status rs_mlp_set_weights(const float* params, size_t count) {
+    return rs::learned_inject_weights(params, count);
+}
+
+extern "C" rs_status rs_learned_debug_fault(int kind, const uint64_t* splitters, size_t count) {
+    return rs::learned_inject_fault(kind, splitters, count);
 }
 
 // ---- tuning table -----------------------------------------------------------

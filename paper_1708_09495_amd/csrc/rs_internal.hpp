@@ -72,7 +72,12 @@ struct LsdPlan {
 // rounds (its first word: the mask of skipped rounds).
 constexpr size_t ROUTE_OFFSET = 16;
 
-// Plans an LSD sort; returns false when (kb, vb, bits, vb2) is not supported.
+// Largest key count + 1 of the LSD rounds: digit counts and prefixes are
+// 32-bit words.
+constexpr uint64_t LSD_MAX_N = 1ull << 32;
+
+// Plans an LSD sort; returns false when (kb, vb, bits, vb2) is not supported
+// or n >= LSD_MAX_N.
 bool lsd_plan(size_t n, int kb, int vb, int bits, LsdPlan* p, int vb2 = 0);
 
 // Enqueues the whole LSD sort on `st`.  `ws` holds at least p.total bytes.
@@ -169,6 +174,9 @@ struct LearnReport {
     double train_loss;
     uint32_t device_error, unsorted;
     int32_t feature_mode;
+    // device word holding the path's own errors and every inner LSD sort's
+    // status word, complete once the stream reaches the end of the call
+    const uint32_t* err_word;
 };
 LearnOpts& learn_opts();
 size_t learned_ws_bytes(size_t n, int vb);
@@ -176,6 +184,12 @@ size_t learned_ws_bytes(size_t n, int vb);
 rs_status learned_run(const void* kin, void* kout, const void* vin, void* vout, size_t n, int vb, void* ws,
                       size_t ws_bytes, hipStream_t st, LearnReport* rep);
 rs_status mlp_forward(const float* params, const float* x, float* y, size_t m, hipStream_t st);
+rs_status mlp_adam_step(float* params, float* m1, float* m2, const float* grad, int step, float lr,
+                        float beta1, float beta2, float eps, hipStream_t st);
+// Test hooks of the learned path: parameters used instead of training
+// (NULL: back to training); a planted fault (RS_LEARNED_FAULT_*).
+rs_status learned_inject_weights(const float* params, size_t count);
+rs_status learned_inject_fault(int kind, const uint64_t* spl, size_t count);
 rs_status mlp_loss_grad(const float* params, const float* x, const float* t, size_t m, float* grad,
                         hipStream_t st);
 constexpr int MLP_NPARAM = 1153;

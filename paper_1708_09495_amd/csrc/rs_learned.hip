@@ -32,6 +32,7 @@
 
 #include <vector>
 
+#include "../../include/rs_learned.h"
 #include "rs_dev.h"
 #include "rs_internal.hpp"
 
@@ -70,7 +71,6 @@ struct State {
                            // 2 piecewise linear between the sample's key quantiles
     uint32_t reach;        // number of reachable splitters
     float loss;            // last training loss (mean squared error)
-    uint32_t bar_count, bar_gen;
     uint32_t ovf_buckets;          // buckets over the LDS capacity
     unsigned long long ovf_keys;   // keys in them
     uint32_t mid_buckets;          // buckets split and sorted by k_bucket_mid
@@ -250,43 +250,16 @@ __global__ void k_targets(const uint64_t* __restrict__ s, const State* __restric
 }
 
 // ---- 2. training -------------------------------------------------------------------
-
-// Grid-wide barrier for a cooperative launch (every workgroup resident).
-// Bounded: a workgroup that waits SPIN_LIMIT polls records an error and
-// gives up, so the kernel always ends.
-__device__ bool grid_sync(State* st, uint32_t nblocks) {
-    __shared__ uint32_t s_ok;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        s_ok = 1;
-        const uint32_t g0 = __hip_atomic_load(&st->bar_gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __threadfence();
-        if (atomicAdd(&st->bar_count, 1u) == nblocks - 1) {
-            __hip_atomic_store(&st->bar_count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __threadfence();
-            atomicAdd(&st->bar_gen, 1u);
-        } else {
-            uint32_t spins = 0;
-            while (__hip_atomic_load(&st->bar_gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g0) {
-                if (++spins > SPIN_LIMIT) {
-                    atomicOr(&st->err, STATUS_SPIN);
-                    s_ok = 0;
-                    break;
-                }
-                __builtin_amdgcn_s_sleep(2);
-            }
-        }
-        __threadfence();
-    }
-    __syncthreads();
-    return s_ok != 0;
-}
+//
+// Each Adam step is two ordinary launches on the caller's stream: k_grad
+// (every workgroup adds the gradient of its samples into one buffer) and
+// k_adam (the update of every parameter, which also clears the buffer for
+// the next step).  Stream order is the only synchronisation between steps.
 
 struct TrainCfg {
-    int steps;
     float lr, beta1, beta2, eps;
     uint32_t m;        // samples
-    int grad_only;     // 1: one gradient over all m samples into gbuf[0], no update
+    int grad_only;     // 1: one gradient over all m samples, scaled by 1/m
 };
 
 // Data-dependent initialisation from the sorted sample's features xs:
@@ -337,141 +310,140 @@ __device__ float init_param(int p, const float* __restrict__ xs, uint32_t m) {
     return logit_mid(H / 2) - acc;
 }
 
-__global__ __launch_bounds__(TR_NT) void k_train(const float* __restrict__ xs, const float* __restrict__ ts,
-                                                 float* __restrict__ params, float* __restrict__ gbuf,
-                                                 State* __restrict__ st, TrainCfg cfg, int init) {
-    __shared__ float raw[NP], m1[NP], m2[NP], gl[GBUF];
+// Parameters at the start of training (one thread per parameter).
+__global__ void k_train_init(const float* __restrict__ xs, uint32_t m, float* __restrict__ params) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < NP) params[p] = init_param(p, xs, m);
+}
+
+// Gradient of the mean squared error through the softplus, added into gbuf
+// (gbuf[NP] gets the summed squared error).  Training step `step`: workgroup
+// g of G takes the TR_NT samples starting at ((step * G + g) * TR_NT) mod m,
+// so that one step sees a batch of G * TR_NT samples and the steps cycle
+// through the set; the mean is over that batch.  grad_only: workgroup g takes
+// slices g, g + G, ... of all m samples, and the mean is over m.
+__global__ __launch_bounds__(TR_NT) void k_grad(const float* __restrict__ xs, const float* __restrict__ ts,
+                                                const float* __restrict__ params, float* __restrict__ gbuf,
+                                                TrainCfg cfg, int step) {
+    __shared__ float raw[NP], gl[GBUF];
     __shared__ Mlp W;
     __shared__ float A[TR_NT][H + 1], Hm[TR_NT][H + 1];
     __shared__ float xsl[TR_NT], dzl[TR_NT], e2[TR_NT];
     const int t = threadIdx.x;
     const uint32_t G = gridDim.x, g = blockIdx.x;
-    for (int p = t; p < NP; p += TR_NT) {
-        raw[p] = init ? init_param(p, xs, cfg.m) : params[p];
-        m1[p] = 0.f;
-        m2[p] = 0.f;
-    }
+    for (int p = t; p < NP; p += TR_NT) raw[p] = params[p];
+    for (int p = t; p < GBUF; p += TR_NT) gl[p] = 0.f;
     __syncthreads();
     mlp_derive(raw, W, true);
     __syncthreads();
-    const uint32_t bsz = cfg.grad_only ? cfg.m : (uint32_t)G * TR_NT;
-    const int steps = cfg.grad_only ? 1 : cfg.steps;
-    const uint32_t slices = cfg.grad_only ? (cfg.m + TR_NT - 1) / TR_NT : 1;
-    bool ok = true;
-    for (int step = 0; step < steps && ok; ++step) {
-        float* cur = gbuf + (size_t)(cfg.grad_only ? 0 : step % 3) * GBUF;
-        if (!cfg.grad_only && g == 0) {
-            // zero the buffer the step after this one will fill; it was last
-            // read two steps ago, before every workgroup reached the previous
-            // barrier
-            float* nxt = gbuf + (size_t)((step + 1) % 3) * GBUF;
-            for (int p = t; p < GBUF; p += TR_NT) nxt[p] = 0.f;
-        }
-        for (int p = t; p < GBUF; p += TR_NT) gl[p] = 0.f;
-        // training: one slice of 256 samples per workgroup per step, cycling
-        // through the sample; gradient only: slices g, g+G, ... of all m
-        const uint32_t sl_first = cfg.grad_only ? g : 0u;
-        const uint32_t sl_end = cfg.grad_only ? slices : 1u;
-        const uint32_t sl_step = cfg.grad_only ? G : 1u;
-        for (uint32_t sl = sl_first; sl < sl_end; sl += sl_step) {
-            const uint32_t base = cfg.grad_only ? sl * TR_NT
-                                                : ((uint32_t)(step * G + g) * TR_NT) % cfg.m;
-            const uint32_t i = base + t;
-            const bool live = i < cfg.m;
-            const float x = live ? xs[i] : 0.f, tt = live ? ts[i] : 0.f;
-            float h1[H], h2[H];
-            const float y = mlp_fwd(W, x, h1, h2);
-            const float e = live ? (y - tt) : 0.f;
-            const float dz = (2.f * e / (float)bsz) * y * (1.f - y);
-            float da2[H];
+    const uint32_t bsz = cfg.grad_only ? cfg.m : G * TR_NT;
+    const uint32_t slices = cfg.grad_only ? (cfg.m + TR_NT - 1) / TR_NT : 1u;
+    const uint32_t sl_first = cfg.grad_only ? g : 0u;
+    const uint32_t sl_step = cfg.grad_only ? G : 1u;
+    for (uint32_t sl = sl_first; sl < slices; sl += sl_step) {
+        const uint32_t base = cfg.grad_only ? sl * TR_NT
+                                            : (uint32_t)((((uint64_t)step * G + g) * TR_NT) % cfg.m);
+        const uint32_t i = base + t;
+        const bool live = i < cfg.m;
+        const float x = live ? xs[i] : 0.f, tt = live ? ts[i] : 0.f;
+        float h1[H], h2[H];
+        const float y = mlp_fwd(W, x, h1, h2);
+        const float e = live ? (y - tt) : 0.f;
+        const float dz = (2.f * e / (float)bsz) * y * (1.f - y);
+        float da2[H];
 #pragma unroll
-            for (int o = 0; o < H; ++o) da2[o] = dz * W.w3[o] * (1.f - h2[o] * h2[o]);
-            __syncthreads();
-#pragma unroll
-            for (int o = 0; o < H; ++o) {
-                A[t][o] = da2[o];
-                Hm[t][o] = h1[o];
-            }
-            xsl[t] = x;
-            dzl[t] = dz;
-            e2[t] = e * e;
-            __syncthreads();
-            {   // dW2 (4 entries per thread) and db2
-                const int o = t >> 3, i0 = (t & 7) * 4;
-                float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f, acc3 = 0.f, asum = 0.f;
-                for (int s = 0; s < TR_NT; ++s) {
-                    const float a = A[s][o];
-                    acc0 = fmaf(a, Hm[s][i0 + 0], acc0);
-                    acc1 = fmaf(a, Hm[s][i0 + 1], acc1);
-                    acc2 = fmaf(a, Hm[s][i0 + 2], acc2);
-                    acc3 = fmaf(a, Hm[s][i0 + 3], acc3);
-                    asum += a;
-                }
-                gl[P_V2 + o * H + i0 + 0] += acc0 * W.s2[o * H + i0 + 0];
-                gl[P_V2 + o * H + i0 + 1] += acc1 * W.s2[o * H + i0 + 1];
-                gl[P_V2 + o * H + i0 + 2] += acc2 * W.s2[o * H + i0 + 2];
-                gl[P_V2 + o * H + i0 + 3] += acc3 * W.s2[o * H + i0 + 3];
-                if ((t & 7) == 0) gl[P_B2 + o] += asum;
-            }
-            // da1 = (W2^T da2) (1 - h1^2); dz * h2 for the output weights
-            float da1[H];
-#pragma unroll
-            for (int i = 0; i < H; ++i) da1[i] = 0.f;
-#pragma unroll 4
-            for (int o = 0; o < H; ++o) {
-#pragma unroll
-                for (int i = 0; i < H; ++i) da1[i] = fmaf(da2[o], W.w2[o * H + i], da1[i]);
-            }
-            __syncthreads();
-#pragma unroll
-            for (int i = 0; i < H; ++i) {
-                Hm[t][i] = da1[i] * (1.f - h1[i] * h1[i]);
-                A[t][i] = dz * h2[i];
-            }
-            __syncthreads();
-            if (t < H) {
-                float sb = 0.f, sv = 0.f;
-                for (int s = 0; s < TR_NT; ++s) {
-                    sb += Hm[s][t];
-                    sv = fmaf(Hm[s][t], xsl[s], sv);
-                }
-                gl[P_B1 + t] += sb;
-                gl[P_V1 + t] += sv * W.s1[t];
-            } else if (t < 2 * H) {
-                float sv = 0.f;
-                for (int s = 0; s < TR_NT; ++s) sv += A[s][t - H];
-                gl[P_V3 + t - H] += sv * W.s3[t - H];
-            } else if (t == 2 * H) {
-                float sb = 0.f;
-                for (int s = 0; s < TR_NT; ++s) sb += dzl[s];
-                gl[P_B3] += sb;
-            } else if (t == 2 * H + 1) {
-                float se = 0.f;
-                for (int s = 0; s < TR_NT; ++s) se += e2[s];
-                gl[NP] += se;
-            }
-            __syncthreads();
-        }
-        for (int p = t; p < GBUF; p += TR_NT) atomicAdd(&cur[p], gl[p]);
-        if (cfg.grad_only) break;
-        ok = grid_sync(st, G);
-        // every workgroup applies the same Adam step to its own copy
-        const float c1 = 1.f - powf(cfg.beta1, (float)(step + 1));
-        const float c2 = 1.f - powf(cfg.beta2, (float)(step + 1));
-        for (int p = t; p < NP; p += TR_NT) {
-            const float gr = __hip_atomic_load(&cur[p], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            m1[p] = cfg.beta1 * m1[p] + (1.f - cfg.beta1) * gr;
-            m2[p] = cfg.beta2 * m2[p] + (1.f - cfg.beta2) * gr * gr;
-            raw[p] -= cfg.lr * (m1[p] / c1) / (sqrtf(m2[p] / c2) + cfg.eps);
-        }
-        if (g == 0 && t == 0)
-            st->loss = __hip_atomic_load(&cur[NP], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) / (float)bsz;
+        for (int o = 0; o < H; ++o) da2[o] = dz * W.w3[o] * (1.f - h2[o] * h2[o]);
         __syncthreads();
-        mlp_derive(raw, W, true);
+#pragma unroll
+        for (int o = 0; o < H; ++o) {
+            A[t][o] = da2[o];
+            Hm[t][o] = h1[o];
+        }
+        xsl[t] = x;
+        dzl[t] = dz;
+        e2[t] = e * e;
+        __syncthreads();
+        {   // dW2 (4 entries per thread) and db2
+            const int o = t >> 3, i0 = (t & 7) * 4;
+            float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f, acc3 = 0.f, asum = 0.f;
+            for (int s = 0; s < TR_NT; ++s) {
+                const float a = A[s][o];
+                acc0 = fmaf(a, Hm[s][i0 + 0], acc0);
+                acc1 = fmaf(a, Hm[s][i0 + 1], acc1);
+                acc2 = fmaf(a, Hm[s][i0 + 2], acc2);
+                acc3 = fmaf(a, Hm[s][i0 + 3], acc3);
+                asum += a;
+            }
+            gl[P_V2 + o * H + i0 + 0] += acc0 * W.s2[o * H + i0 + 0];
+            gl[P_V2 + o * H + i0 + 1] += acc1 * W.s2[o * H + i0 + 1];
+            gl[P_V2 + o * H + i0 + 2] += acc2 * W.s2[o * H + i0 + 2];
+            gl[P_V2 + o * H + i0 + 3] += acc3 * W.s2[o * H + i0 + 3];
+            if ((t & 7) == 0) gl[P_B2 + o] += asum;
+        }
+        // da1 = (W2^T da2) (1 - h1^2); dz * h2 for the output weights
+        float da1[H];
+#pragma unroll
+        for (int i = 0; i < H; ++i) da1[i] = 0.f;
+#pragma unroll 4
+        for (int o = 0; o < H; ++o) {
+#pragma unroll
+            for (int i = 0; i < H; ++i) da1[i] = fmaf(da2[o], W.w2[o * H + i], da1[i]);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < H; ++i) {
+            Hm[t][i] = da1[i] * (1.f - h1[i] * h1[i]);
+            A[t][i] = dz * h2[i];
+        }
+        __syncthreads();
+        if (t < H) {
+            float sb = 0.f, sv = 0.f;
+            for (int s = 0; s < TR_NT; ++s) {
+                sb += Hm[s][t];
+                sv = fmaf(Hm[s][t], xsl[s], sv);
+            }
+            gl[P_B1 + t] += sb;
+            gl[P_V1 + t] += sv * W.s1[t];
+        } else if (t < 2 * H) {
+            float sv = 0.f;
+            for (int s = 0; s < TR_NT; ++s) sv += A[s][t - H];
+            gl[P_V3 + t - H] += sv * W.s3[t - H];
+        } else if (t == 2 * H) {
+            float sb = 0.f;
+            for (int s = 0; s < TR_NT; ++s) sb += dzl[s];
+            gl[P_B3] += sb;
+        } else if (t == 2 * H + 1) {
+            float se = 0.f;
+            for (int s = 0; s < TR_NT; ++s) se += e2[s];
+            gl[NP] += se;
+        }
         __syncthreads();
     }
-    if (!cfg.grad_only && g == 0)
-        for (int p = t; p < NP; p += TR_NT) params[p] = raw[p];
+    for (int p = t; p < GBUF; p += TR_NT)
+        if (gl[p] != 0.f) atomicAdd(&gbuf[p], gl[p]);
+}
+
+// One Adam step (Kingma and Ba, bias-corrected; step counts from 0) on every
+// parameter, from the gradient in gbuf; thread p owns parameter p and its
+// two moments.  With `clear`, gbuf is zeroed for the next step, and the
+// batch's mean squared error is stored as the reported loss.
+__global__ void k_adam(float* __restrict__ params, float* __restrict__ m1, float* __restrict__ m2,
+                       float* __restrict__ gbuf, TrainCfg cfg, int step, uint32_t bsz, State* __restrict__ st,
+                       int clear) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < NP) {
+        const float gr = gbuf[p];
+        const float c1 = 1.f - powf(cfg.beta1, (float)(step + 1));
+        const float c2 = 1.f - powf(cfg.beta2, (float)(step + 1));
+        const float a = cfg.beta1 * m1[p] + (1.f - cfg.beta1) * gr;
+        const float v = cfg.beta2 * m2[p] + (1.f - cfg.beta2) * gr * gr;
+        m1[p] = a;
+        m2[p] = v;
+        params[p] -= cfg.lr * (a / c1) / (sqrtf(v / c2) + cfg.eps);
+    } else if (p == NP && st) {
+        st->loss = gbuf[NP] / (float)bsz;
+    }
+    if (clear && p < GBUF) gbuf[p] = 0.f;
 }
 
 // ---- 3a. calibration knots ------------------------------------------------------------
@@ -1316,6 +1288,27 @@ __global__ void k_check_sorted(const uint64_t* __restrict__ keys, uint64_t n, St
     if (ballot(bad) && (threadIdx.x & 63) == 0) atomicOr(&st->unsorted, 1u);
 }
 
+// Planted bucket-sort error (test hook): the first and last pair of the
+// output trade places.
+template <int VB>
+__global__ void k_fault_swap(uint64_t* __restrict__ keys, uint64_t* __restrict__ vals, uint64_t n) {
+    if (threadIdx.x != 0 || n < 2) return;
+    const uint64_t k = keys[0];
+    keys[0] = keys[n - 1];
+    keys[n - 1] = k;
+    if constexpr (VB != 0) {
+        const uint64_t v = vals[0];
+        vals[0] = vals[n - 1];
+        vals[n - 1] = v;
+    }
+}
+
+// Folds the status word of an inner LSD sort (sample, bucket-id rounds,
+// large buckets, fallback) into the learned path's own error word.
+__global__ void k_or_status(const uint32_t* __restrict__ src, State* __restrict__ st) {
+    if (threadIdx.x == 0 && *src) atomicOr(&st->err, *src);
+}
+
 __global__ void k_mlp_forward(const float* __restrict__ params, const float* __restrict__ x,
                               float* __restrict__ y, uint64_t m) {
     __shared__ Mlp W;
@@ -1380,7 +1373,15 @@ bool learn_layout(size_t n, int vb, LearnLayout* L) {
     return true;
 }
 
-int g_coop_grid = 0;
+// Test hooks (host copies, process-wide): parameters used instead of
+// training, and splitters used instead of the network's.
+struct Inject {
+    bool weights = false;
+    int fault = 0;  // RS_LEARNED_FAULT_*
+    std::vector<float> params;
+    std::vector<uint64_t> spl;
+};
+Inject g_inject;
 
 }  // namespace
 
@@ -1392,12 +1393,12 @@ size_t learned_ws_bytes(size_t n, int vb) {
     return L.total;
 }
 
-static rs_status launch_train(const float* xs, const float* ts, float* params, float* gbuf, State* st,
-                              const TrainCfg& cfg, int init, int grid, hipStream_t s) {
-    void* args[] = {(void*)&xs, (void*)&ts, (void*)&params, (void*)&gbuf, (void*)&st, (void*)&cfg,
-                    (void*)&init};
-    hipError_t e = hipLaunchCooperativeKernel((const void*)k_train, dim3(grid), dim3(TR_NT), args, 0, s);
-    return e == hipSuccess ? RS_OK : hip_fail(e);
+// Folds an inner LSD plan's status word into st->err (device side, in
+// stream order).
+static rs_status or_status(const unsigned char* plan_ws, const LsdPlan& p, State* st, hipStream_t s) {
+    hipLaunchKernelGGL(k_or_status, dim3(1), dim3(64), 0, s,
+                       reinterpret_cast<const uint32_t*>(plan_ws + p.off_status), st);
+    return launch_status();
 }
 
 rs_status learned_run(const void* kin, void* kout, const void* vin, void* vout, size_t n, int vb,
@@ -1408,6 +1409,7 @@ rs_status learned_run(const void* kin, void* kout, const void* vin, void* vout, 
     if (!ws_ || ws_bytes < L.total || (reinterpret_cast<uintptr_t>(ws_) % ALIGN)) return RS_ERR_WORKSPACE;
     unsigned char* ws = static_cast<unsigned char*>(ws_);
     State* st = reinterpret_cast<State*>(ws + L.off_state);
+    rep->err_word = &st->err;
     uint64_t* sample = reinterpret_cast<uint64_t*>(ws + L.off_sample);
     uint64_t* sorted = reinterpret_cast<uint64_t*>(ws + L.off_sorted);
     float* xs = reinterpret_cast<float*>(ws + L.off_xs);
@@ -1437,37 +1439,49 @@ rs_status learned_run(const void* kin, void* kout, const void* vin, void* vout, 
     if ((rc = launch_status()) != RS_OK) return rc;
     if ((rc = lsd_run(L.sample_plan, sample, sorted, nullptr, nullptr, ws + L.off_sample_ws, s)) != RS_OK)
         return rc;
+    if ((rc = or_status(ws + L.off_sample_ws, L.sample_plan, st, s)) != RS_OK) return rc;
     prof(s, KID_LEARN_SAMPLE, 0);
     hipLaunchKernelGGL(k_setup, dim3(1), dim3(64), 0, s, sorted, st, opt.feature_mode);
     hipLaunchKernelGGL(k_targets, dim3(M / 256), dim3(256), 0, s, sorted, st, xs, ts);
     prof(s, KID_LEARN_SAMPLE, 1);
     if ((rc = launch_status()) != RS_OK) return rc;
 
-    // 2. training (one cooperative launch)
-    if (g_coop_grid == 0) {
-        int dev = 0, cus = 0, per = 0;
-        if ((e = hipGetDevice(&dev)) != hipSuccess) return hip_fail(e);
-        if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)
-            return hip_fail(e);
-        if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_train, TR_NT, 0)) != hipSuccess)
-            return hip_fail(e);
-        const int cap = cus * (per > 0 ? per : 1);
-        g_coop_grid = opt.train_blocks < cap ? opt.train_blocks : cap;
-        if (g_coop_grid < 1) g_coop_grid = 1;
-    }
+    // 2. training: per Adam step one gradient launch and one update launch
+    //    (the gradient buffer, then the two moment vectors, in gbuf)
     if (opt.use_network) {
-        TrainCfg cfg{opt.train_steps, opt.lr, 0.9f, 0.999f, 1e-8f, M, 0};
-        prof(s, KID_LEARN_TRAIN, 0);
-        rc = launch_train(xs, ts, params, gbuf, st, cfg, 1, g_coop_grid, s);
-        prof(s, KID_LEARN_TRAIN, 1);
-        if (rc != RS_OK) return rc;
+        if (g_inject.weights) {
+            if ((e = hipMemcpyAsync(params, g_inject.params.data(), 4 * (size_t)NP, hipMemcpyHostToDevice, s)) !=
+                hipSuccess)
+                return hip_fail(e);
+        } else {
+            const TrainCfg cfg{opt.lr, 0.9f, 0.999f, 1e-8f, M, 0};
+            const int grid = opt.train_blocks;
+            float* m1 = gbuf + GBUF;
+            float* m2 = gbuf + 2 * GBUF;
+            prof(s, KID_LEARN_TRAIN, 0);
+            hipLaunchKernelGGL(k_train_init, dim3((NP + 255) / 256), dim3(256), 0, s, xs, M, params);
+            for (int step = 0; step < opt.train_steps; ++step) {
+                hipLaunchKernelGGL(k_grad, dim3(grid), dim3(TR_NT), 0, s, xs, ts, params, gbuf, cfg, step);
+                hipLaunchKernelGGL(k_adam, dim3((GBUF + 255) / 256), dim3(256), 0, s, params, m1, m2, gbuf, cfg,
+                                   step, (uint32_t)grid * TR_NT, st, 1);
+            }
+            prof(s, KID_LEARN_TRAIN, 1);
+            if ((rc = launch_status()) != RS_OK) return rc;
+        }
     }
 
     // 3. calibration knots, splitters
     prof(s, KID_LEARN_SPLIT, 0);
     hipLaunchKernelGGL(k_calibrate, dim3(1), dim3(256), 0, s, params, sorted, st, knot, opt.use_network);
     hipLaunchKernelGGL(k_splitters, dim3(NB / 256), dim3(256), 0, s, params, st, knot, spl, opt.use_network);
-    hipLaunchKernelGGL(k_split_fix, dim3(1), dim3(1024), 0, s, spl);
+    if (g_inject.fault == RS_LEARNED_FAULT_SPLITTERS) {
+        // test hook: the caller's splitters replace the network's, as given
+        if ((e = hipMemcpyAsync(spl, g_inject.spl.data(), 8 * (size_t)(NB - 1), hipMemcpyHostToDevice, s)) !=
+            hipSuccess)
+            return hip_fail(e);
+    } else {
+        hipLaunchKernelGGL(k_split_fix, dim3(1), dim3(1024), 0, s, spl);
+    }
     hipLaunchKernelGGL(k_top, dim3(TOP / 256), dim3(256), 0, s, spl, topg);
     prof(s, KID_LEARN_SPLIT, 1);
     if ((rc = launch_status()) != RS_OK) return rc;
@@ -1486,6 +1500,7 @@ rs_status learned_run(const void* kin, void* kout, const void* vin, void* vout, 
     if ((rc = lsd_run(L.pass_plan, bid0, bid1, kin, kout, big, s, vb ? vin : nullptr, vb ? vout : nullptr)) !=
         RS_OK)
         return rc;
+    if ((rc = or_status(big, L.pass_plan, st, s)) != RS_OK) return rc;
     // 6. bucket bounds, per-bucket sort
     if ((rc = fill_u32(start, NB + 1, (uint32_t)n, s)) != RS_OK) return rc;
     {
@@ -1529,6 +1544,7 @@ rs_status learned_run(const void* kin, void* kout, const void* vin, void* vout, 
     rep->buckets_overflowed = hs.ovf_buckets;
     rep->keys_overflowed = (int64_t)hs.ovf_keys;
     rep->device_error = hs.err;
+    rep->err_word = &st->err;
     rep->feature_mode = hs.mode;
 
     // too many keys, or too many separate buckets, beyond what one workgroup
@@ -1550,7 +1566,16 @@ rs_status learned_run(const void* kin, void* kout, const void* vin, void* vout, 
             uint64_t* kp = static_cast<uint64_t*>(kout) + a;
             uint64_t* vp = vb ? static_cast<uint64_t*>(vout) + a : nullptr;
             if ((rc = lsd_run(bp, kp, kp, vp, vp, big, s)) != RS_OK) return rc;
+            if ((rc = or_status(big, bp, st, s)) != RS_OK) return rc;
         }
+    }
+    if (!whole && g_inject.fault == RS_LEARNED_FAULT_SWAP) {
+        if (vb)
+            hipLaunchKernelGGL(k_fault_swap<8>, dim3(1), dim3(64), 0, s, (uint64_t*)kout, (uint64_t*)vout, (uint64_t)n);
+        else
+            hipLaunchKernelGGL(k_fault_swap<0>, dim3(1), dim3(64), 0, s, (uint64_t*)kout, (uint64_t*)nullptr,
+                               (uint64_t)n);
+        if ((rc = launch_status()) != RS_OK) return rc;
     }
     if (!whole) {
         prof(s, KID_LEARN_CHECK, 0);
@@ -1566,7 +1591,9 @@ rs_status learned_run(const void* kin, void* kout, const void* vin, void* vout, 
     }
     if (whole) {
         rep->fallback = 1;
-        return lsd_run(L.fb_plan, kin, kout, vb ? vin : nullptr, vb ? vout : nullptr, big, s);
+        if ((rc = lsd_run(L.fb_plan, kin, kout, vb ? vin : nullptr, vb ? vout : nullptr, big, s)) != RS_OK)
+            return rc;
+        if ((rc = or_status(big, L.fb_plan, st, s)) != RS_OK) return rc;
     }
     return RS_OK;
 }
@@ -1585,11 +1612,42 @@ rs_status mlp_loss_grad(const float* params, const float* x, const float* t, siz
     if (!m || m > 0x7FFFFFFFu) return RS_ERR_INVALID;
     rs_status rc = fill_u32(grad, GBUF, 0u, s);
     if (rc != RS_OK) return rc;
-    TrainCfg cfg{1, 0.f, 0.9f, 0.999f, 1e-8f, (uint32_t)m, 1};
-    const int init = 0;
-    State* st = nullptr;
-    hipLaunchKernelGGL(k_train, dim3(64), dim3(TR_NT), 0, s, x, t, const_cast<float*>(params), grad, st, cfg, init);
+    const TrainCfg cfg{0.f, 0.9f, 0.999f, 1e-8f, (uint32_t)m, 1};
+    hipLaunchKernelGGL(k_grad, dim3(64), dim3(TR_NT), 0, s, x, t, params, grad, cfg, 0);
     return launch_status();
+}
+
+rs_status mlp_adam_step(float* params, float* m1, float* m2, const float* grad, int step, float lr, float beta1,
+                        float beta2, float eps, hipStream_t s) {
+    const TrainCfg cfg{lr, beta1, beta2, eps, 1u, 0};
+    hipLaunchKernelGGL(k_adam, dim3((GBUF + 255) / 256), dim3(256), 0, s, params, m1, m2, const_cast<float*>(grad),
+                       cfg, step, 1u, (State*)nullptr, 0);
+    return launch_status();
+}
+
+rs_status learned_inject_weights(const float* params, size_t count) {
+    if (!params) {
+        g_inject.weights = false;
+        g_inject.params.clear();
+        return RS_OK;
+    }
+    if (count != (size_t)NP) return RS_ERR_INVALID;
+    g_inject.params.assign(params, params + NP);
+    g_inject.weights = true;
+    return RS_OK;
+}
+
+rs_status learned_inject_fault(int kind, const uint64_t* spl, size_t count) {
+    if (kind == RS_LEARNED_FAULT_SPLITTERS) {
+        if (!spl || count != (size_t)NB - 1) return RS_ERR_INVALID;
+        g_inject.spl.assign(spl, spl + (NB - 1));
+    } else if (kind == RS_LEARNED_FAULT_NONE || kind == RS_LEARNED_FAULT_SWAP) {
+        g_inject.spl.clear();
+    } else {
+        return RS_ERR_INVALID;
+    }
+    g_inject.fault = kind;
+    return RS_OK;
 }
 
 }  // namespace rs

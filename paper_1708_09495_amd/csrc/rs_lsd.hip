@@ -713,6 +713,8 @@ bool lsd_plan(size_t n, int kb, int vb, int bits, LsdPlan* p, int vb2) {
         if (!(kb == 2 && vb == 8 && (vb2 == 0 || vb2 == 8) && bits == 8)) return false;
     }
     if (kb != 2 && vb2 != 0) return false;
+    // digit counts, the global histograms and tile 0's prefix are 32-bit
+    if ((uint64_t)n >= LSD_MAX_N) return false;
     LsdPlan q;
     q.n = n;
     q.kb = kb;

@@ -74,8 +74,19 @@ __global__ void k_seg_scatter(const int64_t* __restrict__ off, uint64_t S, int64
 
 // ---- large segments: radix-2^8 rounds by one workgroup ------------------------
 
+// Tiles of the large path over a segment of L keys, and the keys of tile t:
+// every index and bound below is 64-bit, so segments up to 2^32 - 1 keys
+// (the largest the entry point accepts) never wrap a loop counter.
+__host__ __device__ constexpr uint64_t seg_tiles(uint64_t L) { return (L + SG_T - 1) / SG_T; }
+__host__ __device__ constexpr uint32_t seg_tile_keys(uint64_t L, uint64_t t) {
+    return t * SG_T >= L ? 0u : (L - t * SG_T < (uint64_t)SG_T ? (uint32_t)(L - t * SG_T) : (uint32_t)SG_T);
+}
+static_assert(seg_tiles(0xFFFFFFFFull) == 524288 && seg_tile_keys(0xFFFFFFFFull, 524287) == SG_T - 1 &&
+                  seg_tile_keys(0xFFFFFFFFull, 524288) == 0,
+              "the longest segment's last tile is partial and nothing follows it");
+
 __device__ void seg_large(const uint32_t* __restrict__ in, uint32_t* __restrict__ out,
-                          uint32_t* __restrict__ tmp, uint32_t L, unsigned char* smem,
+                          uint32_t* __restrict__ tmp, uint64_t L, unsigned char* smem,
                           uint32_t* status) {
     uint64_t* wmask = reinterpret_cast<uint64_t*>(smem);              // NW*R
     uint16_t* wcnt = reinterpret_cast<uint16_t*>(smem + 16384);       // NW*R
@@ -94,7 +105,7 @@ __device__ void seg_large(const uint32_t* __restrict__ in, uint32_t* __restrict_
     for (int i = tid; i < SG_P * SG_R; i += SG_NT) hist[i] = 0;
     __syncthreads();
     // one read counts the digits of all four rounds (four loads in flight)
-    uint32_t q = tid;
+    uint64_t q = tid;
     for (; q + 3 * SG_NT < L; q += 4 * SG_NT) {
         const uint32_t k0 = in[q], k1 = in[q + SG_NT], k2 = in[q + 2 * SG_NT], k3 = in[q + 3 * SG_NT];
 #pragma unroll
@@ -126,18 +137,20 @@ __device__ void seg_large(const uint32_t* __restrict__ in, uint32_t* __restrict_
         // keys of the tile at b (past the end: the largest key); the next
         // tile of the round loads while the current one is written out
         const uint32_t wb = wave * (SG_ITEMS * WAVE) + lane;
-        auto load_tile = [&](uint32_t b, uint32_t (&kt)[SG_ITEMS]) {
-            const uint32_t nv = b < L ? ((L - b) < (uint32_t)SG_T ? (L - b) : (uint32_t)SG_T) : 0u;
+        auto load_tile = [&](uint64_t t, uint32_t (&kt)[SG_ITEMS]) {
+            const uint32_t nv = seg_tile_keys(L, t);
+            const uint32_t* __restrict__ ts = src + t * SG_T;
 #pragma unroll
             for (int i = 0; i < SG_ITEMS; ++i) {
                 const uint32_t j = wb + i * WAVE;
-                kt[i] = j < nv ? src[b + j] : 0xFFFFFFFFu;
+                kt[i] = j < nv ? ts[j] : 0xFFFFFFFFu;
             }
         };
         uint32_t kn[SG_ITEMS];
         load_tile(0, kn);
-        for (uint32_t base = 0; base < L; base += SG_T) {
-            const uint32_t nvalid = (L - base) < (uint32_t)SG_T ? (L - base) : (uint32_t)SG_T;
+        const uint64_t ntiles = seg_tiles(L);
+        for (uint64_t ti = 0; ti < ntiles; ++ti) {
+            const uint32_t nvalid = seg_tile_keys(L, ti);
             uint32_t k[SG_ITEMS];
 #pragma unroll
             for (int i = 0; i < SG_ITEMS; ++i) k[i] = kn[i];
@@ -187,7 +200,7 @@ __device__ void seg_large(const uint32_t* __restrict__ in, uint32_t* __restrict_
                 skeys[loc[d] + wcnt[wave * SG_R + d] + (dr[i] >> 16)] = k[i];
             }
             __syncthreads();
-            load_tile(base + SG_T, kn);
+            load_tile(ti + 1, kn);
             // each digit's run of this tile lands at the digit's running offset
 #pragma unroll
             for (int q = 0; q < SG_ITEMS; ++q) {
@@ -196,7 +209,7 @@ __device__ void seg_large(const uint32_t* __restrict__ in, uint32_t* __restrict_
                     const uint32_t key = skeys[j];
                     const uint32_t d = (key >> shift) & 255u;
                     const uint32_t o = run[d] - loc[d] + j;
-                    if (o < L) dst[o] = key;
+                    if ((uint64_t)o < L) dst[o] = key;
                     else atomicOr(status, STATUS_RANGE);
                 }
             }
@@ -277,7 +290,7 @@ __attribute__((amdgpu_waves_per_eu(4))) __global__ __launch_bounds__(SG_NT) void
             const int c = len_class((int64_t)L);
             seg_small(in + b, out + b, (uint32_t)L, table.algo[c], table.p[c], smem);
         } else {
-            seg_large(in + b, out + b, tmp + b, (uint32_t)L, smem, status);
+            seg_large(in + b, out + b, tmp + b, L, smem, status);
         }
     }
 }

@@ -32,6 +32,47 @@ def multiset_hash(a, chunk=1 << 24):
     return int(h)
 
 
+def _lsr(z, k):
+    """Logical right shift of an int64 tensor holding uint64 bit patterns."""
+    return (z >> k) & ((1 << (64 - k)) - 1)
+
+
+def _s64(u):
+    return u - (1 << 64) if u >= (1 << 63) else u
+
+
+def mix64_dev(z):
+    """The same 64-bit mix as _mix64, on an int64 torch tensor holding
+    uint64 bit patterns (products wrap modulo 2^64)."""
+    z = (z ^ _lsr(z, 30)) * _s64(0xBF58476D1CE4E5B9)
+    z = (z ^ _lsr(z, 27)) * _s64(0x94D049BB133111EB)
+    return z ^ _lsr(z, 31)
+
+
+def multiset_hash_rows_dev(t2d):
+    """Per-row multiset hash (the sum of mix64(x + golden) mod 2^64, as
+    multiset_hash) of a 2-D int32/int64 torch tensor of unsigned keys: one
+    int64 per row, equal for rows that hold the same multiset."""
+    import torch
+    z = t2d.to(torch.int64)
+    if t2d.dtype == torch.int32:
+        z = z & 0xFFFFFFFF
+    return mix64_dev(z + _s64(0x9E3779B97F4A7C15)).sum(dim=1)
+
+
+def segment_hashes_dev(t, seg_ids, num_segments, chunk=1 << 27):
+    """Per-segment multiset hash of a 1-D int32 tensor of uint32 keys whose
+    element i belongs to segment seg_ids[i]: int64 tensor of num_segments."""
+    import torch
+    h = torch.zeros(num_segments, dtype=torch.int64, device=t.device)
+    for a in range(0, t.numel(), chunk):
+        b = min(t.numel(), a + chunk)
+        z = (t[a:b].to(torch.int64) & 0xFFFFFFFF) + _s64(0x9E3779B97F4A7C15)
+        h.index_add_(0, seg_ids[a:b], mix64_dev(z))
+        del z
+    return h
+
+
 def first_mismatch(a, b):
     d = np.nonzero(a != b)[0]
     return None if d.size == 0 else int(d[0])

@@ -73,6 +73,36 @@ def test_argument_errors_return_before_device_work(lib):
     lib.rs_sort_kv.argtypes = [vp, vp, vp, vp, ctypes.c_size_t, ctypes.c_int, ctypes.c_int,
                                ctypes.c_int, ctypes.c_int, vp, ctypes.c_size_t, vp]
     assert lib.rs_sort_kv(vp(256), vp(4096), vp(8192), vp(16384), 10, 4, 2, 8, 1, None, 0, None) == 1
+    # keys sorted in place but values not (and the reverse): the rounds pick
+    # their buffers from the keys, so the mixed case is refused, for every
+    # algorithm that takes values
+    for algo in (0, 1, 4):
+        assert lib.rs_sort_kv(vp(256), vp(1 << 20), vp(256), vp(1 << 24), 10, 8, 8, 8, algo,
+                              None, 0, None) == 1
+        assert lib.rs_sort_kv(vp(256), vp(1 << 20), vp(1 << 24), vp(1 << 20), 10, 8, 8, 8, algo,
+                              None, 0, None) == 1
+
+
+def test_lsd_key_count_limit(lib):
+    """Digit counts and prefixes of the LSD rounds are 32-bit words: n = 2^32
+    is refused (unsupported), n = 2^32 - 1 is planned."""
+    vp, sz = ctypes.c_void_p, ctypes.c_size_t
+    lib.rs_workspace_bytes.restype = ctypes.c_size_t
+    lib.rs_workspace_bytes.argtypes = [ctypes.c_int, sz, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                       ctypes.c_int, sz]
+    big = 1 << 32
+    for kb in (4, 8):
+        for bits in (8, 11):
+            assert lib.rs_workspace_bytes(0, big, kb, 0, bits, 1, 0) == 0
+            assert lib.rs_workspace_bytes(0, big - 1, kb, 0, bits, 1, 0) > (big - 1) * kb
+        assert lib.rs_workspace_bytes(1, big, kb, 4, 8, 1, 0) == 0
+    assert lib.rs_workspace_bytes(0, big, 8, 0, 8, 4, 0) == 0     # learned path
+    lib.rs_sort_u32.argtypes = [vp, vp, sz, ctypes.c_int, ctypes.c_int, vp, sz, vp]
+    lib.rs_sort_u64.argtypes = [vp, vp, sz, ctypes.c_int, ctypes.c_int, vp, sz, vp]
+    # in place, so no overlap check stops it first; refused before any device work
+    assert lib.rs_sort_u32(vp(256), vp(256), big, 8, 1, None, 0, None) == 2
+    assert lib.rs_sort_u32(vp(256), vp(256), big, 8, 0, None, 0, None) == 2
+    assert lib.rs_sort_u64(vp(256), vp(256), big, 8, 4, None, 0, None) == 2
 
 
 def test_block_network_queries_and_errors(lib):

@@ -155,3 +155,64 @@ def test_argument_errors(rs):
     assert L.rs_sort_u32(p(a.data_ptr()), p(a.data_ptr()), 100, 8, 1, None, 0, s) == rs.RS_ERR_WORKSPACE
     assert L.rs_sort_kv(p(a.data_ptr()), None, p(a.data_ptr()), None, 100, 4, 3, 8, 1, p(ws.data_ptr()), ws.numel(), s) == rs.RS_ERR_INVALID
     assert L.rs_sort_u32(None, None, 0, 8, 1, None, 0, s) == rs.RS_OK
+
+
+@pytest.mark.parametrize("log2n,extra", [(23, 1237), (28, 0)])
+def test_headline_tiles_bit_exact(rs, orc, log2n, extra):
+    """uint32 keys at radix 2^8 from 2^23 keys up take the large tiles (28
+    keys per thread), the launch configuration the benchmark times; here
+    every key is compared with the oracle, at 2^23 + 1,237 keys (a ragged
+    last tile) and at the benchmark's own 2^28 keys and seed."""
+    import gen
+    n = (1 << log2n) + extra
+    seed = gen.S0 + 2 if extra == 0 else gen.S0 + 21
+    print("case headline tiles n=%d" % n, flush=True)
+    import torch
+    a = gen.uniform_u32(seed, n)
+    d = torch.empty(n, dtype=torch.int32, device="cuda")
+    gen.uniform_u32_dev(seed, d)          # the benchmark's own input path
+    _check(to_host(d, np.uint32), a, "device generator against the host one")
+    out = rs.rs_sort_u32(d, radix_bits=8, algo=rs.RS_ALGO_LSD)
+    st = rs.rs_get_stats()
+    assert st.device_error == 0 and st.passes == 4 and st.tile_keys == 512 * 28
+    out = to_host(out, np.uint32)
+    _check(out, orc.lsd(a, 8), "u32 n=%d b=8" % n)
+
+
+@pytest.mark.parametrize("kdt", [np.uint32, np.uint64])
+def test_kv_in_place_odd_rounds(rs, orc, kdt):
+    """Key-value sorts in place whose executed round count is odd, so the
+    rounds end in the workspace and copy back: radix 2^11 for uint32 keys (3
+    rounds) and 2^10 for uint64 keys (7 rounds) with every round run, and AUTO at radix 2^8 on keys whose
+    top byte is zero (uint32: 3 of 4 rounds run; uint64 keys below 2^40:
+    5 of 8), each compared with the oracle's stable sort."""
+    rng = np.random.default_rng(21)
+    n = 300_007
+    below = 2**24 if kdt == np.uint32 else 2**40
+    odd_bits = 11 if kdt == np.uint32 else 10       # 3 rounds / 7 rounds
+    cases = [(odd_bits, rs.RS_ALGO_LSD, rng.integers(0, 2**32, n, dtype=np.uint64).astype(kdt)),
+             (8, rs.RS_ALGO_AUTO, rng.integers(0, below, n, dtype=np.uint64).astype(kdt))]
+    for bits, algo, keys in cases:
+        keys[::5] = keys[3]                       # ties
+        vals = np.arange(n, dtype=np.uint32)
+        print("case kv in place %s bits=%d algo=%d" % (np.dtype(kdt).name, bits, algo), flush=True)
+        kt, vt = to_dev(keys), to_dev(vals)
+        rs.rs_sort_kv(kt, vt, kt, vt, radix_bits=bits, algo=algo)
+        st = rs.rs_get_stats()
+        assert st.device_error == 0
+        assert (st.passes - st.passes_skipped) % 2 == 1
+        rk, rv = orc.lsd(keys, bits, vals=vals)
+        _check(to_host(kt, kdt), rk, "kv in place keys")
+        _check(to_host(vt, np.uint32), rv, "kv in place vals")
+
+
+def test_kv_mixed_in_place_refused(rs):
+    """Keys in place but values not (or the reverse) is refused on the host."""
+    import torch
+    k = torch.zeros(1000, dtype=torch.int32, device="cuda")
+    v = torch.zeros(1000, dtype=torch.int32, device="cuda")
+    v2 = torch.zeros(1000, dtype=torch.int32, device="cuda")
+    for kw in (dict(keys_out=k, vals_out=v2), dict(keys_out=torch.empty_like(k), vals_out=v)):
+        with pytest.raises(rs.RsError) as e:
+            rs.rs_sort_kv(k, v, radix_bits=11, algo=rs.RS_ALGO_LSD, **kw)
+        assert e.value.code == rs.RS_ERR_INVALID

@@ -8,7 +8,7 @@ principle is checked exhaustively on the GPU kernels themselves for n <= 16.
 import numpy as np
 import pytest
 
-from gpu_util import first_mismatch, multiset_hash, to_dev, to_host
+from gpu_util import first_mismatch, multiset_hash, multiset_hash_rows_dev, to_dev, to_host
 
 pytestmark = pytest.mark.gpu
 
@@ -98,17 +98,23 @@ def test_pad_value_and_duplicates(rs, orc, algo):
 def test_full_config_10000_instances(rs, orc, n):
     """The full small-n workload: 10,000 seeded instances per size in one
     launch per algorithm; 40 sampled instances against the oracle, every
-    instance checked sorted and a permutation of its input."""
+    instance checked sorted and holding the multiset of its own input (a
+    per-instance 64-bit multiset hash, so a key swapped between two
+    instances that both stay sorted is caught)."""
     import gen
     count = 10_000
     a = gen.instances_u32(gen.S0 + 3, n, count)
     dev = to_dev(a.ravel())
+    h_in = multiset_hash_rows_dev(dev.view(count, n))
     rng = np.random.default_rng(n)
     sample = rng.choice(count, 40, replace=False)
     for algo in ("BTN", "OET", "LDS_RADIX"):
         print("case full %s n=%d" % (algo, n), flush=True)
-        out = to_host(rs.rs_sort_batch_u32(dev, n, count, algo=getattr(rs, "RS_ALGO_" + algo)),
-                      np.uint32).reshape(count, n)
+        outd = rs.rs_sort_batch_u32(dev, n, count, algo=getattr(rs, "RS_ALGO_" + algo))
+        h_out = multiset_hash_rows_dev(outd.view(count, n))
+        bad = (h_out != h_in).nonzero()
+        assert bad.numel() == 0, "%s n=%d: instance %d changed its multiset" % (algo, n, int(bad[0]))
+        out = to_host(outd, np.uint32).reshape(count, n)
         assert (np.diff(out.astype(np.int64), axis=1) >= 0).all()
         assert multiset_hash(out.ravel()) == multiset_hash(a.ravel())
         for i in sample:
