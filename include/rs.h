@@ -195,6 +195,34 @@ const char* rs_status_string(rs_status s);
  * learned path's overflow counts), this synchronises that call's stream. */
 rs_status rs_get_stats(rs_stats* out);
 
+/* ---- sorting without allocation ------------------------------------------ */
+
+#define RS_NOALLOC_SCRATCH_BYTES (40u << 20) /* static scratch per device        */
+#define RS_NOALLOC_MAX_KEYS (1u << 22)       /* largest n of rs_sort_u32_noalloc */
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * sort as rs_sort_u32 with algo LSD or AUTO, taking no workspace.  Its
+ * scratch is a static device array of RS_NOALLOC_SCRATCH_BYTES inside the
+ * library, one copy on every device the library runs on, held until the
+ * process ends; the call makes no hipMalloc, hipFree or other allocating
+ * call (and records no kernel timing events).
+ *   in, out     DEVICE arrays of n uint32 keys (in == out: in place);
+ *   n           <= RS_NOALLOC_MAX_KEYS (4,194,304), else RS_ERR_UNSUPPORTED;
+ *   radix_bits  0 (= 8) or 1..11; 12..16 return RS_ERR_UNSUPPORTED;
+ *   algo        RS_ALGO_LSD or RS_ALGO_AUTO, else RS_ERR_UNSUPPORTED;
+ *   stream      a hipStream_t of the CURRENT device (NULL: the default
+ *               stream), else RS_ERR_INVALID; the current device's scratch
+ *               is used.
+ * Every call on one device shares that device's scratch, which keeps the
+ * last call's contents (each call clears what must start at zero itself):
+ * calls that may overlap on one device -- on different streams, or from
+ * different host threads -- race, and the caller must order them.
+ * Argument errors return before anything is enqueued, as for rs_sort_u32;
+ * rs_get_stats reports the call. */
+rs_status rs_sort_u32_noalloc(const uint32_t* in, uint32_t* out, size_t n, int radix_bits,
+                              rs_algo algo, void* stream);
+
 /* ---- tuning table --------------------------------------------------------- */
 
 /* The small-array choice for length class size_log2 = k (arrays of length

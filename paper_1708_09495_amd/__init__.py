@@ -18,7 +18,7 @@ RS_ALGO_AUTO, RS_ALGO_LSD, RS_ALGO_BTN, RS_ALGO_OET, RS_ALGO_LEARNED, RS_ALGO_LD
 RS_OP_SORT, RS_OP_SORT_KV, RS_OP_BATCH, RS_OP_SEGMENTED, RS_OP_TUNE, RS_OP_BLOCKS = range(6)
 
 EXPORTS = ["rs_sort_u32", "rs_sort_u64", "rs_sort_kv", "rs_sort_batch_u32", "rs_sort_segmented",
-           "rs_sort_blocks_u32", "rs_blocks_set_model", "rs_blocks_get_model", "rs_blocks_default_p",
+           "rs_sort_blocks_u32", "rs_sort_u32_noalloc", "rs_blocks_set_model", "rs_blocks_get_model", "rs_blocks_default_p",
            "rs_workspace_bytes", "rs_small_capacity", "rs_status_string", "rs_get_stats",
            "rs_tune_set", "rs_tune_get", "rs_tune_run", "rs_profile_enable", "rs_profile_read",
            "rs_learned_set_opts", "rs_learned_get_opts", "rs_mlp_num_params", "rs_mlp_forward",
@@ -96,6 +96,8 @@ def lib():
         L.rs_sort_batch_u32.argtypes = [vp, vp, sz, sz, i, i, vp, sz, vp]
         L.rs_sort_segmented.argtypes = [vp, vp, vp, sz, ctypes.c_int64, i, vp, sz, vp]
         L.rs_sort_blocks_u32.argtypes = [vp, vp, sz, i, i, vp, sz, vp]
+        L.rs_sort_u32_noalloc.argtypes = [vp, vp, sz, i, i, vp]
+        L.rs_sort_u32_noalloc.restype = i
         L.rs_blocks_set_model.argtypes = [ctypes.POINTER(rs_block_model)]
         L.rs_blocks_get_model.argtypes = [ctypes.POINTER(rs_block_model)]
         L.rs_blocks_default_p.argtypes = [sz, i]
@@ -373,6 +375,23 @@ def rs_sort_kv(keys_in, vals_in, keys_out=None, vals_out=None, radix_bits=0, alg
     _call(lib().rs_sort_kv(_ptr(keys_in), _ptr(vals_in), _ptr(keys_out), _ptr(vals_out), n, kb, vb,
                            radix_bits, algo, _ptr(ws), ws.numel(), _stream(stream)), "rs_sort_kv")
     return keys_out, vals_out
+
+
+RS_NOALLOC_SCRATCH_BYTES = 40 << 20
+RS_NOALLOC_MAX_KEYS = 1 << 22
+
+
+def rs_sort_u32_noalloc(keys_in, keys_out=None, radix_bits=0, algo=RS_ALGO_LSD, stream=None):
+    """rs_sort_u32 with the library's static scratch instead of a workspace
+    (n <= RS_NOALLOC_MAX_KEYS; LSD or AUTO)."""
+    _check_dev(keys_in, 4, "keys_in")
+    keys_out = keys_in.new_empty(keys_in.shape) if keys_out is None else keys_out
+    _check_dev(keys_out, 4, "keys_out")
+    if keys_out.numel() != keys_in.numel():
+        raise ValueError("keys_out must hold as many keys as keys_in")
+    _call(lib().rs_sort_u32_noalloc(_ptr(keys_in), _ptr(keys_out), keys_in.numel(), radix_bits, algo,
+                                    _stream(stream)), "rs_sort_u32_noalloc")
+    return keys_out
 
 
 def rs_sort_batch_u32(keys_in, n, count, keys_out=None, algo=RS_ALGO_AUTO, p=0, ws=None,

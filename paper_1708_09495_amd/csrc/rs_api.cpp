@@ -533,6 +533,7 @@ extern "C" int rs_tune_get(rs_tune_entry* out, int max) {
 
 namespace rs {
 bool g_prof_on = false;
+thread_local bool g_prof_muted = false;
 namespace {
 const char* const KNAMES[KID_COUNT_] = {
     "fill", "hist", "onesweep", "copy", "batch", "seg_plan", "seg",
@@ -615,4 +616,73 @@ extern "C" int rs_profile_read(rs_kernel_time* out, int max) {
         ++k;
     }
     return k;
+}
+
+// ---- sorting without allocation ----------------------------------------------
+//
+// rs_sort_u32_noalloc takes its scratch from `scratch`, a static device array
+// of the library's code object: every device the library runs on holds its
+// own copy until the process ends.  In host code the array's name is only a
+// host-side stand-in; the device address comes from hipGetSymbolAddress,
+// looked up once per device (with that device current) and kept.
+namespace rs {
+namespace {
+constexpr size_t NOALLOC_SCRATCH_BYTES = size_t(40) << 20;
+constexpr size_t NOALLOC_MAX_KEYS = size_t(1) << 22;
+constexpr int NOALLOC_MAX_DEVICES = 64;
+static_assert(NOALLOC_SCRATCH_BYTES == (size_t)RS_NOALLOC_SCRATCH_BYTES &&
+                  NOALLOC_MAX_KEYS == (size_t)RS_NOALLOC_MAX_KEYS,
+              "the header states the same limits");
+__device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+
+// Device address of the current device's copy of `scratch`.
+rs_status scratch_of_current_device(void** out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e);
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return RS_ERR_UNSUPPORTED;
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e);
+        if (!p || (reinterpret_cast<uintptr_t>(p) % ALIGN) != 0) return RS_ERR_HIP;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return RS_OK;
+}
+}  // namespace
+}  // namespace rs
+
+extern "C" rs_status rs_sort_u32_noalloc(const uint32_t* in, uint32_t* out, size_t n, int radix_bits,
+                                         rs_algo algo, void* stream) {
+    using namespace rs;
+    if (radix_bits < 0 || radix_bits > 16) return RS_ERR_INVALID;
+    if (algo != RS_ALGO_LSD && algo != RS_ALGO_AUTO) return RS_ERR_UNSUPPORTED;
+    if (n > NOALLOC_MAX_KEYS || default_bits(radix_bits) > 11) return RS_ERR_UNSUPPORTED;
+    if (n > 0 && (!in || !out)) return RS_ERR_INVALID;
+    if (n == 0) return sort_keys_common(in, out, nullptr, nullptr, 0, 4, 0, radix_bits, algo, nullptr, 0, stream);
+    LsdPlan plan;
+    if (!lsd_plan(n, 4, 0, default_bits(radix_bits), &plan) || plan.total > NOALLOC_SCRATCH_BYTES)
+        return RS_ERR_UNSUPPORTED;
+    // the stream must belong to the current device, whose scratch is used
+    if (stream) {
+        int cur = -1, sdev = -1;
+        hipError_t e = hipGetDevice(&cur);
+        if (e == hipSuccess) e = hipStreamGetDevice(static_cast<hipStream_t>(stream), &sdev);
+        if (e != hipSuccess) return hip_fail(e);
+        if (sdev != cur) return RS_ERR_INVALID;
+    }
+    void* ws = nullptr;
+    rs_status rc = scratch_of_current_device(&ws);
+    if (rc != RS_OK) return rc;
+    // no timing events either: creating one may allocate
+    g_prof_muted = true;
+    rc = sort_keys_common(in, out, nullptr, nullptr, n, 4, 0, radix_bits, algo, ws, NOALLOC_SCRATCH_BYTES,
+                          stream);
+    g_prof_muted = false;
+    return rc;
 }

@@ -43,9 +43,12 @@ enum KernelId {
     KID_COUNT_
 };
 extern bool g_prof_on;
+// set on the calling thread while an entry point that must not create HIP
+// events (the no-allocation sort) runs
+extern thread_local bool g_prof_muted;
 void prof_record(hipStream_t st, int kid, int phase);
 inline void prof(hipStream_t st, int kid, int phase) {
-    if (g_prof_on) prof_record(st, kid, phase);
+    if (g_prof_on && !g_prof_muted) prof_record(st, kid, phase);
 }
 
 // ---- LSD radix sort (count-sort rounds, Section 3) -----------------------

@@ -198,3 +198,24 @@ def test_block_model_default_p(lib):
         assert lib.rs_blocks_default_p(0, OET) == 0 and lib.rs_blocks_default_p(1000, 1) == 0
     finally:
         assert lib.rs_blocks_set_model(ctypes.byref(dflt)) == 0
+
+
+def test_noalloc_limits_on_the_host(lib):
+    """The no-allocation sort refuses, before any device call, sizes above
+    its limit, wide radices and algorithms other than LSD / AUTO; the
+    largest accepted plan at every radix fits its static scratch."""
+    vp, sz = ctypes.c_void_p, ctypes.c_size_t
+    lib.rs_sort_u32_noalloc.argtypes = [vp, vp, sz, ctypes.c_int, ctypes.c_int, vp]
+    lib.rs_sort_u32_noalloc.restype = ctypes.c_int
+    lib.rs_workspace_bytes.restype = ctypes.c_size_t
+    lib.rs_workspace_bytes.argtypes = [ctypes.c_int, sz, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                       ctypes.c_int, sz]
+    nmax, scratch = 1 << 22, 40 << 20
+    assert lib.rs_sort_u32_noalloc(vp(256), vp(256), nmax + 1, 8, 1, None) == 2
+    assert lib.rs_sort_u32_noalloc(vp(256), vp(256), 1000, 16, 1, None) == 2
+    assert lib.rs_sort_u32_noalloc(vp(256), vp(256), 1000, 8, 2, None) == 2
+    assert lib.rs_sort_u32_noalloc(vp(256), vp(256), 1000, 17, 1, None) == 1
+    assert lib.rs_sort_u32_noalloc(None, vp(256), 1000, 8, 1, None) == 1
+    for bits in range(1, 12):
+        need = lib.rs_workspace_bytes(0, nmax, 4, 0, bits, 1, 0)
+        assert 0 < need <= scratch, (bits, need)
