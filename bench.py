@@ -47,6 +47,8 @@ def parse():
     ap.add_argument("--kv", action="store_true", help="stable sort with a payload = index")
     ap.add_argument("--small-n", type=int, default=4096)
     ap.add_argument("--instances", type=int, default=10000)
+    ap.add_argument("--batch-only", action="store_true",
+                    help="small: time only the batched launch (no single-instance timings)")
     ap.add_argument("--algo", default="auto", choices=["auto", "btn", "oet", "lds_radix"])
     ap.add_argument("--p", type=int, default=0)
     ap.add_argument("--segments", type=int, default=65536)
@@ -307,14 +309,16 @@ def bench_small(args, torch, rs, gen, np):
     used = {rs.RS_ALGO_BTN: "btn", rs.RS_ALGO_OET: "oet", rs.RS_ALGO_LDS_RADIX: "lds_radix"}[st.algo]
     p = st.runs_p
     # one instance alone, and the device-wide LSD sort of one instance
-    one = keys[:n].clone()
-    one_out = torch.empty_like(one)
-    single_ms, _ = timed_steps(lambda: rs.rs_sort_batch_u32(one, n, 1, one_out, algo=algo, p=args.p),
-                               20, 3, rs, torch)
-    ws = torch.empty(rs.rs_workspace_bytes(rs.RS_OP_SORT, n, 4, 0, 8, rs.RS_ALGO_LSD), dtype=torch.uint8,
-                     device="cuda")
-    lsd_ms, _ = timed_steps(lambda: rs.rs_sort_u32(one, one_out, radix_bits=8, algo=rs.RS_ALGO_LSD, ws=ws),
-                            20, 3, rs, torch)
+    single_ms = lsd_ms = float("nan")
+    if not args.batch_only:
+        one = keys[:n].clone()
+        one_out = torch.empty_like(one)
+        single_ms, _ = timed_steps(lambda: rs.rs_sort_batch_u32(one, n, 1, one_out, algo=algo, p=args.p),
+                                   20, 3, rs, torch)
+        ws = torch.empty(rs.rs_workspace_bytes(rs.RS_OP_SORT, n, 4, 0, 8, rs.RS_ALGO_LSD), dtype=torch.uint8,
+                         device="cuda")
+        lsd_ms, _ = timed_steps(lambda: rs.rs_sort_u32(one, one_out, radix_bits=8, algo=rs.RS_ALGO_LSD, ws=ws),
+                                20, 3, rs, torch)
     total = n * count
     launches, tot_ms = prof.get("batch", (0, 0.0))
     avg = tot_ms / launches if launches else float("nan")
