@@ -225,44 +225,91 @@ rs_status rs_sort_u32_noalloc(const uint32_t* in, uint32_t* out, size_t n, int r
 
 /* ---- tuning table --------------------------------------------------------- */
 
-/* The small-array choice for length class size_log2 = k (arrays of length
- * in (2^(k-1), 2^k], k = 0..14): algo is RS_ALGO_BTN, RS_ALGO_OET or
- * RS_ALGO_LDS_RADIX, p the runs of BTN/OET.  Used by RS_ALGO_AUTO for small
- * single arrays and batches, and for the small segments of
- * rs_sort_segmented. */
+/* The tuned choices for length class size_log2 = k (arrays of length in
+ * (2^(k-1), 2^k], k = 0..32):
+ *   algo, p         k <= 14 only (0 above): the small-array algorithm,
+ *                   RS_ALGO_BTN, RS_ALGO_OET or RS_ALGO_LDS_RADIX, and p the
+ *                   runs of BTN/OET.  Used by RS_ALGO_AUTO for small single
+ *                   arrays and batches, and for the small segments of
+ *                   rs_sort_segmented;
+ *   radix_bits      the radix of LSD sorts of single uint32 arrays (keys
+ *                   only) of the class called with radix_bits = 0 (0: 8);
+ *   tile_items      keys per thread of the tiles of uint32 keys-only LSD
+ *                   rounds at radix <= 2^8: 16 or 28 (0: by size, 16 below
+ *                   2^23 keys);
+ *   seg_tile_items  keys per thread of the tiles that sort a segment of the
+ *                   class longer than one workgroup's capacity: 8 or 16
+ *                   (0: 16).
+ * The choices change the workspace a call needs: rs_workspace_bytes reads
+ * the same table, so size the workspace after the table is set. */
 typedef struct {
     int32_t size_log2;
     int32_t algo;
     int32_t p;
+    int32_t radix_bits;
+    int32_t tile_items;
+    int32_t seg_tile_items;
 } rs_tune_entry;
 
 /* Replaces the entries for the classes listed (process-wide, not
  * thread-safe against concurrent sorts).  RS_ERR_INVALID for a bad class,
- * algorithm, or p (p must be a power of two with 2^k / p <= 64). */
+ * algorithm, p (a power of two with 2^k / p <= 64), radix (0..16) or tile. */
 rs_status rs_tune_set(const rs_tune_entry* entries, int count);
 
-/* Copies the current table (classes 0..14) to `out` (host); returns the
+/* Copies the current table (classes 0..32) to `out` (host); returns the
  * number of entries written. */
 int rs_tune_get(rs_tune_entry* out, int max);
 
+/* Writes the current table to the file `path` as JSON, keyed by the current
+ * device's gfx architecture name and compute unit count:
+ *   {"format": "rs-tuning-1", "arch": "...", "cus": N,
+ *    "classes": [{"size_log2": k, "algo": a, "p": p, "radix_bits": b,
+ *                 "tile_items": t, "seg_tile_items": s}, ...]}
+ * RS_ERR_INVALID if the file cannot be written, RS_ERR_HIP without a device. */
+rs_status rs_tune_save(const char* path);
+
+/* Replaces the table with the one in `path` (as rs_tune_save writes it).
+ * RS_ERR_INVALID for a file that cannot be read or parsed or holds a bad
+ * entry; RS_ERR_UNSUPPORTED when it was written for another architecture or
+ * compute unit count; RS_ERR_HIP without a device.  The table is unchanged
+ * unless RS_OK.  The environment variable RS_TUNING_FILE names a file loaded
+ * the same way when the table is first used (silently skipped when it does
+ * not load). */
+rs_status rs_tune_load(const char* path);
+
 /* One timing of the autotuner. */
 typedef struct {
-    int32_t size_log2;     /* arrays of 2^size_log2 keys                        */
-    int32_t algo;          /* RS_ALGO_BTN / _OET / _LDS_RADIX, or RS_ALGO_LSD:  */
-                           /* the device-wide radix sort, one array per call    */
-    int32_t p;             /* runs of BTN/OET                                   */
-    int32_t chosen;        /* 1 if installed in the tuning table                */
-    double us_per_array;   /* batch of `instances` arrays in one launch, per array */
-    double us_single;      /* one array alone: launch latency included           */
+    int32_t size_log2;      /* arrays (or segments) of 2^size_log2 keys         */
+    int32_t algo;           /* RS_ALGO_BTN / _OET / _LDS_RADIX: one workgroup   */
+                            /* per array; RS_ALGO_LSD: the device-wide radix    */
+                            /* sort of one array; RS_ALGO_AUTO: the segmented   */
+                            /* sort of segments of that length                  */
+    int32_t p;              /* runs of BTN/OET                                   */
+    int32_t radix_bits;     /* LSD: radix bits                                   */
+    int32_t tile_items;     /* LSD: keys per thread of its tiles (0: by size)    */
+    int32_t seg_tile_items; /* segmented: keys per thread of a large segment's   */
+                            /* tiles                                             */
+    int32_t chosen;         /* 1 if installed in the tuning table                */
+    double us_per_array;    /* per array (segment), `instances` in one launch;  */
+                            /* LSD: one array per call                           */
+    double us_single;       /* one array alone: launch latency included          */
 } rs_tune_result;
 
-/* Autotuner: on the current device, for every class k = 1..14, times BTN and
- * OET at every valid p and the LDS radix sort on `instances` arrays of 2^k
- * keys in one launch (and one array alone), installs the fastest in the
- * tuning table, and times the device-wide LSD sort of one array.  Writes at
- * most `max` results to `out` (host) and returns how many, or minus an
- * rs_status.  Synchronises `stream`.  The workspace (device, at least
- * rs_workspace_bytes(RS_OP_TUNE, instances, ...)) holds the inputs. */
+/* Autotuner, on the current device:
+ *   - every class k = 1..14: BTN and OET at every valid p and the LDS radix
+ *     sort on `instances` arrays of 2^k keys in one launch (and one array
+ *     alone); the fastest is installed; the device-wide LSD sort of one
+ *     array is timed beside them (the small-n crossover);
+ *   - every class k = 15 .. min(24, lg(instances * 16384)): the LSD sort of
+ *     one array of 2^k uint32 keys at radix 2^8 with 16- and 28-key tiles
+ *     and at radix 2^11; the fastest is installed as the class's radix and
+ *     tile;
+ *   - every class k = 15 .. min(20, ...): the segmented sort of
+ *     instances * 16384 / 2^k segments of 2^k keys with 8- and 16-key-per-
+ *     thread tiles; the faster is installed.
+ * Writes at most `max` results to `out` (host) and returns how many, or
+ * minus an rs_status.  Synchronises `stream`.  The workspace (device, at
+ * least rs_workspace_bytes(RS_OP_TUNE, instances, ...)) holds the inputs. */
 int rs_tune_run(void* ws, size_t ws_bytes, int instances, void* stream, rs_tune_result* out,
                 int max);
 

@@ -20,7 +20,7 @@ RS_OP_SORT, RS_OP_SORT_KV, RS_OP_BATCH, RS_OP_SEGMENTED, RS_OP_TUNE, RS_OP_BLOCK
 EXPORTS = ["rs_sort_u32", "rs_sort_u64", "rs_sort_kv", "rs_sort_batch_u32", "rs_sort_segmented",
            "rs_sort_blocks_u32", "rs_sort_u32_noalloc", "rs_blocks_set_model", "rs_blocks_get_model", "rs_blocks_default_p",
            "rs_workspace_bytes", "rs_small_capacity", "rs_status_string", "rs_get_stats",
-           "rs_tune_set", "rs_tune_get", "rs_tune_run", "rs_profile_enable", "rs_profile_read",
+           "rs_tune_set", "rs_tune_get", "rs_tune_run", "rs_tune_save", "rs_tune_load", "rs_profile_enable", "rs_profile_read",
            "rs_learned_set_opts", "rs_learned_get_opts", "rs_mlp_num_params", "rs_mlp_forward",
            "rs_mlp_loss_grad", "rs_mlp_adam_step", "rs_mlp_set_weights", "rs_learned_debug_fault"]
 
@@ -53,13 +53,16 @@ class rs_block_model(ctypes.Structure):
 
 
 class rs_tune_entry(ctypes.Structure):
-    _fields_ = [("size_log2", ctypes.c_int32), ("algo", ctypes.c_int32), ("p", ctypes.c_int32)]
+    _fields_ = [("size_log2", ctypes.c_int32), ("algo", ctypes.c_int32), ("p", ctypes.c_int32),
+                ("radix_bits", ctypes.c_int32), ("tile_items", ctypes.c_int32),
+                ("seg_tile_items", ctypes.c_int32)]
 
 
 class rs_tune_result(ctypes.Structure):
     _fields_ = [("size_log2", ctypes.c_int32), ("algo", ctypes.c_int32), ("p", ctypes.c_int32),
-                ("chosen", ctypes.c_int32), ("us_per_array", ctypes.c_double),
-                ("us_single", ctypes.c_double)]
+                ("radix_bits", ctypes.c_int32), ("tile_items", ctypes.c_int32),
+                ("seg_tile_items", ctypes.c_int32), ("chosen", ctypes.c_int32),
+                ("us_per_array", ctypes.c_double), ("us_single", ctypes.c_double)]
 
 
 class rs_learned_opts(ctypes.Structure):
@@ -115,6 +118,10 @@ def lib():
         L.rs_tune_get.restype = i
         L.rs_tune_run.argtypes = [vp, sz, i, vp, ctypes.POINTER(rs_tune_result), i]
         L.rs_tune_run.restype = i
+        L.rs_tune_save.argtypes = [ctypes.c_char_p]
+        L.rs_tune_save.restype = i
+        L.rs_tune_load.argtypes = [ctypes.c_char_p]
+        L.rs_tune_load.restype = i
         L.rs_learned_set_opts.argtypes = [ctypes.POINTER(rs_learned_opts)]
         L.rs_learned_set_opts.restype = i
         L.rs_learned_get_opts.argtypes = [ctypes.POINTER(rs_learned_opts)]
@@ -196,13 +203,27 @@ def rs_get_stats():
     return s
 
 
+TUNE_FIELDS = ("size_log2", "algo", "p", "radix_bits", "tile_items", "seg_tile_items")
+
+
 def rs_tune_set(entries):
-    """entries: iterable of (size_log2, algo, p)."""
+    """entries: iterable of (size_log2, algo, p) or (size_log2, algo, p,
+    radix_bits, tile_items, seg_tile_items); missing fields are 0."""
     entries = list(entries)
     arr = (rs_tune_entry * max(1, len(entries)))()
-    for k, (c, a, p) in enumerate(entries):
-        arr[k].size_log2, arr[k].algo, arr[k].p = c, a, p
+    for k, e in enumerate(entries):
+        e = tuple(e) + (0,) * (len(TUNE_FIELDS) - len(e))
+        for f, v in zip(TUNE_FIELDS, e):
+            setattr(arr[k], f, int(v))
     _call(lib().rs_tune_set(arr, len(entries)), "rs_tune_set")
+
+
+def rs_tune_save(path):
+    _call(lib().rs_tune_save(os.fsencode(path)), "rs_tune_save")
+
+
+def rs_tune_load(path):
+    _call(lib().rs_tune_load(os.fsencode(path)), "rs_tune_load")
 
 
 def rs_blocks_get_model():
@@ -223,19 +244,21 @@ def rs_blocks_default_p(n, algo):
 
 
 def rs_tune_get():
-    arr = (rs_tune_entry * 16)()
-    k = lib().rs_tune_get(arr, 16)
-    return [(arr[i].size_log2, arr[i].algo, arr[i].p) for i in range(k)]
+    """The table as tuples (size_log2, algo, p, radix_bits, tile_items,
+    seg_tile_items), classes 0..32."""
+    arr = (rs_tune_entry * 64)()
+    k = lib().rs_tune_get(arr, 64)
+    return [tuple(getattr(arr[i], f) for f in TUNE_FIELDS) for i in range(k)]
 
 
 def rs_tune_run(instances=1024, ws=None, stream=None):
     """Runs the autotuner on the current device; returns a list of dicts
-    (size_log2, algo, p, chosen, us_per_array, us_single)."""
+    (the fields of rs_tune_result)."""
     torch = _torch()
     need = rs_workspace_bytes(RS_OP_TUNE, instances)
     ws = _workspace(need, ws, torch.device("cuda", torch.cuda.current_device()))
-    buf = (rs_tune_result * 512)()
-    k = lib().rs_tune_run(_ptr(ws), ws.numel(), instances, _stream(stream), buf, 512)
+    buf = (rs_tune_result * 1024)()
+    k = lib().rs_tune_run(_ptr(ws), ws.numel(), instances, _stream(stream), buf, 1024)
     if k < 0:
         raise RsError(-k, "rs_tune_run")
     return [{f: getattr(buf[i], f) for f, _ in rs_tune_result._fields_} for i in range(k)]

@@ -3,7 +3,11 @@
 // the kernels' launchers.  Nothing here waits on the device except
 // rs_get_stats.
 #include <cmath>
+#include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
+
+#include <string>
 
 #include "../../include/rs_learned.h"
 #include "rs_internal.hpp"
@@ -63,10 +67,11 @@ rs_status sort_wide(const void* kin, void* kout, const void* vin, void* vout, si
 // skip: rounds whose digit is the same for every key are skipped (decided on
 // the device from the all-round histogram).
 rs_status sort_lsd(const void* kin, void* kout, const void* vin, void* vout, size_t n, int kb,
-                   int vb, int bits, void* ws, size_t ws_bytes, hipStream_t st, bool skip = false) {
+                   int vb, int bits, void* ws, size_t ws_bytes, hipStream_t st, bool skip = false,
+                   int items = 0) {
     if (bits >= 12) return sort_wide(kin, kout, vin, vout, n, kb, vb, bits, ws, ws_bytes, st);
     LsdPlan p;
-    if (!lsd_plan(n, kb, vb, bits, &p)) return RS_ERR_UNSUPPORTED;
+    if (!lsd_plan(n, kb, vb, bits, &p, 0, items)) return RS_ERR_UNSUPPORTED;
     p.skip = skip && n < (1ull << 32) && p.passes <= 32;
     begin_call(RS_ALGO_LSD);
     g_call.stats.radix_bits = bits;
@@ -196,13 +201,14 @@ rs_status sort_keys_common(const void* kin, void* kout, const void* vin, void* v
     // rounds pick their buffers from the keys alone
     if (vb && n > 0 && (kin == kout) != (vin == vout)) return RS_ERR_INVALID;
     if ((uint64_t)n >= LSD_MAX_N) return RS_ERR_UNSUPPORTED;
-    bits = default_bits(bits);
+    int items = 0;
+    lsd_tuned(n, kb, vb, bits, &bits, &items);
     hipStream_t st = static_cast<hipStream_t>(stream);
     switch (algo) {
         case RS_ALGO_AUTO:
-            return sort_lsd(kin, kout, vin, vout, n, kb, vb, bits, ws, ws_bytes, st, true);
+            return sort_lsd(kin, kout, vin, vout, n, kb, vb, bits, ws, ws_bytes, st, true, items);
         case RS_ALGO_LSD:
-            return sort_lsd(kin, kout, vin, vout, n, kb, vb, bits, ws, ws_bytes, st);
+            return sort_lsd(kin, kout, vin, vout, n, kb, vb, bits, ws, ws_bytes, st, false, items);
         case RS_ALGO_LEARNED:
             if (kb != 8) return RS_ERR_UNSUPPORTED;
             return sort_learned(kin, kout, vin, vout, n, vb, ws, ws_bytes, st);
@@ -341,6 +347,7 @@ size_t rs_workspace_bytes(int op, size_t n, int key_bytes, int val_bytes, int ra
                           rs_algo algo, size_t num_segments) {
     (void)algo;
     (void)num_segments;
+    const int raw_bits = radix_bits;
     radix_bits = default_bits(radix_bits);
     if (op == RS_OP_SORT || op == RS_OP_SORT_KV) {
         if ((algo == RS_ALGO_BTN || algo == RS_ALGO_OET) && op == RS_OP_SORT && key_bytes == 4 &&
@@ -357,12 +364,14 @@ size_t rs_workspace_bytes(int op, size_t n, int key_bytes, int val_bytes, int ra
             return l > p.total ? l : p.total;
         }
         const int vb = op == RS_OP_SORT ? 0 : val_bytes;
-        if (radix_bits >= 12) {
+        int bits = 0, items = 0;
+        lsd_tuned(n, key_bytes, vb, raw_bits, &bits, &items);
+        if (bits >= 12) {
             WidePlan w;
-            return wide_plan(n, key_bytes, vb, radix_bits, &w) ? w.total : 0;
+            return wide_plan(n, key_bytes, vb, bits, &w) ? w.total : 0;
         }
         LsdPlan p;
-        if (!lsd_plan(n, key_bytes, vb, radix_bits, &p)) return 0;
+        if (!lsd_plan(n, key_bytes, vb, bits, &p, 0, items)) return 0;
         return p.total;
     }
     if (op == RS_OP_BATCH) return ALIGN;
@@ -484,34 +493,203 @@ extern "C" rs_status rs_learned_debug_fault(int kind, const uint64_t* splitters,
 // ---- tuning table -----------------------------------------------------------
 
 namespace rs {
+namespace {
+SegTable default_table() {
+    SegTable d{};
+    for (int c = 0; c < 64; ++c) {
+        const uint32_t npad = c < 15 ? (1u << c) : 16384u;
+        d.algo[c] = (int8_t)RS_ALGO_BTN;
+        d.p[c] = (int16_t)small_default_p(RS_ALGO_BTN, npad);
+    }
+    return d;
+}
+rs_status load_table(const char* path, SegTable* t);
+}  // namespace
+
+// The process-wide table: defaults, then RS_TUNING_FILE if it names a table
+// written for this device (same gfx architecture and compute unit count).
 SegTable& tune_table() {
     static SegTable t = [] {
-        SegTable d{};
-        for (int c = 0; c < 64; ++c) {
-            const uint32_t npad = c < 15 ? (1u << c) : 16384u;
-            d.algo[c] = (int8_t)RS_ALGO_BTN;
-            d.p[c] = (int16_t)small_default_p(RS_ALGO_BTN, npad);
-        }
+        SegTable d = default_table();
+        if (const char* f = getenv("RS_TUNING_FILE"))
+            if (*f) (void)load_table(f, &d);
         return d;
     }();
     return t;
 }
+
+void lsd_tuned(size_t n, int kb, int vb, int radix_bits, int* bits, int* items) {
+    int c = 0;
+    while (c < 63 && (1ull << c) < (unsigned long long)n) ++c;
+    const SegTable& t = tune_table();
+    const bool u32k = kb == 4 && vb == 0;
+    int b = radix_bits;
+    if (b == 0) b = (u32k && t.radix[c] > 0) ? t.radix[c] : 8;
+    *bits = b;
+    *items = (u32k && b <= 8) ? t.items[c] : 0;
+}
+
+namespace {
+bool entry_ok(const rs_tune_entry& e) {
+    const int c = e.size_log2;
+    if (c < 0 || c >= TUNE_CLASSES) return false;
+    if (c <= 14) {
+        if (e.algo != RS_ALGO_BTN && e.algo != RS_ALGO_OET && e.algo != RS_ALGO_LDS_RADIX) return false;
+        if (e.algo != RS_ALGO_LDS_RADIX && !small_valid_p(1u << c, e.p)) return false;
+    } else if (e.algo != 0 || e.p != 0) {
+        return false;  // no small-array choice above one workgroup's capacity
+    }
+    if (e.radix_bits < 0 || e.radix_bits > 16) return false;
+    if (e.tile_items != 0 && e.tile_items != 16 && e.tile_items != 28) return false;
+    if (e.seg_tile_items != 0 && e.seg_tile_items != 8 && e.seg_tile_items != 16) return false;
+    return true;
+}
+
+void put_entry(SegTable& t, const rs_tune_entry& e) {
+    const int c = e.size_log2;
+    if (c <= 14) {
+        t.algo[c] = (int8_t)e.algo;
+        t.p[c] = (int16_t)e.p;
+    }
+    t.radix[c] = (int8_t)e.radix_bits;
+    t.items[c] = (int8_t)e.tile_items;
+    t.seg_items[c] = (int8_t)e.seg_tile_items;
+}
+
+rs_tune_entry get_entry(const SegTable& t, int c) {
+    rs_tune_entry e{};
+    e.size_log2 = c;
+    e.algo = c <= 14 ? t.algo[c] : 0;
+    e.p = c <= 14 ? t.p[c] : 0;
+    e.radix_bits = t.radix[c];
+    e.tile_items = t.items[c];
+    e.seg_tile_items = t.seg_items[c];
+    return e;
+}
+
+// The current device's architecture name and compute unit count.
+rs_status device_key(char* arch, size_t cap, int* cus) {
+    int dev = 0;
+    hipDeviceProp_t prop;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipGetDeviceProperties(&prop, dev);
+    if (e != hipSuccess) return hip_fail(e);
+    snprintf(arch, cap, "%s", prop.gcnArchName);
+    *cus = prop.multiProcessorCount;
+    return RS_OK;
+}
+
+// ---- a small JSON reader for the tuning file: objects, arrays, strings
+//      without escapes other than \" and \\, integers
+struct JReader {
+    const char* p;
+    const char* end;
+    bool ok = true;
+    void ws() {
+        while (p < end && (*p == ' ' || *p == '\n' || *p == '\r' || *p == '\t')) ++p;
+    }
+    bool eat(char c) {
+        ws();
+        if (p < end && *p == c) {
+            ++p;
+            return true;
+        }
+        return false;
+    }
+    bool str(std::string* out) {
+        ws();
+        if (p >= end || *p != '"') return ok = false;
+        ++p;
+        out->clear();
+        while (p < end && *p != '"') {
+            if (*p == '\\' && p + 1 < end) ++p;
+            out->push_back(*p++);
+        }
+        if (p >= end) return ok = false;
+        ++p;
+        return true;
+    }
+    bool num(long long* out) {
+        ws();
+        const char* q = p;
+        if (q < end && *q == '-') ++q;
+        if (q >= end || *q < '0' || *q > '9') return ok = false;
+        long long v = 0;
+        while (q < end && *q >= '0' && *q <= '9' && v < (1ll << 50)) v = v * 10 + (*q++ - '0');
+        *out = (*p == '-') ? -v : v;
+        p = q;
+        return true;
+    }
+};
+
+rs_status load_table(const char* path, SegTable* t) {
+    FILE* f = fopen(path, "rb");
+    if (!f) return RS_ERR_INVALID;
+    std::string text;
+    char buf[4096];
+    size_t got;
+    while ((got = fread(buf, 1, sizeof buf, f)) > 0 && text.size() < (1u << 20)) text.append(buf, got);
+    fclose(f);
+    JReader r{text.data(), text.data() + text.size()};
+    std::string key, arch, fmt;
+    long long cus = -1;
+    SegTable nt = default_table();
+    bool have_classes = false;
+    if (!r.eat('{')) return RS_ERR_INVALID;
+    while (r.ok && !r.eat('}')) {
+        if (!r.str(&key) || !r.eat(':')) return RS_ERR_INVALID;
+        if (key == "format") {
+            if (!r.str(&fmt)) return RS_ERR_INVALID;
+        } else if (key == "arch") {
+            if (!r.str(&arch)) return RS_ERR_INVALID;
+        } else if (key == "cus") {
+            if (!r.num(&cus)) return RS_ERR_INVALID;
+        } else if (key == "classes") {
+            if (!r.eat('[')) return RS_ERR_INVALID;
+            have_classes = true;
+            while (r.ok && !r.eat(']')) {
+                rs_tune_entry e{};
+                if (!r.eat('{')) return RS_ERR_INVALID;
+                while (r.ok && !r.eat('}')) {
+                    long long v = 0;
+                    if (!r.str(&key) || !r.eat(':') || !r.num(&v)) return RS_ERR_INVALID;
+                    if (v < -(1ll << 30) || v > (1ll << 30)) return RS_ERR_INVALID;
+                    if (key == "size_log2") e.size_log2 = (int32_t)v;
+                    else if (key == "algo") e.algo = (int32_t)v;
+                    else if (key == "p") e.p = (int32_t)v;
+                    else if (key == "radix_bits") e.radix_bits = (int32_t)v;
+                    else if (key == "tile_items") e.tile_items = (int32_t)v;
+                    else if (key == "seg_tile_items") e.seg_tile_items = (int32_t)v;
+                    else return RS_ERR_INVALID;
+                    r.eat(',');
+                }
+                if (!entry_ok(e)) return RS_ERR_INVALID;
+                put_entry(nt, e);
+                r.eat(',');
+            }
+        } else {
+            return RS_ERR_INVALID;
+        }
+        r.eat(',');
+    }
+    if (!r.ok || fmt != "rs-tuning-1" || arch.empty() || cus < 1 || !have_classes) return RS_ERR_INVALID;
+    char darch[256];
+    int dcus = 0;
+    rs_status rc = device_key(darch, sizeof darch, &dcus);
+    if (rc != RS_OK) return rc;
+    if (arch != darch || cus != dcus) return RS_ERR_UNSUPPORTED;
+    *t = nt;
+    return RS_OK;
+}
+}  // namespace
 }  // namespace rs
 
 extern "C" rs_status rs_tune_set(const rs_tune_entry* e, int count) {
     if (count < 0 || (count > 0 && !e)) return RS_ERR_INVALID;
-    for (int i = 0; i < count; ++i) {
-        const int c = e[i].size_log2;
-        if (c < 0 || c > 14) return RS_ERR_INVALID;
-        if (e[i].algo != RS_ALGO_BTN && e[i].algo != RS_ALGO_OET && e[i].algo != RS_ALGO_LDS_RADIX)
-            return RS_ERR_INVALID;
-        if (e[i].algo != RS_ALGO_LDS_RADIX && !rs::small_valid_p(1u << c, e[i].p)) return RS_ERR_INVALID;
-    }
+    for (int i = 0; i < count; ++i)
+        if (!rs::entry_ok(e[i])) return RS_ERR_INVALID;
     rs::SegTable& t = rs::tune_table();
-    for (int i = 0; i < count; ++i) {
-        t.algo[e[i].size_log2] = (int8_t)e[i].algo;
-        t.p[e[i].size_log2] = (int16_t)e[i].p;
-    }
+    for (int i = 0; i < count; ++i) rs::put_entry(t, e[i]);
     return RS_OK;
 }
 
@@ -519,12 +697,47 @@ extern "C" int rs_tune_get(rs_tune_entry* out, int max) {
     if (!out || max <= 0) return 0;
     const rs::SegTable& t = rs::tune_table();
     int k = 0;
-    for (int c = 0; c <= 14 && k < max; ++c, ++k) {
-        out[k].size_log2 = c;
-        out[k].algo = t.algo[c];
-        out[k].p = t.p[c];
-    }
+    for (int c = 0; c < rs::TUNE_CLASSES && k < max; ++c, ++k) out[k] = rs::get_entry(t, c);
     return k;
+}
+
+extern "C" rs_status rs_tune_save(const char* path) {
+    if (!path || !*path) return RS_ERR_INVALID;
+    char arch[256];
+    int cus = 0;
+    rs_status rc = rs::device_key(arch, sizeof arch, &cus);
+    if (rc != RS_OK) return rc;
+    for (const char* q = arch; *q; ++q)
+        if (*q == '"' || *q == '\\') return RS_ERR_UNSUPPORTED;
+    std::string tmp = std::string(path) + ".tmp";
+    FILE* f = fopen(tmp.c_str(), "wb");
+    if (!f) return RS_ERR_INVALID;
+    const rs::SegTable& t = rs::tune_table();
+    bool ok = fprintf(f, "{\"format\": \"rs-tuning-1\", \"arch\": \"%s\", \"cus\": %d,\n \"classes\": [\n", arch,
+                      cus) > 0;
+    for (int c = 0; c < rs::TUNE_CLASSES && ok; ++c) {
+        const rs_tune_entry e = rs::get_entry(t, c);
+        ok = fprintf(f,
+                     "  {\"size_log2\": %d, \"algo\": %d, \"p\": %d, \"radix_bits\": %d, \"tile_items\": %d, "
+                     "\"seg_tile_items\": %d}%s\n",
+                     e.size_log2, e.algo, e.p, e.radix_bits, e.tile_items, e.seg_tile_items,
+                     c + 1 < rs::TUNE_CLASSES ? "," : "") > 0;
+    }
+    ok = ok && fprintf(f, " ]}\n") > 0;
+    ok = (fclose(f) == 0) && ok;
+    if (!ok || rename(tmp.c_str(), path) != 0) {
+        remove(tmp.c_str());
+        return RS_ERR_INVALID;
+    }
+    return RS_OK;
+}
+
+extern "C" rs_status rs_tune_load(const char* path) {
+    if (!path || !*path) return RS_ERR_INVALID;
+    rs::SegTable t;
+    rs_status rc = rs::load_table(path, &t);
+    if (rc == RS_OK) rs::tune_table() = t;
+    return rc;
 }
 
 // ---- kernel timing --------------------------------------------------------
@@ -662,11 +875,13 @@ extern "C" rs_status rs_sort_u32_noalloc(const uint32_t* in, uint32_t* out, size
     using namespace rs;
     if (radix_bits < 0 || radix_bits > 16) return RS_ERR_INVALID;
     if (algo != RS_ALGO_LSD && algo != RS_ALGO_AUTO) return RS_ERR_UNSUPPORTED;
-    if (n > NOALLOC_MAX_KEYS || default_bits(radix_bits) > 11) return RS_ERR_UNSUPPORTED;
+    if (n > NOALLOC_MAX_KEYS || radix_bits > 11) return RS_ERR_UNSUPPORTED;
     if (n > 0 && (!in || !out)) return RS_ERR_INVALID;
     if (n == 0) return sort_keys_common(in, out, nullptr, nullptr, 0, 4, 0, radix_bits, algo, nullptr, 0, stream);
+    int bits = 0, items = 0;
+    lsd_tuned(n, 4, 0, radix_bits, &bits, &items);
     LsdPlan plan;
-    if (!lsd_plan(n, 4, 0, default_bits(radix_bits), &plan) || plan.total > NOALLOC_SCRATCH_BYTES)
+    if (bits > 11 || !lsd_plan(n, 4, 0, bits, &plan, 0, items) || plan.total > NOALLOC_SCRATCH_BYTES)
         return RS_ERR_UNSUPPORTED;
     // the stream must belong to the current device, whose scratch is used
     if (stream) {

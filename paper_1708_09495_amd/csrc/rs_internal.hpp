@@ -80,8 +80,14 @@ constexpr size_t ROUTE_OFFSET = 16;
 constexpr uint64_t LSD_MAX_N = 1ull << 32;
 
 // Plans an LSD sort; returns false when (kb, vb, bits, vb2) is not supported
-// or n >= LSD_MAX_N.
-bool lsd_plan(size_t n, int kb, int vb, int bits, LsdPlan* p, int vb2 = 0);
+// or n >= LSD_MAX_N.  items: keys per thread of the tiles, 0 = by size; 16 or
+// 28 for uint32 keys without values at radix <= 2^8 (other shapes: 0 only).
+bool lsd_plan(size_t n, int kb, int vb, int bits, LsdPlan* p, int vb2 = 0, int items = 0);
+
+// Radix bits and tile items of an LSD sort of n keys asked for with
+// radix_bits (0: the tuned radix of n's length class for uint32 keys without
+// values, else 8), from the tuning table (items 0: by size).
+void lsd_tuned(size_t n, int kb, int vb, int radix_bits, int* bits, int* items);
 
 // Enqueues the whole LSD sort on `st`.  `ws` holds at least p.total bytes.
 rs_status lsd_run(const LsdPlan& p, const void* kin, void* kout, const void* vin, void* vout,
@@ -124,11 +130,15 @@ rs_status small_run(int algo, const uint32_t* in, uint32_t* out, uint32_t n, siz
 
 // ---- segmented sort ---------------------------------------------------------
 constexpr uint32_t SEG_SMALL_MAX = 16384;        // longest segment sorted in LDS
-// Small-array choice per length class c (length in (2^(c-1), 2^c]).
+// Tuned choices per length class c (length in (2^(c-1), 2^c]).
 struct SegTable {
-    int8_t algo[64];    // RS_ALGO_BTN, RS_ALGO_OET or RS_ALGO_LDS_RADIX
-    int16_t p[64];      // runs for BTN/OET
+    int8_t algo[64];      // small arrays: RS_ALGO_BTN, RS_ALGO_OET or RS_ALGO_LDS_RADIX
+    int16_t p[64];        // runs for BTN/OET
+    int8_t radix[64];     // single uint32 arrays, radix_bits = 0: LSD radix bits (0: 8)
+    int8_t items[64];     // their radix-2^8 tiles: keys per thread (0: by size)
+    int8_t seg_items[64]; // large segments: keys per thread of a tile, 8 or 16 (0: 16)
 };
+constexpr int TUNE_CLASSES = 33;  // classes 0 .. 32 in rs_tune_get / rs_tune_set
 struct SegPlan {
     size_t off_status = 0, off_cnt = 0, off_order = 0, off_tmp = 0;
     size_t zero_bytes = 0, total = 0;

@@ -707,7 +707,7 @@ rs_status fill_u32(void* p, size_t words, uint32_t v, hipStream_t st) {
     return launch_status();
 }
 
-bool lsd_plan(size_t n, int kb, int vb, int bits, LsdPlan* p, int vb2) {
+bool lsd_plan(size_t n, int kb, int vb, int bits, LsdPlan* p, int vb2, int items) {
     if ((kb != 4 && kb != 8) || (vb != 0 && vb != 4 && vb != 8) || bits < 1 || bits > 11) {
         // the only other shape: 16-bit digit keys, radix 2^8, 8-byte payload(s)
         if (!(kb == 2 && vb == 8 && (vb2 == 0 || vb2 == 8) && bits == 8)) return false;
@@ -723,8 +723,10 @@ bool lsd_plan(size_t n, int kb, int vb, int bits, LsdPlan* p, int vb2) {
     q.passes = (8 * kb + bits - 1) / bits;
     q.R = 1 << bits;
     q.vb2 = vb2;
+    const bool two_tiles = kb == 4 && vb == 0 && bits <= 8;  // the shape with a choice of tile
+    if (items != 0 && !(two_tiles && (items == LSD_ITEMS_SMALL || items == lsd_items(4, 0, 8)))) return false;
     q.tile = NT * (kb == 2 ? 16
-                           : (kb == 4 && vb == 0 && bits <= 8 && n < LSD_SMALL_N)
+                           : (two_tiles && (items ? items == LSD_ITEMS_SMALL : n < LSD_SMALL_N))
                                  ? LSD_ITEMS_SMALL
                                  : lsd_items(kb, vb, bits <= 8 ? 8 : 11));
     q.tiles = n ? (n + q.tile - 1) / q.tile : 0;

@@ -27,8 +27,8 @@ namespace {
 
 constexpr int SG_NT = 512;
 constexpr int SG_NW = SG_NT / WAVE;
-constexpr int SG_ITEMS = 16;
-constexpr int SG_T = SG_NT * SG_ITEMS;        // keys per tile of the large path
+constexpr int SG_ITEMS = 16;                  // keys per thread of a large-path tile (at most)
+constexpr int SG_T = SG_NT * SG_ITEMS;        // keys per tile of the large path (at most)
 constexpr int SG_R = 256;                     // radix 2^8
 constexpr int SG_P = 4;                       // rounds for 32-bit keys
 constexpr int NCLASS = 64;
@@ -74,20 +74,25 @@ __global__ void k_seg_scatter(const int64_t* __restrict__ off, uint64_t S, int64
 
 // ---- large segments: radix-2^8 rounds by one workgroup ------------------------
 
-// Tiles of the large path over a segment of L keys, and the keys of tile t:
-// every index and bound below is 64-bit, so segments up to 2^32 - 1 keys
-// (the largest the entry point accepts) never wrap a loop counter.
-__host__ __device__ constexpr uint64_t seg_tiles(uint64_t L) { return (L + SG_T - 1) / SG_T; }
-__host__ __device__ constexpr uint32_t seg_tile_keys(uint64_t L, uint64_t t) {
-    return t * SG_T >= L ? 0u : (L - t * SG_T < (uint64_t)SG_T ? (uint32_t)(L - t * SG_T) : (uint32_t)SG_T);
+// Tiles of T keys over a segment of L keys, and the keys of tile t: every
+// index and bound below is 64-bit, so segments up to 2^32 - 1 keys (the
+// largest the entry point accepts) never wrap a loop counter.
+__host__ __device__ constexpr uint64_t seg_tiles(uint64_t L, uint64_t T) { return (L + T - 1) / T; }
+__host__ __device__ constexpr uint32_t seg_tile_keys(uint64_t L, uint64_t t, uint64_t T) {
+    return t * T >= L ? 0u : (L - t * T < T ? (uint32_t)(L - t * T) : (uint32_t)T);
 }
-static_assert(seg_tiles(0xFFFFFFFFull) == 524288 && seg_tile_keys(0xFFFFFFFFull, 524287) == SG_T - 1 &&
-                  seg_tile_keys(0xFFFFFFFFull, 524288) == 0,
+static_assert(seg_tiles(0xFFFFFFFFull, 8192) == 524288 && seg_tile_keys(0xFFFFFFFFull, 524287, 8192) == 8191 &&
+                  seg_tile_keys(0xFFFFFFFFull, 524288, 8192) == 0 && seg_tiles(0xFFFFFFFFull, 4096) == 1048576 &&
+                  seg_tile_keys(0xFFFFFFFFull, 1048575, 4096) == 4095,
               "the longest segment's last tile is partial and nothing follows it");
 
+// IT keys per thread: tiles of SG_NT * IT keys (the tuning table picks 8 or
+// 16 per length class).
+template <int IT>
 __device__ void seg_large(const uint32_t* __restrict__ in, uint32_t* __restrict__ out,
                           uint32_t* __restrict__ tmp, uint64_t L, unsigned char* smem,
                           uint32_t* status) {
+    constexpr int TK = SG_NT * IT;  // keys per tile
     uint64_t* wmask = reinterpret_cast<uint64_t*>(smem);              // NW*R
     uint16_t* wcnt = reinterpret_cast<uint16_t*>(smem + 16384);       // NW*R
     uint32_t* skeys = reinterpret_cast<uint32_t*>(smem + 20480);      // T
@@ -136,31 +141,31 @@ __device__ void seg_large(const uint32_t* __restrict__ in, uint32_t* __restrict_
         }
         // keys of the tile at b (past the end: the largest key); the next
         // tile of the round loads while the current one is written out
-        const uint32_t wb = wave * (SG_ITEMS * WAVE) + lane;
-        auto load_tile = [&](uint64_t t, uint32_t (&kt)[SG_ITEMS]) {
-            const uint32_t nv = seg_tile_keys(L, t);
-            const uint32_t* __restrict__ ts = src + t * SG_T;
+        const uint32_t wb = wave * (IT * WAVE) + lane;
+        auto load_tile = [&](uint64_t t, uint32_t (&kt)[IT]) {
+            const uint32_t nv = seg_tile_keys(L, t, TK);
+            const uint32_t* __restrict__ ts = src + t * TK;
 #pragma unroll
-            for (int i = 0; i < SG_ITEMS; ++i) {
+            for (int i = 0; i < IT; ++i) {
                 const uint32_t j = wb + i * WAVE;
                 kt[i] = j < nv ? ts[j] : 0xFFFFFFFFu;
             }
         };
-        uint32_t kn[SG_ITEMS];
+        uint32_t kn[IT];
         load_tile(0, kn);
-        const uint64_t ntiles = seg_tiles(L);
+        const uint64_t ntiles = seg_tiles(L, TK);
         for (uint64_t ti = 0; ti < ntiles; ++ti) {
-            const uint32_t nvalid = seg_tile_keys(L, ti);
-            uint32_t k[SG_ITEMS];
+            const uint32_t nvalid = seg_tile_keys(L, ti, TK);
+            uint32_t k[IT];
 #pragma unroll
-            for (int i = 0; i < SG_ITEMS; ++i) k[i] = kn[i];
+            for (int i = 0; i < IT; ++i) k[i] = kn[i];
             __syncthreads();  // run[] set; previous tile finished with wcnt/skeys
-            uint32_t dr[SG_ITEMS];
+            uint32_t dr[IT];
             {
                 uint16_t* wc = wcnt + wave * SG_R;
                 uint64_t* wm = wmask + wave * SG_R;
 #pragma unroll
-                for (int i = 0; i < SG_ITEMS; ++i) {
+                for (int i = 0; i < IT; ++i) {
                     const uint32_t d = (k[i] >> shift) & 255u;
                     atomicOr((unsigned long long*)&wm[d], (unsigned long long)mybit);
                     const uint64_t m =
@@ -195,7 +200,7 @@ __device__ void seg_large(const uint32_t* __restrict__ in, uint32_t* __restrict_
             }
             __syncthreads();
 #pragma unroll
-            for (int i = 0; i < SG_ITEMS; ++i) {
+            for (int i = 0; i < IT; ++i) {
                 const uint32_t d = dr[i] & 0xFFFFu;
                 skeys[loc[d] + wcnt[wave * SG_R + d] + (dr[i] >> 16)] = k[i];
             }
@@ -203,7 +208,7 @@ __device__ void seg_large(const uint32_t* __restrict__ in, uint32_t* __restrict_
             load_tile(ti + 1, kn);
             // each digit's run of this tile lands at the digit's running offset
 #pragma unroll
-            for (int q = 0; q < SG_ITEMS; ++q) {
+            for (int q = 0; q < IT; ++q) {
                 const uint32_t j = q * SG_NT + tid;
                 if (j < nvalid) {
                     const uint32_t key = skeys[j];
@@ -290,7 +295,11 @@ __attribute__((amdgpu_waves_per_eu(4))) __global__ __launch_bounds__(SG_NT) void
             const int c = len_class((int64_t)L);
             seg_small(in + b, out + b, (uint32_t)L, table.algo[c], table.p[c], smem);
         } else {
-            seg_large(in + b, out + b, tmp + b, L, smem, status);
+            const int c = len_class((int64_t)L);
+            if (table.seg_items[c] == 8)
+                seg_large<8>(in + b, out + b, tmp + b, L, smem, status);
+            else
+                seg_large<16>(in + b, out + b, tmp + b, L, smem, status);
         }
     }
 }

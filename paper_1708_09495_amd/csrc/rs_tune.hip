@@ -23,6 +23,28 @@ __global__ void k_fill_hash(uint32_t* __restrict__ p, uint64_t n, uint64_t seed)
     }
 }
 
+// Offsets of S segments of L keys each: off[i] = i * L, i = 0..S.
+__global__ void k_even_offsets(int64_t* __restrict__ off, uint64_t S, uint64_t L) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i <= S; i += stride) off[i] = (int64_t)(i * L);
+}
+
+constexpr int TUNE_LSD_MAX = 24;  // largest class of the single-array LSD timings
+constexpr int TUNE_SEG_MAX = 20;  // largest class of the segment timings
+
+struct LsdCand {
+    int bits, items;
+};
+constexpr LsdCand LSD_CANDS[] = {{8, 16}, {8, 28}, {11, 0}};
+
+// Largest class the tuner times with `instances` small arrays of workspace.
+int tune_cmax(int instances) {
+    const uint64_t N = (uint64_t)instances * SMALL_CAP_U32;
+    int c = 14;
+    while (c < TUNE_LSD_MAX && (1ull << (c + 1)) <= N) ++c;
+    return c;
+}
+
 struct Timer {
     hipEvent_t a = nullptr, b = nullptr;
     bool ok = false;
@@ -35,10 +57,28 @@ struct Timer {
 
 }  // namespace
 
-size_t tune_ws_bytes(int instances) {
+// Workspace of the tuner: the input and output arrays of instances * 16384
+// keys, then the largest LSD or segmented-sort workspace it times, then the
+// segment offsets.
+namespace {
+size_t tune_inner_bytes(int instances) {
+    const uint64_t N = (uint64_t)instances * SMALL_CAP_U32;
     LsdPlan lp;
     lsd_plan(SMALL_CAP_U32, 4, 0, 8, &lp);
-    return align_up((size_t)instances * SMALL_CAP_U32 * 4) * 2 + align_up(lp.total);
+    size_t inner = lp.total;
+    const int cmax = tune_cmax(instances);
+    for (int c = 15; c <= cmax; ++c)
+        for (const LsdCand& cd : LSD_CANDS)
+            if (lsd_plan(1ull << c, 4, 0, cd.bits, &lp, 0, cd.items) && lp.total > inner) inner = lp.total;
+    SegPlan sp;
+    if (cmax >= 15 && seg_plan(N >> 15, (int64_t)N, &sp) && sp.total > inner) inner = sp.total;
+    return align_up(inner);
+}
+}  // namespace
+
+size_t tune_ws_bytes(int instances) {
+    const uint64_t N = (uint64_t)instances * SMALL_CAP_U32;
+    return align_up((size_t)N * 4) * 2 + tune_inner_bytes(instances) + align_up(8 * ((N >> 15) + 1));
 }
 
 }  // namespace rs
@@ -55,6 +95,7 @@ extern "C" int rs_tune_run(void* ws, size_t ws_bytes, int instances, void* strea
     uint32_t* in = reinterpret_cast<uint32_t*>(w);
     uint32_t* dst = reinterpret_cast<uint32_t*>(w + align_up((size_t)instances * SMALL_CAP_U32 * 4));
     void* lws = w + 2 * align_up((size_t)instances * SMALL_CAP_U32 * 4);
+    const int cmax = tune_cmax(instances);
     LsdPlan lp;
     lsd_plan(SMALL_CAP_U32, 4, 0, 8, &lp);
     const uint64_t total = (uint64_t)instances * SMALL_CAP_U32;
@@ -92,6 +133,7 @@ extern "C" int rs_tune_run(void* ws, size_t ws_bytes, int instances, void* strea
             const double ms = time_ms([&] { small_run(cd.algo, in, dst, n, (size_t)instances, cd.p, st); }, 3);
             const double single = time_ms([&] { small_run(cd.algo, in, dst, n, 1, cd.p, st); }, 5);
             if (k < max) {
+                out[k] = rs_tune_result{};
                 out[k].size_log2 = c;
                 out[k].algo = cd.algo;
                 out[k].p = cd.p;
@@ -115,10 +157,10 @@ extern "C" int rs_tune_run(void* ws, size_t ws_bytes, int instances, void* strea
         lsd_plan(n, 4, 0, 8, &p1);
         const double lsd = time_ms([&] { lsd_run(p1, in, dst, nullptr, nullptr, lws, st); }, 5);
         if (k < max) {
+            out[k] = rs_tune_result{};
             out[k].size_log2 = c;
             out[k].algo = RS_ALGO_LSD;
-            out[k].p = 0;
-            out[k].chosen = 0;
+            out[k].radix_bits = 8;
             out[k].us_per_array = lsd * 1e3;
             out[k].us_single = lsd * 1e3;
             ++k;
@@ -126,5 +168,71 @@ extern "C" int rs_tune_run(void* ws, size_t ws_bytes, int instances, void* strea
     }
     table.algo[0] = table.algo[1];
     table.p[0] = 1;
+
+    // Larger classes: the single-array LSD sort's radix and tile, and the
+    // tile of a segment sorted by one workgroup's radix rounds.
+    const uint64_t N = (uint64_t)instances * SMALL_CAP_U32;
+    int64_t* off = reinterpret_cast<int64_t*>(static_cast<unsigned char*>(lws) + tune_inner_bytes(instances));
+    for (int c = 15; c <= cmax; ++c) {
+        const uint64_t n = 1ull << c;
+        double best = INFINITY;
+        int bb = 8, bi = 0, bk = -1;
+        for (const LsdCand& cd : LSD_CANDS) {
+            LsdPlan pl;
+            if (!lsd_plan(n, 4, 0, cd.bits, &pl, 0, cd.items)) continue;
+            const double ms = time_ms([&] { lsd_run(pl, in, dst, nullptr, nullptr, lws, st); }, 5);
+            if (k < max) {
+                out[k] = rs_tune_result{};
+                out[k].size_log2 = c;
+                out[k].algo = RS_ALGO_LSD;
+                out[k].radix_bits = cd.bits;
+                out[k].tile_items = cd.items;
+                out[k].us_per_array = ms * 1e3;
+                out[k].us_single = ms * 1e3;
+                ++k;
+            }
+            if (ms < best) {
+                best = ms;
+                bb = cd.bits;
+                bi = cd.items;
+                bk = k - 1;
+            }
+        }
+        if (bk >= 0 && bk < max) out[bk].chosen = 1;
+        table.radix[c] = (int8_t)bb;
+        table.items[c] = (int8_t)bi;
+        if (c > TUNE_SEG_MAX) continue;
+        // S segments of 2^c keys, sorted as one batch with each tile size
+        const uint64_t S = N >> c;
+        SegPlan sp;
+        if (!seg_plan(S, (int64_t)(S * n), &sp)) continue;
+        hipLaunchKernelGGL(k_even_offsets, dim3(64), dim3(256), 0, st, off, S, n);
+        if (hipGetLastError() != hipSuccess) return -RS_ERR_HIP;
+        best = INFINITY;
+        int bs = 16;
+        bk = -1;
+        for (int it : {8, 16}) {
+            SegTable t2 = table;
+            t2.seg_items[c] = (int8_t)it;
+            const double ms = time_ms([&] { seg_run(sp, in, dst, off, S, (int64_t)(S * n), t2, lws, st); }, 3);
+            if (k < max) {
+                out[k] = rs_tune_result{};
+                out[k].size_log2 = c;
+                out[k].algo = RS_ALGO_AUTO;
+                out[k].seg_tile_items = it;
+                out[k].us_per_array = ms * 1e3 / (double)S;
+                out[k].us_single = NAN;
+                ++k;
+            }
+            if (ms < best) {
+                best = ms;
+                bs = it;
+                bk = k - 1;
+            }
+        }
+        if (bk >= 0 && bk < max) out[bk].chosen = 1;
+        table.seg_items[c] = (int8_t)bs;
+    }
+    if (hipStreamSynchronize(st) != hipSuccess) return -RS_ERR_HIP;
     return k;
 }

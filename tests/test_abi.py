@@ -219,3 +219,48 @@ def test_noalloc_limits_on_the_host(lib):
     for bits in range(1, 12):
         need = lib.rs_workspace_bytes(0, nmax, 4, 0, bits, 1, 0)
         assert 0 < need <= scratch, (bits, need)
+
+
+class _TuneEntry(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_int32) for f in ("size_log2", "algo", "p", "radix_bits", "tile_items",
+                                               "seg_tile_items")]
+
+
+def test_tuning_table_on_the_host(lib, tmp_path):
+    """The tuning table's checks and file format, host side: classes 0..32,
+    small-array choices only up to class 14, radix 0..16, tiles 16/28 and
+    8/16; a file that does not parse (or holds a bad entry) is refused before
+    any device call; a well-formed file needs the device it was written for
+    (none here)."""
+    E = _TuneEntry
+    lib.rs_tune_set.argtypes = [ctypes.POINTER(E), ctypes.c_int]
+    lib.rs_tune_get.argtypes = [ctypes.POINTER(E), ctypes.c_int]
+    lib.rs_tune_load.argtypes = [ctypes.c_char_p]
+    arr = (E * 64)()
+    assert lib.rs_tune_get(arr, 64) == 33
+    old = [tuple(getattr(arr[i], f) for f, _ in E._fields_) for i in range(33)]
+    assert all(e[1] == 0 and e[2] == 0 for e in old[15:])
+
+    def put(*e):
+        one = (E * 1)(E(*e))
+        return lib.rs_tune_set(one, 1)
+    try:
+        assert put(20, 0, 0, 11, 0, 8) == 0
+        assert put(12, 2, 64, 8, 28, 16) == 0
+        assert lib.rs_tune_get(arr, 64) == 33
+        assert tuple(getattr(arr[20], f) for f, _ in E._fields_) == (20, 0, 0, 11, 0, 8)
+        for bad in ((33, 0, 0, 8, 0, 0), (20, 2, 4, 8, 0, 0), (20, 0, 0, 17, 0, 0), (20, 0, 0, 8, 20, 0),
+                    (20, 0, 0, 8, 0, 12), (12, 2, 3, 8, 0, 0)):
+            assert put(*bad) == 1, bad
+        good = ('{"format": "rs-tuning-1", "arch": "gfx950", "cus": 256, "classes": '
+                '[{"size_log2": 20, "algo": 0, "p": 0, "radix_bits": 11, "tile_items": 0, "seg_tile_items": 8}]}')
+        for text, rc in ((good, 4), (good.replace("rs-tuning-1", "other"), 1), ("{", 1), ("[]", 1),
+                         (good.replace('"radix_bits": 11', '"radix_bits": 99'), 1),
+                         (good.replace('"algo": 0', '"algo": 2'), 1), (good.replace('"cus"', '"cuz"'), 1)):
+            f = tmp_path / "t.json"
+            f.write_text(text)
+            assert lib.rs_tune_load(str(f).encode()) == rc, text
+        assert lib.rs_tune_load(str(tmp_path / "missing.json").encode()) == 1
+    finally:
+        restore = (E * 33)(*[E(*e) for e in old])
+        assert lib.rs_tune_set(restore, 33) == 0

@@ -78,7 +78,7 @@ def test_tuning_table_round_trip(rs, orc):
     old = rs.rs_tune_get()
     try:
         rs.rs_tune_set([(c, rs.RS_ALGO_OET, max(1, (1 << c) // 32)) for c in range(1, 15)])
-        assert all(a == rs.RS_ALGO_OET for c, a, p in rs.rs_tune_get()[1:])
+        assert all(e[1] == rs.RS_ALGO_OET for e in rs.rs_tune_get()[1:15])
         lens = np.array([3, 700, 9000, 16384], dtype=np.int64)
         off = _offsets(lens)
         keys = gen.uniform_u32(gen.S0 + 41, int(off[-1]))

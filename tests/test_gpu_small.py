@@ -149,7 +149,7 @@ def test_autotuner_installs_fastest_and_stays_correct(rs, orc):
     old = rs.rs_tune_get()
     try:
         res = rs.rs_tune_run(instances=256)
-        table = {c: (a, p) for c, a, p in rs.rs_tune_get()}
+        table = {e[0]: e[1:] for e in rs.rs_tune_get()}
         for c in range(1, 15):
             rows = [r for r in res if r["size_log2"] == c and r["algo"] != rs.RS_ALGO_LSD]
             assert rows and all(r["us_per_array"] > 0 for r in rows)

@@ -1,0 +1,111 @@
+"""The autotuner beyond the small arrays, and its table on file: the radix
+and tile it installs for single arrays (LSD) and the tile for segments
+sorted by one workgroup's radix rounds are the fastest it timed; the table
+round-trips through rs_tune_save / rs_tune_load and through RS_TUNING_FILE
+in a fresh process; sorts under the tuned table still match the oracle."""
+import json
+import os
+import subprocess
+import sys
+
+import numpy as np
+import pytest
+
+from gpu_util import first_mismatch, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def rs():
+    import paper_1708_09495_amd as rs
+    rs.lib()
+    return rs
+
+
+@pytest.fixture(scope="module")
+def tuned(rs, tmp_path_factory):
+    """Runs the tuner once (256 instances: classes up to 2^22) and saves the
+    table; restores the previous table afterwards."""
+    old = rs.rs_tune_get()
+    res = rs.rs_tune_run(instances=256)
+    path = str(tmp_path_factory.mktemp("tune") / "table.json")
+    rs.rs_tune_save(path)
+    yield res, rs.rs_tune_get(), path
+    rs.rs_tune_set(old)
+
+
+def test_large_classes_install_the_fastest(rs, tuned):
+    res, table, _ = tuned
+    t = {e[0]: e for e in table}
+    for c in range(15, 23):
+        rows = [r for r in res if r["size_log2"] == c and r["algo"] == rs.RS_ALGO_LSD]
+        assert {(r["radix_bits"], r["tile_items"]) for r in rows} == {(8, 16), (8, 28), (11, 0)}, c
+        best = min(rows, key=lambda r: r["us_per_array"])
+        assert best["chosen"] == 1 and sum(r["chosen"] for r in rows) == 1
+        assert (t[c][3], t[c][4]) == (best["radix_bits"], best["tile_items"])
+        print("class %d: LSD %s" % (c, ", ".join("%d-bit/%d: %.1f us" % (r["radix_bits"], r["tile_items"],
+                                                                         r["us_per_array"]) for r in rows)))
+        if c <= 20:
+            seg = [r for r in res if r["size_log2"] == c and r["algo"] == rs.RS_ALGO_AUTO]
+            assert {r["seg_tile_items"] for r in seg} == {8, 16}
+            bseg = min(seg, key=lambda r: r["us_per_array"])
+            assert bseg["chosen"] == 1 and t[c][5] == bseg["seg_tile_items"]
+
+
+def test_table_round_trips_through_the_file(rs, tuned):
+    import torch
+    _, table, path = tuned
+    with open(path) as f:
+        d = json.load(f)
+    prop = torch.cuda.get_device_properties(0)
+    assert d["format"] == "rs-tuning-1" and d["cus"] == prop.multi_processor_count
+    assert d["arch"].split(":")[0] == prop.gcnArchName.split(":")[0]
+    assert len(d["classes"]) == 33
+    # back to defaults, then the file
+    rs.rs_tune_set([(c, rs.RS_ALGO_BTN, 1 << max(0, c - 5)) if c <= 14 else (c, 0, 0) for c in range(0, 15)]
+                   + [(c, 0, 0, 0, 0, 0) for c in range(15, 33)])
+    assert rs.rs_tune_get() != table
+    rs.rs_tune_load(path)
+    assert rs.rs_tune_get() == table
+    # written for another device: refused, table unchanged
+    d2 = dict(d, arch="gfx000")
+    other = path + ".other.json"
+    with open(other, "w") as f:
+        json.dump(d2, f)
+    with pytest.raises(rs.RsError) as e:
+        rs.rs_tune_load(other)
+    assert e.value.code == rs.RS_ERR_UNSUPPORTED
+    assert rs.rs_tune_get() == table
+    # a fresh process picks the table up from RS_TUNING_FILE at first use
+    code = ("import sys; sys.path.insert(0, %r); import paper_1708_09495_amd as rs; rs.lib(); "
+            "print(repr(rs.rs_tune_get()))" % ROOT)
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=120,
+                         env=dict(os.environ, RS_TUNING_FILE=path))
+    assert out.returncode == 0, out.stderr[-2000:]
+    assert eval(out.stdout.strip().splitlines()[-1]) == table
+
+
+def test_sorts_under_the_tuned_table_match_the_oracle(rs, orc, tuned):
+    import gen
+    import torch
+    _, table, _ = tuned
+    t = {e[0]: e for e in table}
+    # single arrays with radix_bits = 0 take the class's tuned radix
+    for n in ((1 << 15) + 17, (1 << 19) - 3, (1 << 21) + 1001, 1 << 22):
+        c = (n - 1).bit_length()
+        a = gen.uniform_u32(gen.S0 + 70 + c, n)
+        out = to_host(rs.rs_sort_u32(to_dev(a), radix_bits=0, algo=rs.RS_ALGO_LSD), np.uint32)
+        st = rs.rs_get_stats()
+        assert st.device_error == 0 and st.radix_bits == (t[c][3] or 8), (n, st.radix_bits, t[c])
+        assert first_mismatch(out, orc.lsd(a, 8)) is None, n
+    # segments across the tuned classes, one launch
+    lens = np.array([20000, 40000, 70000, 131072, 300001, 1 << 20, 5, 16384, 0, 600000], dtype=np.int64)
+    off = np.zeros(lens.size + 1, dtype=np.int64)
+    np.cumsum(lens, out=off[1:])
+    keys = gen.uniform_u32(gen.S0 + 77, int(off[-1]))
+    out = rs.rs_sort_segmented(to_dev(keys), torch.from_numpy(off).cuda())
+    assert rs.rs_get_stats().device_error == 0
+    assert first_mismatch(to_host(out, np.uint32), orc.segmented(keys, off)) is None
