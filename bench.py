@@ -40,7 +40,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="lsd", choices=["lsd", "small", "segmented", "learned", "blocks"])
+    ap.add_argument("--workload", default="lsd",
+                    choices=["lsd", "small", "segmented", "learned", "blocks", "crossover"])
     ap.add_argument("--log2n", type=int, default=None, help="lsd, learned: 28; blocks: 27")
     ap.add_argument("--radix-bits", type=int, default=8)
     ap.add_argument("--key-bytes", type=int, default=4, choices=[4, 8])
@@ -59,6 +60,12 @@ def parse():
                     help="blocks: also time OET and one workgroup's radix sort of the whole array and "
                          "report the MBSP model's g, G and predictions (Section 3, Eqs. TsG, ToG, TbG)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--tune", type=int, default=0,
+                    help="run the autotuner with this many instances first (0: no)")
+    ap.add_argument("--tuning-file", default=None, help="load a saved tuning table first")
+    ap.add_argument("--save-tuning", default=None, help="save the tuning table after --tune")
+    ap.add_argument("--cross-lo", type=int, default=10, help="crossover: smallest lg n")
+    ap.add_argument("--cross-hi", type=int, default=22, help="crossover: largest lg n")
     ap.add_argument("--cpu-log2n", type=int, default=28)
     return ap.parse_args()
 
@@ -135,21 +142,28 @@ def timed_steps(step, steps, warmup, rs, torch):
     return (t1 - t0) * 1e3 / steps, rs.rs_profile_read()
 
 
-def copy_ceiling_gbs(torch, nbytes):
-    """Read+write bandwidth of a plain device-to-device copy of nbytes."""
+def copy_ceiling_gbs(torch, nbytes, rs=None):
+    """Read+write bandwidth of a device-to-device copy of nbytes: with rs,
+    the library's own streaming copy kernel (timed by the library's launch
+    events), else torch's copy_."""
     a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
     b = torch.empty_like(a)
-    for _ in range(2):
-        b.copy_(a)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
     reps = 10
-    for _ in range(reps):
-        b.copy_(a)
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / reps
+    if rs is not None:
+        ms, prof = timed_steps(lambda: rs.rs_stream_copy(a, b), reps, 2, rs, torch)
+        launches, tot = prof.get("stream_copy", (0, 0.0))
+        ms = tot / launches if launches else ms
+    else:
+        for _ in range(2):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
     del a, b
     return 2 * nbytes / (ms * 1e-3) / 1e9
 
@@ -251,7 +265,8 @@ def bench_lsd(args, torch, rs, gen, np):
     torch.cuda.empty_cache()
     extra = {
         "hbm_gbs": call_bytes / (ms * 1e-3) / 1e9,
-        "copy_ceiling_gbs": copy_ceiling_gbs(torch, 1 << 30),
+        "copy_ceiling_gbs": copy_ceiling_gbs(torch, 1 << 30, rs),
+        "copy_ceiling_torch_gbs": copy_ceiling_gbs(torch, 1 << 30),
     }
     res = line(args, gkeys, ms, "u32" if kb == 4 else "u64",
                "synthetic: SplitMix64 uniform keys on the full range, seed S0+2"
@@ -606,6 +621,72 @@ def mbsp_check(args, torch, rs, keys, n, p, name, ms, stages, prof):
     }
 
 
+# ---- the small-n crossover: one array at a time, networks against radix ----------
+
+def bench_crossover(args, torch, rs, gen, np):
+    """One array of n uint32 keys per call, n = 2^lo .. 2^hi: the block
+    networks (one workgroup up to 16,384 keys at the tuned p, device scale
+    above at the MBSP model's p) and the one-workgroup LDS radix sort against
+    the device-wide LSD sort, each timed alone (launch latency included);
+    the crossover is the smallest n from which LSD is faster than both
+    networks."""
+    rows = []
+    cap = rs.rs_small_capacity(4)
+    table = {e[0]: e for e in rs.rs_tune_get()}
+    for lg in range(args.cross_lo, args.cross_hi + 1):
+        n = 1 << lg
+        keys = torch.empty(n, dtype=torch.int32, device="cuda")
+        gen.uniform_u32_dev(gen.S0 + 3 + lg, keys)
+        out = torch.empty_like(keys)
+        lws = torch.empty(rs.rs_workspace_bytes(rs.RS_OP_SORT, n, 4, 0, 8, rs.RS_ALGO_LSD), dtype=torch.uint8,
+                          device="cuda")
+        row = {"log2n": lg}
+        steps = max(5, args.steps)
+        row["lsd_us"] = timed_steps(lambda: rs.rs_sort_u32(keys, out, radix_bits=8, algo=rs.RS_ALGO_LSD,
+                                                           ws=lws), steps, 2, rs, torch)[0] * 1e3
+        for name, algo in (("btn", rs.RS_ALGO_BTN), ("oet", rs.RS_ALGO_OET)):
+            if n <= cap:
+                p = table[lg][2] if table[lg][1] == algo else 0
+                row[name + "_us"] = timed_steps(lambda: rs.rs_sort_batch_u32(keys, n, 1, out, algo=algo, p=p),
+                                                steps, 2, rs, torch)[0] * 1e3
+                row[name + "_p"] = rs.rs_get_stats().runs_p
+            else:
+                p = rs.rs_blocks_default_p(n, algo)
+                bws = torch.empty(rs.rs_workspace_bytes(rs.RS_OP_BLOCKS, n, 4, 0, 0, algo, p), dtype=torch.uint8,
+                                  device="cuda")
+                row[name + "_us"] = timed_steps(lambda: rs.rs_sort_blocks_u32(keys, out, algo=algo, p=p, ws=bws),
+                                                steps, 2, rs, torch)[0] * 1e3
+                row[name + "_p"] = p
+                del bws
+        if n <= cap:
+            row["lds_radix_us"] = timed_steps(lambda: rs.rs_sort_batch_u32(keys, n, 1, out,
+                                                                           algo=rs.RS_ALGO_LDS_RADIX),
+                                              steps, 2, rs, torch)[0] * 1e3
+        row["lsd_wins"] = row["lsd_us"] < min(row["btn_us"], row["oet_us"])
+        print("crossover n=2^%d: lsd %.1f us  btn %.1f us (p=%d)  oet %.1f us (p=%d)%s" % (
+            lg, row["lsd_us"], row["btn_us"], row["btn_p"], row["oet_us"], row["oet_p"],
+            ("  lds radix %.1f us" % row["lds_radix_us"]) if "lds_radix_us" in row else ""),
+            file=sys.stderr, flush=True)
+        rows.append(row)
+        del keys, out, lws
+        torch.cuda.empty_cache()
+    wins = [r["log2n"] for r in rows if r["lsd_wins"]]
+    first = None
+    for r in rows:                       # the smallest n from which LSD wins at every larger n
+        if all(q["lsd_wins"] for q in rows if q["log2n"] >= r["log2n"]):
+            first = r["log2n"]
+            break
+    last = rows[-1]
+    n = 1 << last["log2n"]
+    best_us = min(last["lsd_us"], last["btn_us"], last["oet_us"])
+    res = line(args, n / (best_us * 1e-6) / 1e9, best_us * 1e-3, "u32",
+               "synthetic: SplitMix64 uniform u32 keys, one array per call, seed S0+3+lg n",
+               {"workload": "small-n crossover: one array of n = 2^%d .. 2^%d uint32 keys per call, BTN / OET "
+                            "against LSD radix" % (args.cross_lo, args.cross_hi), "n": n},
+               None, {}, {"crossover": rows, "lsd_wins_from_log2n": first, "lsd_wins_at": wins})
+    return res
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -622,9 +703,24 @@ def main():
     torch.cuda.set_device(torch.device("cuda:0"))
     if args.log2n is None:
         args.log2n = 27 if args.workload == "blocks" else 28
+    tuning = None
+    if args.tuning_file:
+        rs.rs_tune_load(args.tuning_file)
+        tuning = {"file": args.tuning_file}
+    if args.tune:
+        t0 = time.perf_counter()
+        rs.rs_tune_run(instances=args.tune)
+        tuning = {"instances": args.tune, "seconds": time.perf_counter() - t0}
+        if args.save_tuning:
+            rs.rs_tune_save(args.save_tuning)
+    if tuning is not None:
+        tuning["table"] = [e for e in rs.rs_tune_get() if e[0] >= 1]
     fn = {"lsd": bench_lsd, "small": bench_small, "segmented": bench_segmented,
-          "learned": bench_learned, "blocks": bench_blocks}[args.workload]
-    print(json.dumps(fn(args, torch, rs, gen, np)), flush=True)
+          "learned": bench_learned, "blocks": bench_blocks, "crossover": bench_crossover}[args.workload]
+    res = fn(args, torch, rs, gen, np)
+    if tuning is not None:
+        res["tuning"] = tuning
+    print(json.dumps(res), flush=True)
 
 
 if __name__ == "__main__":

@@ -303,10 +303,14 @@ typedef struct {
  *   - every class k = 15 .. min(24, lg(instances * 16384)): the LSD sort of
  *     one array of 2^k uint32 keys at radix 2^8 with 16- and 28-key tiles
  *     and at radix 2^11; the fastest is installed as the class's radix and
- *     tile;
- *   - every class k = 15 .. min(20, ...): the segmented sort of
- *     instances * 16384 / 2^k segments of 2^k keys with 8- and 16-key-per-
- *     thread tiles; the faster is installed.
+ *     tile if it beats the default (radix 2^8, 16-key tiles below 2^23
+ *     keys, 28 above) by at least 3%, else the default;
+ *   - every class k = 15 .. 20 with at least 512 segments of 2^k keys in
+ *     instances * 16384 keys: the segmented sort of those segments with 8-
+ *     and 16-key-per-thread tiles; 8 is installed if at least 3% faster,
+ *     else 16 (classes with fewer segments keep their entry).
+ * Each candidate is timed twice, interleaved with the others, and keeps its
+ * faster time.
  * Writes at most `max` results to `out` (host) and returns how many, or
  * minus an rs_status.  Synchronises `stream`.  The workspace (device, at
  * least rs_workspace_bytes(RS_OP_TUNE, instances, ...)) holds the inputs. */
@@ -320,6 +324,13 @@ typedef struct {
     int64_t launches;  /* launches recorded since the last read                */
     double total_ms;   /* summed duration between the bracketing HIP events    */
 } rs_kernel_time;
+
+/* Copies `bytes` bytes of device memory from `in` to `out` (not
+ * overlapping) with a plain streaming kernel, 16-byte words when both are
+ * 16-byte aligned: the read + write bandwidth ceiling the sorts are measured
+ * against (timed as "stream_copy").  RS_ERR_INVALID for NULL or
+ * overlapping buffers. */
+rs_status rs_stream_copy(const void* in, void* out, size_t bytes, void* stream);
 
 /* on = 1: from now on every kernel launch of this library is bracketed by a
  * pair of HIP events recorded on the launch's own stream (process-wide).

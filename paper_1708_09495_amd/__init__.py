@@ -18,7 +18,7 @@ RS_ALGO_AUTO, RS_ALGO_LSD, RS_ALGO_BTN, RS_ALGO_OET, RS_ALGO_LEARNED, RS_ALGO_LD
 RS_OP_SORT, RS_OP_SORT_KV, RS_OP_BATCH, RS_OP_SEGMENTED, RS_OP_TUNE, RS_OP_BLOCKS = range(6)
 
 EXPORTS = ["rs_sort_u32", "rs_sort_u64", "rs_sort_kv", "rs_sort_batch_u32", "rs_sort_segmented",
-           "rs_sort_blocks_u32", "rs_sort_u32_noalloc", "rs_blocks_set_model", "rs_blocks_get_model", "rs_blocks_default_p",
+           "rs_sort_blocks_u32", "rs_sort_u32_noalloc", "rs_stream_copy", "rs_blocks_set_model", "rs_blocks_get_model", "rs_blocks_default_p",
            "rs_workspace_bytes", "rs_small_capacity", "rs_status_string", "rs_get_stats",
            "rs_tune_set", "rs_tune_get", "rs_tune_run", "rs_tune_save", "rs_tune_load", "rs_profile_enable", "rs_profile_read",
            "rs_learned_set_opts", "rs_learned_get_opts", "rs_mlp_num_params", "rs_mlp_forward",
@@ -101,6 +101,8 @@ def lib():
         L.rs_sort_blocks_u32.argtypes = [vp, vp, sz, i, i, vp, sz, vp]
         L.rs_sort_u32_noalloc.argtypes = [vp, vp, sz, i, i, vp]
         L.rs_sort_u32_noalloc.restype = i
+        L.rs_stream_copy.argtypes = [vp, vp, sz, vp]
+        L.rs_stream_copy.restype = i
         L.rs_blocks_set_model.argtypes = [ctypes.POINTER(rs_block_model)]
         L.rs_blocks_get_model.argtypes = [ctypes.POINTER(rs_block_model)]
         L.rs_blocks_default_p.argtypes = [sz, i]
@@ -340,6 +342,15 @@ def rs_learned_debug_fault(kind, splitters=None):
     import numpy as np
     a = np.ascontiguousarray(splitters, dtype=np.uint64)
     _call(lib().rs_learned_debug_fault(int(kind), a.ctypes.data, a.size), "rs_learned_debug_fault")
+
+
+def rs_stream_copy(src, dst, stream=None):
+    """Copies device tensor src into dst (same byte size) with the library's
+    streaming copy kernel."""
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nbytes or not src.is_contiguous() or not dst.is_contiguous():
+        raise ValueError("src and dst must be contiguous and of the same byte size")
+    _call(lib().rs_stream_copy(_ptr(src), _ptr(dst), nbytes, _stream(stream)), "rs_stream_copy")
 
 
 def rs_profile_enable(on=True):

@@ -751,7 +751,7 @@ namespace {
 const char* const KNAMES[KID_COUNT_] = {
     "fill", "hist", "onesweep", "copy", "batch", "seg_plan", "seg",
     "learn_sample", "learn_train", "learn_split", "learn_assign", "learn_bucket", "learn_check",
-    "wide_count", "wide_scatter", "learn_pass", "learn_mid", "block_merge"};
+    "wide_count", "wide_scatter", "learn_pass", "learn_mid", "block_merge", "stream_copy"};
 struct Mark {
     int kid;
     hipEvent_t b, e;
@@ -794,6 +794,13 @@ void prof_record(hipStream_t st, int kid, int phase) {
     }
 }
 }  // namespace rs
+
+extern "C" rs_status rs_stream_copy(const void* in, void* out, size_t bytes, void* stream) {
+    if (bytes && (!in || !out)) return RS_ERR_INVALID;
+    if (bytes && in != out && rs::overlaps(in, bytes, out, bytes)) return RS_ERR_INVALID;
+    (void)hipGetLastError();
+    return rs::stream_copy(in, out, bytes, static_cast<hipStream_t>(stream));
+}
 
 extern "C" rs_status rs_profile_enable(int on) {
     rs::g_prof_on = on != 0;

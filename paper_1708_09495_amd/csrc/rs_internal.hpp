@@ -40,6 +40,7 @@ enum KernelId {
     KID_LEARN_PASS,
     KID_LEARN_MID,
     KID_BLOCK_MERGE,
+    KID_STREAM_COPY,
     KID_COUNT_
 };
 extern bool g_prof_on;
@@ -206,6 +207,10 @@ rs_status learned_inject_fault(int kind, const uint64_t* spl, size_t count);
 rs_status mlp_loss_grad(const float* params, const float* x, const float* t, size_t m, float* grad,
                         hipStream_t st);
 constexpr int MLP_NPARAM = 1153;
+
+// Device-to-device copy by a streaming kernel (16-byte words when both
+// pointers are 16-byte aligned).
+rs_status stream_copy(const void* in, void* out, size_t bytes, hipStream_t st);
 
 // Zero-fill of device memory by a kernel (no hipMemsetAsync, so callers may
 // capture the stream into a graph).

@@ -31,6 +31,11 @@ __global__ void k_even_offsets(int64_t* __restrict__ off, uint64_t S, uint64_t L
 
 constexpr int TUNE_LSD_MAX = 24;  // largest class of the single-array LSD timings
 constexpr int TUNE_SEG_MAX = 20;  // largest class of the segment timings
+// A segment class is timed only with enough segments to occupy every
+// workgroup slot of the persistent launch at once (its throughput, not the
+// latency of a few segments, decides the batched workload).
+constexpr uint64_t TUNE_SEG_MIN_COUNT = 512;
+constexpr double TUNE_MARGIN = 0.03;
 
 struct LsdCand {
     int bits, items;
@@ -173,65 +178,76 @@ extern "C" int rs_tune_run(void* ws, size_t ws_bytes, int instances, void* strea
     // tile of a segment sorted by one workgroup's radix rounds.
     const uint64_t N = (uint64_t)instances * SMALL_CAP_U32;
     int64_t* off = reinterpret_cast<int64_t*>(static_cast<unsigned char*>(lws) + tune_inner_bytes(instances));
+    // Each candidate is timed twice, the candidates interleaved, and keeps
+    // its faster time; a candidate replaces the library's default only when
+    // it is at least TUNE_MARGIN faster (timings of one batch vary by a few
+    // per cent from run to run).
     for (int c = 15; c <= cmax; ++c) {
         const uint64_t n = 1ull << c;
-        double best = INFINITY;
-        int bb = 8, bi = 0, bk = -1;
-        for (const LsdCand& cd : LSD_CANDS) {
-            LsdPlan pl;
-            if (!lsd_plan(n, 4, 0, cd.bits, &pl, 0, cd.items)) continue;
-            const double ms = time_ms([&] { lsd_run(pl, in, dst, nullptr, nullptr, lws, st); }, 5);
-            if (k < max) {
+        constexpr int NL = (int)(sizeof(LSD_CANDS) / sizeof(LSD_CANDS[0]));
+        double lt[NL];
+        LsdPlan pl[NL];
+        bool okp[NL];
+        for (int q = 0; q < NL; ++q) {
+            lt[q] = INFINITY;
+            okp[q] = lsd_plan(n, 4, 0, LSD_CANDS[q].bits, &pl[q], 0, LSD_CANDS[q].items);
+        }
+        for (int pass = 0; pass < 2; ++pass)
+            for (int q = 0; q < NL; ++q)
+                if (okp[q]) {
+                    const double ms = time_ms([&] { lsd_run(pl[q], in, dst, nullptr, nullptr, lws, st); }, 5);
+                    lt[q] = ms < lt[q] ? ms : lt[q];
+                }
+        // the default: radix 2^8, 16-key tiles below 2^23 keys, 28 above
+        const int def = n < (1ull << 23) ? 0 : 1;
+        int best = def;
+        for (int q = 0; q < NL; ++q)
+            if (okp[q] && lt[q] < lt[best]) best = q;
+        const int pick = lt[best] < lt[def] * (1.0 - TUNE_MARGIN) ? best : def;
+        for (int q = 0; q < NL; ++q)
+            if (okp[q] && k < max) {
                 out[k] = rs_tune_result{};
                 out[k].size_log2 = c;
                 out[k].algo = RS_ALGO_LSD;
-                out[k].radix_bits = cd.bits;
-                out[k].tile_items = cd.items;
-                out[k].us_per_array = ms * 1e3;
-                out[k].us_single = ms * 1e3;
+                out[k].radix_bits = LSD_CANDS[q].bits;
+                out[k].tile_items = LSD_CANDS[q].items;
+                out[k].chosen = q == pick;
+                out[k].us_per_array = lt[q] * 1e3;
+                out[k].us_single = lt[q] * 1e3;
                 ++k;
             }
-            if (ms < best) {
-                best = ms;
-                bb = cd.bits;
-                bi = cd.items;
-                bk = k - 1;
-            }
-        }
-        if (bk >= 0 && bk < max) out[bk].chosen = 1;
-        table.radix[c] = (int8_t)bb;
-        table.items[c] = (int8_t)bi;
+        table.radix[c] = (int8_t)LSD_CANDS[pick].bits;
+        table.items[c] = (int8_t)LSD_CANDS[pick].items;
         if (c > TUNE_SEG_MAX) continue;
         // S segments of 2^c keys, sorted as one batch with each tile size
         const uint64_t S = N >> c;
         SegPlan sp;
-        if (!seg_plan(S, (int64_t)(S * n), &sp)) continue;
+        if (S < TUNE_SEG_MIN_COUNT || !seg_plan(S, (int64_t)(S * n), &sp)) continue;
         hipLaunchKernelGGL(k_even_offsets, dim3(64), dim3(256), 0, st, off, S, n);
         if (hipGetLastError() != hipSuccess) return -RS_ERR_HIP;
-        best = INFINITY;
-        int bs = 16;
-        bk = -1;
-        for (int it : {8, 16}) {
-            SegTable t2 = table;
-            t2.seg_items[c] = (int8_t)it;
-            const double ms = time_ms([&] { seg_run(sp, in, dst, off, S, (int64_t)(S * n), t2, lws, st); }, 3);
+        constexpr int SEG_CANDS[2] = {16, 8};  // the default first
+        double stt[2] = {INFINITY, INFINITY};
+        for (int pass = 0; pass < 2; ++pass)
+            for (int q = 0; q < 2; ++q) {
+                SegTable t2 = table;
+                t2.seg_items[c] = (int8_t)SEG_CANDS[q];
+                const double ms =
+                    time_ms([&] { seg_run(sp, in, dst, off, S, (int64_t)(S * n), t2, lws, st); }, 3);
+                stt[q] = ms < stt[q] ? ms : stt[q];
+            }
+        const int spick = stt[1] < stt[0] * (1.0 - TUNE_MARGIN) ? 1 : 0;
+        for (int q = 0; q < 2; ++q)
             if (k < max) {
                 out[k] = rs_tune_result{};
                 out[k].size_log2 = c;
                 out[k].algo = RS_ALGO_AUTO;
-                out[k].seg_tile_items = it;
-                out[k].us_per_array = ms * 1e3 / (double)S;
+                out[k].seg_tile_items = SEG_CANDS[q];
+                out[k].chosen = q == spick;
+                out[k].us_per_array = stt[q] * 1e3 / (double)S;
                 out[k].us_single = NAN;
                 ++k;
             }
-            if (ms < best) {
-                best = ms;
-                bs = it;
-                bk = k - 1;
-            }
-        }
-        if (bk >= 0 && bk < max) out[bk].chosen = 1;
-        table.seg_items[c] = (int8_t)bs;
+        table.seg_items[c] = (int8_t)SEG_CANDS[spick];
     }
     if (hipStreamSynchronize(st) != hipSuccess) return -RS_ERR_HIP;
     return k;

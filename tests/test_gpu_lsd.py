@@ -216,3 +216,14 @@ def test_kv_mixed_in_place_refused(rs):
         with pytest.raises(rs.RsError) as e:
             rs.rs_sort_kv(k, v, radix_bits=11, algo=rs.RS_ALGO_LSD, **kw)
         assert e.value.code == rs.RS_ERR_INVALID
+
+
+def test_stream_copy(rs):
+    """The bench's copy kernel copies exactly, aligned or not, any length."""
+    import torch
+    src = torch.randint(0, 255, ((1 << 22) + 77,), dtype=torch.uint8, device="cuda")
+    for off, n in ((0, 1 << 22), (0, (1 << 22) + 77), (3, 100_003), (16, 17), (1, 0)):
+        a = src[off:off + n]
+        b = torch.zeros(n + 5, dtype=torch.uint8, device="cuda")[5:]
+        rs.rs_stream_copy(a, b)
+        assert torch.equal(a, b), (off, n)

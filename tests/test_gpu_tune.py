@@ -43,16 +43,24 @@ def test_large_classes_install_the_fastest(rs, tuned):
     for c in range(15, 23):
         rows = [r for r in res if r["size_log2"] == c and r["algo"] == rs.RS_ALGO_LSD]
         assert {(r["radix_bits"], r["tile_items"]) for r in rows} == {(8, 16), (8, 28), (11, 0)}, c
+        # the fastest replaces the default (radix 2^8, 16-key tiles below 2^23
+        # keys) only when it is at least 3% faster
         best = min(rows, key=lambda r: r["us_per_array"])
-        assert best["chosen"] == 1 and sum(r["chosen"] for r in rows) == 1
-        assert (t[c][3], t[c][4]) == (best["radix_bits"], best["tile_items"])
+        dflt = [r for r in rows if (r["radix_bits"], r["tile_items"]) == (8, 16 if c < 23 else 28)][0]
+        want = best if best["us_per_array"] < 0.97 * dflt["us_per_array"] else dflt
+        assert want["chosen"] == 1 and sum(r["chosen"] for r in rows) == 1
+        assert (t[c][3], t[c][4]) == (want["radix_bits"], want["tile_items"])
         print("class %d: LSD %s" % (c, ", ".join("%d-bit/%d: %.1f us" % (r["radix_bits"], r["tile_items"],
                                                                          r["us_per_array"]) for r in rows)))
-        if c <= 20:
-            seg = [r for r in res if r["size_log2"] == c and r["algo"] == rs.RS_ALGO_AUTO]
+        seg = [r for r in res if r["size_log2"] == c and r["algo"] == rs.RS_ALGO_AUTO]
+        if (256 * 16384) >> c >= 512:        # enough segments to fill the device
             assert {r["seg_tile_items"] for r in seg} == {8, 16}
-            bseg = min(seg, key=lambda r: r["us_per_array"])
-            assert bseg["chosen"] == 1 and t[c][5] == bseg["seg_tile_items"]
+            t8, t16 = ([r for r in seg if r["seg_tile_items"] == it][0] for it in (8, 16))
+            want = t8 if t8["us_per_array"] < 0.97 * t16["us_per_array"] else t16
+            assert want["chosen"] == 1 and sum(r["chosen"] for r in seg) == 1
+            assert t[c][5] == want["seg_tile_items"]
+        else:
+            assert not seg
 
 
 def test_table_round_trips_through_the_file(rs, tuned):
