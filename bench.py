@@ -56,6 +56,8 @@ def parse():
     ap.add_argument("--plain-sample", type=int, default=512,
                     help="segments timed one plain-radix call each (segmented workload)")
     ap.add_argument("--dist", default="zipf", choices=["zipf", "lognormal", "mixture"])
+    ap.add_argument("--mbsp-radix", action="store_true",
+                    help="lsd: the MBSP check of the parallel radix sort (Eqs. TsG, Tp4, Tp2; Observation 7)")
     ap.add_argument("--mbsp", action="store_true",
                     help="blocks: also time OET and one workgroup's radix sort of the whole array and "
                          "report the MBSP model's g, G and predictions (Section 3, Eqs. TsG, ToG, TbG)")
@@ -268,6 +270,8 @@ def bench_lsd(args, torch, rs, gen, np):
         "copy_ceiling_gbs": copy_ceiling_gbs(torch, 1 << 30, rs),
         "copy_ceiling_torch_gbs": copy_ceiling_gbs(torch, 1 << 30),
     }
+    if args.mbsp_radix and kb == 4 and not args.kv:
+        extra["mbsp_radix"] = mbsp_radix_check(args, torch, rs, keys, n, bits, ms)
     res = line(args, gkeys, ms, "u32" if kb == 4 else "u64",
                "synthetic: SplitMix64 uniform keys on the full range, seed S0+2"
                + (", payload = original index (u32)" if args.kv else ""), config, roof, prof, extra)
@@ -619,6 +623,43 @@ def mbsp_check(args, torch, rs, keys, n, p, name, ms, stages, prof):
         "serial_over_btn_measured": (serial_ms / btn_ms) if btn_ms else None,
         "serial_over_btn_model": 68 * p / (68 + 4 * btn_stages * g / G),
     }
+
+
+def mbsp_radix_check(args, torch, rs, keys, n, bits, ms):
+    """The MBSP model of the parallel radix sort (Section 3, Eqs. TsG, Tp,
+    Tp4, Tp2) and Observation 7 on this GPU, with a processor read as a
+    workgroup slot: p = the workgroups the onesweep round holds at once (2 per
+    compute unit).  G is calibrated on the serial sort, T_s = 68 n G (one
+    workgroup's radix-2^8 sort of the whole array), and the paper's g = 5G is
+    kept, as Eqs. Tp4 and Tp2 do; the model then predicts the device-wide
+    sort at radix 2^8 (PR4) and 2^16 (PR2), and Observation 7's bound on the
+    speed-up of PR4 over the serial sort, about 68 p / 88 = 0.77 p."""
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    p = 2 * cus
+    off = torch.tensor([0, n], dtype=torch.int64, device="cuda")
+    out = torch.empty_like(keys)
+    ws = torch.empty(rs.rs_workspace_bytes(rs.RS_OP_SEGMENTED, n, 4, 0, 0, rs.RS_ALGO_AUTO, 1), dtype=torch.uint8,
+                     device="cuda")
+    serial_ms, _ = timed_steps(lambda: rs.rs_sort_segmented(keys, off, out, ws=ws), 1, 1, rs, torch)
+    del ws
+    G = serial_ms * 1e-3 / (68 * n)
+    res = {"p": p, "G_ps": G * 1e12, "serial_one_workgroup_ms": serial_ms}
+    for name, b, coef, cnt in (("pr4", 8, 88, 40 * 256), ("pr2", 16, 44, 20 * 256 * 256)):
+        if b == bits:
+            meas = ms
+        else:
+            ws = torch.empty(rs.rs_workspace_bytes(rs.RS_OP_SORT, n, 4, 0, b, rs.RS_ALGO_LSD), dtype=torch.uint8,
+                             device="cuda")
+            meas, _ = timed_steps(lambda: rs.rs_sort_u32(keys, out, radix_bits=b, algo=rs.RS_ALGO_LSD, ws=ws),
+                                  3, 1, rs, torch)
+            del ws
+        pred = (coef * n / p + cnt * p) * G * 1e3
+        res[name] = {"measured_ms": meas, "predicted_ms": pred, "predicted_count_exchange_ms": cnt * p * G * 1e3,
+                     "speedup_over_serial_measured": serial_ms / meas,
+                     "speedup_over_serial_model": serial_ms / pred}
+    res["obs7_pr4_speedup_bound"] = 68 * p / 88
+    del out
+    return res
 
 
 # ---- the small-n crossover: one array at a time, networks against radix ----------
