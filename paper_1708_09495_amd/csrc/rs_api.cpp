@@ -395,7 +395,10 @@ size_t rs_small_capacity(int key_bytes) {
 }
 
 const char* rs_status_string(rs_status s) {
-    switch (s) {
+    // C callers may pass any int: read it as one rather than as the enum
+    int v;
+    memcpy(&v, &s, sizeof v);
+    switch (v) {
         case RS_OK: return "ok";
         case RS_ERR_INVALID: return "invalid argument";
         case RS_ERR_UNSUPPORTED: return "unsupported request";
