@@ -235,8 +235,8 @@ rs_status rs_sort_u32_noalloc(const uint32_t* in, uint32_t* out, size_t n, int r
  *   radix_bits      the radix of LSD sorts of single uint32 arrays (keys
  *                   only) of the class called with radix_bits = 0 (0: 8);
  *   tile_items      keys per thread of the tiles of uint32 keys-only LSD
- *                   rounds at radix <= 2^8: 16 or 28 (0: by size, 16 below
- *                   2^23 keys);
+ *                   rounds at radix <= 2^8: 8, 16 or 28 (0: by size, 16
+ *                   below 2^23 keys);
  *   seg_tile_items  keys per thread of the tiles that sort a segment of the
  *                   class longer than one workgroup's capacity: 8 or 16
  *                   (0: 16).
@@ -301,8 +301,8 @@ typedef struct {
  *     alone); the fastest is installed; the device-wide LSD sort of one
  *     array is timed beside them (the small-n crossover);
  *   - every class k = 15 .. min(24, lg(instances * 16384)): the LSD sort of
- *     one array of 2^k uint32 keys at radix 2^8 with 16- and 28-key tiles
- *     and at radix 2^11; the fastest is installed as the class's radix and
+ *     one array of 2^k uint32 keys at radix 2^8 with 8-, 16- and 28-key
+ *     tiles and at radix 2^11; the fastest is installed as the class's radix and
  *     tile if it beats the default (radix 2^8, 16-key tiles below 2^23
  *     keys, 28 above) by at least 3%, else the default;
  *   - every class k = 15 .. 20 with at least 512 segments of 2^k keys in

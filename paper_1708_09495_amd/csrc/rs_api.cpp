@@ -543,7 +543,7 @@ bool entry_ok(const rs_tune_entry& e) {
         return false;  // no small-array choice above one workgroup's capacity
     }
     if (e.radix_bits < 0 || e.radix_bits > 16) return false;
-    if (e.tile_items != 0 && e.tile_items != 16 && e.tile_items != 28) return false;
+    if (e.tile_items != 0 && e.tile_items != 8 && e.tile_items != 16 && e.tile_items != 28) return false;
     if (e.seg_tile_items != 0 && e.seg_tile_items != 8 && e.seg_tile_items != 16) return false;
     return true;
 }

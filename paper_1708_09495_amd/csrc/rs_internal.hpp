@@ -81,8 +81,8 @@ constexpr size_t ROUTE_OFFSET = 16;
 constexpr uint64_t LSD_MAX_N = 1ull << 32;
 
 // Plans an LSD sort; returns false when (kb, vb, bits, vb2) is not supported
-// or n >= LSD_MAX_N.  items: keys per thread of the tiles, 0 = by size; 16 or
-// 28 for uint32 keys without values at radix <= 2^8 (other shapes: 0 only).
+// or n >= LSD_MAX_N.  items: keys per thread of the tiles, 0 = by size; 8, 16
+// or 28 for uint32 keys without values at radix <= 2^8 (other shapes: 0 only).
 bool lsd_plan(size_t n, int kb, int vb, int bits, LsdPlan* p, int vb2 = 0, int items = 0);
 
 // Radix bits and tile items of an LSD sort of n keys asked for with

@@ -63,6 +63,7 @@ constexpr int lsd_items(int kb, int vb, int maxb) {
 // once (measured: at 2^20 keys 0.120 ms per sort against 0.142)
 constexpr size_t LSD_SMALL_N = size_t(1) << 23;
 constexpr int LSD_ITEMS_SMALL = 16;
+constexpr int LSD_ITEMS_TINY = 8;  // a tuning choice for small arrays: twice the tiles
 // 16-bit digit keys carry up to two 8-byte payloads (the learned path moves
 // bucket ids with their keys and values)
 
@@ -683,6 +684,8 @@ hipError_t launch_pass_k(const LsdPlan& p, const void* src, void* dst, const voi
     if constexpr (sizeof(K) == 4 && VB == 0) {
         if (p.bits <= 8 && p.tile == NT * LSD_ITEMS_SMALL)
             return launch_pass_lb<K, VB, 8, LSD_ITEMS_SMALL>(p, src, dst, vsrc, vdst, pass, ws, st, route);
+        if (p.bits <= 8 && p.tile == NT * LSD_ITEMS_TINY)
+            return launch_pass_lb<K, VB, 8, LSD_ITEMS_TINY>(p, src, dst, vsrc, vdst, pass, ws, st, route);
     }
     if (p.bits <= 8)
         return launch_pass_lb<K, VB, 8, lsd_items(sizeof(K), VB, 8)>(p, src, dst, vsrc, vdst, pass, ws, st, route);
@@ -768,11 +771,13 @@ bool lsd_plan(size_t n, int kb, int vb, int bits, LsdPlan* p, int vb2, int items
     q.R = 1 << bits;
     q.vb2 = vb2;
     const bool two_tiles = kb == 4 && vb == 0 && bits <= 8;  // the shape with a choice of tile
-    if (items != 0 && !(two_tiles && (items == LSD_ITEMS_SMALL || items == lsd_items(4, 0, 8)))) return false;
+    if (items != 0 && !(two_tiles && (items == LSD_ITEMS_TINY || items == LSD_ITEMS_SMALL ||
+                                      items == lsd_items(4, 0, 8))))
+        return false;
     q.tile = NT * (kb == 2 ? 16
-                           : (two_tiles && (items ? items == LSD_ITEMS_SMALL : n < LSD_SMALL_N))
-                                 ? LSD_ITEMS_SMALL
-                                 : lsd_items(kb, vb, bits <= 8 ? 8 : 11));
+                   : (two_tiles && items)                     ? items
+                   : (two_tiles && n < LSD_SMALL_N)           ? LSD_ITEMS_SMALL
+                                                              : lsd_items(kb, vb, bits <= 8 ? 8 : 11));
     q.tiles = n ? (n + q.tile - 1) / q.tile : 0;
     q.lb64 = n >= (1ull << 30);
     q.lb_words = q.tiles * (size_t)q.R;

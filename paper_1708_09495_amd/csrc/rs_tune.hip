@@ -40,7 +40,7 @@ constexpr double TUNE_MARGIN = 0.03;
 struct LsdCand {
     int bits, items;
 };
-constexpr LsdCand LSD_CANDS[] = {{8, 16}, {8, 28}, {11, 0}};
+constexpr LsdCand LSD_CANDS[] = {{8, 16}, {8, 28}, {11, 0}, {8, 8}};
 
 // Largest class the tuner times with `instances` small arrays of workspace.
 int tune_cmax(int instances) {

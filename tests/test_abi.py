@@ -250,6 +250,7 @@ def test_tuning_table_on_the_host(lib, tmp_path):
         assert lib.rs_tune_get(arr, 64) == 33
         assert tuple(getattr(arr[20], f) for f, _ in E._fields_) == (20, 0, 0, 11, 0, 8)
         for bad in ((33, 0, 0, 8, 0, 0), (20, 2, 4, 8, 0, 0), (20, 0, 0, 17, 0, 0), (20, 0, 0, 8, 20, 0),
+                    (20, 0, 0, 8, 4, 0),
                     (20, 0, 0, 8, 0, 12), (12, 2, 3, 8, 0, 0)):
             assert put(*bad) == 1, bad
         good = ('{"format": "rs-tuning-1", "arch": "gfx950", "cus": 256, "classes": '

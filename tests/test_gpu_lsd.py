@@ -227,3 +227,24 @@ def test_stream_copy(rs):
         b = torch.zeros(n + 5, dtype=torch.uint8, device="cuda")[5:]
         rs.rs_stream_copy(a, b)
         assert torch.equal(a, b), (off, n)
+
+
+@pytest.mark.parametrize("items", [8, 16, 28])
+def test_tile_choices_bit_exact(rs, orc, items):
+    """Every tile the tuning table can pick for uint32 keys at radix 2^8 (8,
+    16 or 28 keys per thread), forced through the table, sorts exactly,
+    every round run and with rounds skipped."""
+    import gen
+    old = rs.rs_tune_get()
+    try:
+        rs.rs_tune_set([(c, 0, 0, 8, items, 0) for c in (13 + 2, 17, 21)])
+        for n in ((1 << 17) - 5, (1 << 21) - 1001):
+            a = gen.uniform_u32(gen.S0 + 90 + items, n)
+            for algo in (rs.RS_ALGO_LSD, rs.RS_ALGO_AUTO):
+                x = a if algo == rs.RS_ALGO_LSD else a & np.uint32(0x00FFFFFF)
+                out = to_host(rs.rs_sort_u32(to_dev(x), radix_bits=0, algo=algo), np.uint32)
+                st = rs.rs_get_stats()
+                assert st.device_error == 0 and st.tile_keys == 512 * items, (n, st.tile_keys)
+                _check(out, orc.lsd(x, 8), "tile %d n=%d algo=%d" % (items, n, algo))
+    finally:
+        rs.rs_tune_set(old)
