@@ -38,6 +38,20 @@ constexpr int HIST_NT = 256;
 constexpr uint32_t HIST_HOT = 8;  // lanes on lane 0's digit worth one aggregated add
 constexpr uint32_t FLAG_AGG = 1, FLAG_PRE = 2;
 constexpr int LBWIN = 4;         // predecessors read per look-back step
+#ifndef LBB_TILES
+#define LBB_TILES 16
+#endif
+#ifndef LBWIN2
+#define LBWIN2 4
+#endif
+constexpr int LBB = LBB_TILES;   // tiles per look-back block
+constexpr int LBWIN_B = LBWIN2;  // blocks read per look-back step
+constexpr int BW_SH = 26;        // block word: tiles counted above bit 26, their digit count below
+static_assert(LBB < (1 << (32 - BW_SH)) && (size_t)LBB * 65536 < (1u << BW_SH),
+              "a block word holds the tile count and the block's digit count");
+#ifndef LB_BLOCKS
+#define LB_BLOCKS 1
+#endif
 constexpr int RANK_GL = 16;      // lanes per ranking group at radix <= 2^8 (16 or 32)
 
 template <typename LB> struct LBW;
@@ -348,6 +362,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MAXB <= 8 ? 
     for (int i = tid; i < (int)(MSKB / 8); i += NT) wmask[i] = 0;
     __syncthreads();
     const uint32_t tile = s_tile;
+    // per look-back block of LBB tiles and digit: the tiles counted so far
+    // (bits 26 up) and the sum of their counts (LBB * 2^16 < 2^26)
+    uint32_t* __restrict__ bwsum = reinterpret_cast<uint32_t*>(lb + (size_t)gridDim.x * R);
     const uint64_t base = (uint64_t)tile * T;
     const uint32_t nvalid = (uint32_t)((n - base) < (uint64_t)T ? (n - base) : (uint64_t)T);
     const bool full = nvalid == (uint32_t)T;
@@ -448,6 +465,11 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MAXB <= 8 ? 
                 tot[d] = t;
                 if (tile != 0)
                     st_agent(&lb[(size_t)tile * R + d], (LB)(((LB)FLAG_AGG << LBW<LB>::SH) | (LB)t));
+#if LB_BLOCKS
+                // this tile's count joins its look-back block's sum, with one
+                // more tile counted in the word's top bits
+                atomicAdd(&bwsum[(size_t)(tile / LBB) * R + d], (1u << BW_SH) | t);
+#endif
             }
             part[q] = t;
             s += t;
@@ -556,6 +578,73 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MAXB <= 8 ? 
             LB excl = 0;
             int64_t j = (int64_t)tile - 1;  // nearest predecessor not yet consumed
             uint32_t spins = 0;
+#if LB_BLOCKS
+            // first the tiles of this tile's own look-back block, one word
+            // each; then whole blocks before it, each read as its last
+            // tile's word (an inclusive prefix ends the walk) and its sum
+            // (used once every tile of the block has counted); block 0 only
+            // by its last tile's prefix, which holds the digit's global base
+            const int64_t bfirst = (int64_t)(tile / LBB) * LBB;
+            const uint32_t nt = gridDim.x;
+            bool done = false;
+            while (!done && j >= bfirst) {
+                LB w[LBWIN];
+#pragma unroll
+                for (int q = 0; q < LBWIN; ++q)
+                    w[q] = (j - q >= bfirst) ? ld_agent(&lb[(size_t)(j - q) * R + d]) : (LB)0;
+                int used = 0;
+#pragma unroll
+                for (int q = 0; q < LBWIN; ++q) {
+                    if (done || used < q || j - q < bfirst) continue;
+                    const uint32_t f = (uint32_t)(w[q] >> LBW<LB>::SH);
+                    if (f == 0) continue;
+                    excl += w[q] & LBW<LB>::MASK;
+                    used = q + 1;
+                    if (f == FLAG_PRE) done = true;
+                }
+                j -= used;
+                if (!done && used == 0) {
+                    if (++spins > SPIN_LIMIT) {
+                        atomicOr(status, STATUS_SPIN);
+                        done = true;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+                }
+            }
+            int64_t b = bfirst / LBB - 1;  // nearest block not yet consumed
+            while (!done && b >= 0) {
+                LB lt[LBWIN_B];
+                uint32_t bs[LBWIN_B];
+#pragma unroll
+                for (int q = 0; q < LBWIN_B; ++q) {
+                    const bool in = b - q >= 0;
+                    lt[q] = in ? ld_agent(&lb[(size_t)((b - q) * LBB + LBB - 1) * R + d]) : (LB)0;
+                    bs[q] = (in && b - q > 0) ? ld_agent(&bwsum[(size_t)(b - q) * R + d]) : 0u;
+                }
+                int used = 0;
+#pragma unroll
+                for (int q = 0; q < LBWIN_B; ++q) {
+                    if (done || used < q || b - q < 0) continue;
+                    if ((uint32_t)(lt[q] >> LBW<LB>::SH) == FLAG_PRE) {
+                        excl += lt[q] & LBW<LB>::MASK;
+                        done = true;
+                        used = q + 1;
+                    } else if (b - q > 0 && (bs[q] >> BW_SH) == (uint32_t)LBB) {
+                        excl += (LB)(bs[q] & ((1u << BW_SH) - 1u));
+                        used = q + 1;
+                    }
+                }
+                b -= used;
+                if (!done && used == 0) {
+                    if (++spins > SPIN_LIMIT) {
+                        atomicOr(status, STATUS_SPIN);
+                        done = true;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+                }
+            }
+            (void)nt;
+#else
             while (true) {
                 LB w[LBWIN];
 #pragma unroll
@@ -583,6 +672,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MAXB <= 8 ? 
                     __builtin_amdgcn_s_sleep(1);
                 }
             }
+#endif
             st_agent(&lb[(size_t)tile * R + d],
                      (LB)(((LB)FLAG_PRE << LBW<LB>::SH) | (LB)(excl + tot[d])));
             goff[d] = (OFF)((int64_t)excl - (int64_t)loc[d]);
@@ -780,7 +870,13 @@ bool lsd_plan(size_t n, int kb, int vb, int bits, LsdPlan* p, int vb2, int items
                                                               : lsd_items(kb, vb, bits <= 8 ? 8 : 11));
     q.tiles = n ? (n + q.tile - 1) / q.tile : 0;
     q.lb64 = n >= (1ull << 30);
-    q.lb_words = q.tiles * (size_t)q.R;
+    // per round: the tiles' look-back words, then one 32-bit block sum per
+    // look-back block of LBB tiles and digit
+    {
+        const size_t wb = q.lb64 ? 8 : 4;
+        const size_t blocks = (q.tiles + LBB - 1) / LBB;
+        q.lb_words = q.tiles * (size_t)q.R + (4 * blocks * (size_t)q.R + wb - 1) / wb;
+    }
     size_t off = 0;
     q.off_status = off;
     off += ALIGN;
