@@ -38,20 +38,11 @@ constexpr int HIST_NT = 256;
 constexpr uint32_t HIST_HOT = 8;  // lanes on lane 0's digit worth one aggregated add
 constexpr uint32_t FLAG_AGG = 1, FLAG_PRE = 2;
 constexpr int LBWIN = 4;         // predecessors read per look-back step
-#ifndef LBB_TILES
-#define LBB_TILES 16
-#endif
-#ifndef LBWIN2
-#define LBWIN2 4
-#endif
-constexpr int LBB = LBB_TILES;   // tiles per look-back block
-constexpr int LBWIN_B = LBWIN2;  // blocks read per look-back step
+constexpr int LBB = 16;          // tiles per look-back block
+constexpr int LBWIN_B = 4;       // blocks read per look-back step
 constexpr int BW_SH = 26;        // block word: tiles counted above bit 26, their digit count below
 static_assert(LBB < (1 << (32 - BW_SH)) && (size_t)LBB * 65536 < (1u << BW_SH),
               "a block word holds the tile count and the block's digit count");
-#ifndef LB_BLOCKS
-#define LB_BLOCKS 1
-#endif
 constexpr int RANK_GL = 16;      // lanes per ranking group at radix <= 2^8 (16 or 32)
 
 template <typename LB> struct LBW;
@@ -249,6 +240,100 @@ __global__ __launch_bounds__(HIST_NT) void k_hist(const K* __restrict__ keys, ui
         if (h[j]) atomicAdd(&ghist[j], h[j]);
     const uint64_t gstride = (uint64_t)gridDim.x * HIST_NT;
     for (uint64_t j = (uint64_t)blockIdx.x * HIST_NT + threadIdx.x; j < zwords; j += gstride) zp[j] = 0u;
+}
+
+// The same histograms for the common shapes, with the digit arithmetic
+// fixed at compile time and the LDS counters laid out by lane: counter word
+// (pass, digit, column), column = lane mod COLS.  At radix 2^8 with 16
+// columns the 32 lanes that one LDS cycle serves fall in at most two words
+// per bank whatever the digits (skewed keys included); the columns are
+// summed once at the end.  One key and pass costs a bit-field extract, one
+// address operation and one LDS add; the LDS adds set the pace.
+constexpr int HC_NT = 1024;
+constexpr uint64_t HC_GRID = 1024;  // workgroups (fewer for small n)
+
+template <typename K, int BITS, int PASSES, int COLS>
+__global__ __launch_bounds__(HC_NT) __attribute__((amdgpu_waves_per_eu(8))) void k_hist_fixed(
+    const K* __restrict__ keys, uint64_t n, uint32_t* __restrict__ ghist, uint32_t* __restrict__ zp,
+    uint64_t zwords) {
+    static_assert(COLS >= 1 && COLS <= 32 && (COLS & (COLS - 1)) == 0, "a power-of-two column count");
+    constexpr int R = 1 << BITS;
+    constexpr int ROWS = PASSES * R;
+    extern __shared__ uint32_t h[];
+    for (int i = threadIdx.x; i < ROWS * COLS; i += HC_NT) h[i] = 0;
+    __syncthreads();
+    const uint32_t col = threadIdx.x & (COLS - 1);
+    auto count = [&](K key) {
+#pragma unroll
+        for (int p = 0; p < PASSES; ++p) {
+            const uint32_t d = (uint32_t)(key >> (p * BITS)) & (uint32_t)(R - 1);
+            atomicAdd(&h[(p * R + d) * COLS + col], 1u);
+        }
+    };
+    // 16-byte loads over the aligned body, four in flight per thread; the
+    // keys before the first 16-byte boundary and after the last whole
+    // vector are counted one per thread by workgroup 0
+    constexpr int VK = 16 / sizeof(K);
+    const uint64_t mis = (reinterpret_cast<uintptr_t>(keys) & 15) / sizeof(K);
+    uint64_t head = mis ? VK - mis : 0;
+    if (head > n) head = n;
+    const uint64_t nv = (n - head) / VK;
+    const uint64_t tail0 = head + nv * VK;
+    const uint4* __restrict__ kv = reinterpret_cast<const uint4*>(keys + head);
+    auto count_vec = [&](const uint4 v) {
+        if constexpr (sizeof(K) == 8) {
+            count((K)(((uint64_t)v.y << 32) | v.x));
+            count((K)(((uint64_t)v.w << 32) | v.z));
+        } else {
+            const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                if constexpr (sizeof(K) == 4) {
+                    count((K)w[j]);
+                } else {
+                    count((K)(w[j] & 0xffffu));
+                    count((K)(w[j] >> 16));
+                }
+            }
+        }
+    };
+    const uint64_t stride = (uint64_t)gridDim.x * HC_NT;
+    uint64_t i = (uint64_t)blockIdx.x * HC_NT + threadIdx.x;
+    for (; i + 3 * stride < nv; i += 4 * stride) {
+        const uint4 v0 = kv[i], v1 = kv[i + stride], v2 = kv[i + 2 * stride], v3 = kv[i + 3 * stride];
+        count_vec(v0); count_vec(v1); count_vec(v2); count_vec(v3);
+    }
+    for (; i < nv; i += stride) count_vec(kv[i]);
+    if (blockIdx.x == 0) {
+        if (threadIdx.x < head) count(keys[threadIdx.x]);
+        if (tail0 + threadIdx.x < n) count(keys[tail0 + threadIdx.x]);
+    }
+    __syncthreads();
+    // sum the columns of each row, each lane starting at its own column so
+    // that a wave's reads spread over the banks
+    for (int r = threadIdx.x; r < ROWS; r += HC_NT) {
+        uint32_t c_sum = 0;
+#pragma unroll
+        for (int c = 0; c < COLS; ++c) c_sum += h[r * COLS + ((c + r) & (COLS - 1))];
+        if (c_sum) atomicAdd(&ghist[r], c_sum);
+    }
+    const uint64_t gstride = (uint64_t)gridDim.x * HC_NT;
+    for (uint64_t j = (uint64_t)blockIdx.x * HC_NT + threadIdx.x; j < zwords; j += gstride) zp[j] = 0u;
+}
+
+// launch k_hist_fixed<K, BITS, PASSES, COLS> over n keys
+template <typename K, int BITS, int PASSES, int COLS>
+void launch_hist_fixed(const void* kin, uint64_t n, uint32_t* gh, uint32_t* zp, uint64_t zwords,
+                       hipStream_t st) {
+    const size_t shm = sizeof(uint32_t) * (size_t)PASSES * (1u << BITS) * COLS;
+    static_assert(sizeof(uint32_t) * (size_t)PASSES * (1u << BITS) * COLS <= 65536, "LDS per workgroup");
+    uint64_t g = (n + HC_NT * 16 - 1) / (HC_NT * 16);
+    if (g > HC_GRID) g = HC_GRID;
+    const uint64_t gz = (zwords + HC_NT * 16 - 1) / (HC_NT * 16);
+    if (g < gz) g = gz;
+    if (g < 1) g = 1;
+    hipLaunchKernelGGL((k_hist_fixed<K, BITS, PASSES, COLS>), dim3((unsigned)g), dim3(HC_NT), shm, st,
+                       static_cast<const K*>(kin), n, gh, zp, zwords);
 }
 
 // One stable count-sort round over tiles of NT*ITEMS keys.
@@ -465,11 +550,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MAXB <= 8 ? 
                 tot[d] = t;
                 if (tile != 0)
                     st_agent(&lb[(size_t)tile * R + d], (LB)(((LB)FLAG_AGG << LBW<LB>::SH) | (LB)t));
-#if LB_BLOCKS
                 // this tile's count joins its look-back block's sum, with one
                 // more tile counted in the word's top bits
                 atomicAdd(&bwsum[(size_t)(tile / LBB) * R + d], (1u << BW_SH) | t);
-#endif
             }
             part[q] = t;
             s += t;
@@ -578,14 +661,12 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MAXB <= 8 ? 
             LB excl = 0;
             int64_t j = (int64_t)tile - 1;  // nearest predecessor not yet consumed
             uint32_t spins = 0;
-#if LB_BLOCKS
             // first the tiles of this tile's own look-back block, one word
             // each; then whole blocks before it, each read as its last
             // tile's word (an inclusive prefix ends the walk) and its sum
             // (used once every tile of the block has counted); block 0 only
             // by its last tile's prefix, which holds the digit's global base
             const int64_t bfirst = (int64_t)(tile / LBB) * LBB;
-            const uint32_t nt = gridDim.x;
             bool done = false;
             while (!done && j >= bfirst) {
                 LB w[LBWIN];
@@ -643,36 +724,6 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MAXB <= 8 ? 
                     __builtin_amdgcn_s_sleep(1);
                 }
             }
-            (void)nt;
-#else
-            while (true) {
-                LB w[LBWIN];
-#pragma unroll
-                for (int q = 0; q < LBWIN; ++q)
-                    w[q] = (j - q >= 0) ? ld_agent(&lb[(size_t)(j - q) * R + d])
-                                        : (LB)((LB)FLAG_PRE << LBW<LB>::SH);
-                bool done = false;
-                int used = 0;
-#pragma unroll
-                for (int q = 0; q < LBWIN; ++q) {
-                    if (done || used < q) continue;
-                    const uint32_t f = (uint32_t)(w[q] >> LBW<LB>::SH);
-                    if (f == 0) continue;  // not published yet: stop consuming here
-                    excl += w[q] & LBW<LB>::MASK;
-                    used = q + 1;
-                    if (f == FLAG_PRE) done = true;
-                }
-                if (done) break;
-                j -= used;
-                if (used == 0) {
-                    if (++spins > SPIN_LIMIT) {
-                        atomicOr(status, STATUS_SPIN);
-                        break;
-                    }
-                    __builtin_amdgcn_s_sleep(1);
-                }
-            }
-#endif
             st_agent(&lb[(size_t)tile * R + d],
                      (LB)(((LB)FLAG_PRE << LBW<LB>::SH) | (LB)(excl + tot[d])));
             goff[d] = (OFF)((int64_t)excl - (int64_t)loc[d]);
@@ -916,7 +967,13 @@ rs_status lsd_run(const LsdPlan& p, const void* kin, void* kout, const void* vin
         uint32_t* gh = reinterpret_cast<uint32_t*>(ws + p.off_hist);
         uint32_t* zp = reinterpret_cast<uint32_t*>(ws + p.off_lb);
         prof(st, p.kid_hist, 0);
-        if (p.kb == 2)
+        if (p.bits == 8 && p.kb == 4 && p.passes == 4) {
+            launch_hist_fixed<uint32_t, 8, 4, 16>(kin, p.n, gh, zp, lb_u32, st);
+        } else if (p.bits == 8 && p.kb == 2 && p.passes == 2) {
+            launch_hist_fixed<uint16_t, 8, 2, 16>(kin, p.n, gh, zp, lb_u32, st);
+        } else if (p.bits == 8 && p.kb == 8 && p.passes == 8) {
+            launch_hist_fixed<uint64_t, 8, 8, 8>(kin, p.n, gh, zp, lb_u32, st);
+        } else if (p.kb == 2)
             hipLaunchKernelGGL(k_hist<uint16_t>, dim3((unsigned)g), dim3(HIST_NT), shm, st,
                                (const uint16_t*)kin, (uint64_t)p.n, p.bits, p.passes, gh, zp,
                                (uint64_t)lb_u32);

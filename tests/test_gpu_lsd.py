@@ -62,16 +62,21 @@ def test_u32_structured(rs, orc, case, bits):
 
 @pytest.mark.parametrize("bits", [8, 11, 4])
 def test_skewed_histograms(rs, orc, bits):
-    """Digits shared by many lanes of a wave, which the histogram counts
-    with one add per wave: Zipf keys (the high bytes mostly zero, the low
-    ones crowded) and keys 90% equal to one value; every round run (LSD)
-    and with the identity rounds skipped (AUTO)."""
+    """Digits shared by many lanes of a wave (radix 2^8: several lanes on
+    one LDS counter column; other radices: one add per wave for the lanes
+    on lane 0's digit): Zipf keys (the high bytes mostly zero, the low ones
+    crowded), keys 90% equal to one value and keys all equal; every round
+    run (LSD) and with the identity rounds skipped (AUTO)."""
     import gen
     rng = np.random.default_rng(11)
     n = (1 << 20) + 4099
     z = gen.zipf_u64(gen.S0 + 44, n)
     m = np.where(rng.random(n) < 0.9, 0x12345678, rng.integers(0, 2**32, n)).astype(np.uint32)
     zref, mref = orc.lsd(z, bits), orc.lsd(m, bits)
+    e = np.full(n, 0x9ABCDEF0, dtype=np.uint32)
+    out = to_host(rs.rs_sort_u32(to_dev(e), radix_bits=bits, algo=rs.RS_ALGO_LSD), np.uint32)
+    assert rs.rs_get_stats().device_error == 0
+    _check(out, e, "all equal b=%d" % bits)
     for algo in (rs.RS_ALGO_LSD, rs.RS_ALGO_AUTO):
         print("case skewed bits=%d algo=%d" % (bits, algo), flush=True)
         out = to_host(rs.rs_sort_u64(to_dev(z), radix_bits=bits, algo=algo), np.uint64)
@@ -248,3 +253,20 @@ def test_tile_choices_bit_exact(rs, orc, items):
                 _check(out, orc.lsd(x, 8), "tile %d n=%d algo=%d" % (items, n, algo))
     finally:
         rs.rs_tune_set(old)
+
+
+@pytest.mark.parametrize("kdt,offset", [(np.uint32, 1), (np.uint32, 2), (np.uint32, 3), (np.uint64, 1)])
+def test_unaligned_views(rs, orc, kdt, offset):
+    """Key arrays that start off a 16-byte boundary (a view into a larger
+    tensor): the histogram reads the aligned body with 16-byte loads and
+    the keys before and after it one by one."""
+    import gen
+    for n in [1, 3, 5, 4099, (1 << 20) + 7]:
+        print("case unaligned %s offset=%d n=%d" % (np.dtype(kdt).name, offset, n), flush=True)
+        a = (gen.uniform_u32 if kdt == np.uint32 else gen.uniform_u64)(gen.S0 + 70 + n, n + offset)
+        base = to_dev(a)
+        view = base[offset:]
+        sort = rs.rs_sort_u32 if kdt == np.uint32 else rs.rs_sort_u64
+        out = to_host(sort(view, radix_bits=8, algo=rs.RS_ALGO_LSD), kdt)
+        assert rs.rs_get_stats().device_error == 0
+        _check(out, orc.lsd(a[offset:], 8), "unaligned offset=%d n=%d" % (offset, n))
