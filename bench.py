@@ -126,22 +126,33 @@ def time_oracle(fn, runs=4):
     return sum(times) / len(times)
 
 
-def timed_steps(step, steps, warmup, rs, torch):
-    """Warm-up, then exactly `steps` steps between device synchronisations,
-    with the library's launch timing on.  Returns (ms per step, profile)."""
+def timed_steps(step, steps, warmup, rs, torch, launch_timing=False):
+    """Warm-up, then exactly `steps` steps between device synchronisations
+    (ms per step, with nothing recorded between the launches), then, when
+    launch_timing is set, the same number of steps again with the library's
+    launch events on, for the per-kernel averages (each event pair adds a
+    few microseconds between launches, so they stay out of ms per step).
+    Returns (ms per step, profile)."""
     for _ in range(warmup):
         step()
     torch.cuda.synchronize()
-    rs.rs_profile_read()          # drop anything recorded before the timed region
-    rs.rs_profile_enable(True)
+    rs.rs_profile_enable(False)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
         step()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    rs.rs_profile_enable(False)
-    return (t1 - t0) * 1e3 / steps, rs.rs_profile_read()
+    prof = {}
+    if launch_timing:
+        rs.rs_profile_read()          # drop anything recorded before
+        rs.rs_profile_enable(True)
+        for _ in range(steps):
+            step()
+        torch.cuda.synchronize()
+        rs.rs_profile_enable(False)
+        prof = rs.rs_profile_read()
+    return (t1 - t0) * 1e3 / steps, prof
 
 
 def copy_ceiling_gbs(torch, nbytes, rs=None):
@@ -152,7 +163,7 @@ def copy_ceiling_gbs(torch, nbytes, rs=None):
     b = torch.empty_like(a)
     reps = 10
     if rs is not None:
-        ms, prof = timed_steps(lambda: rs.rs_stream_copy(a, b), reps, 2, rs, torch)
+        ms, prof = timed_steps(lambda: rs.rs_stream_copy(a, b), reps, 2, rs, torch, launch_timing=True)
         launches, tot = prof.get("stream_copy", (0, 0.0))
         ms = tot / launches if launches else ms
     else:
@@ -202,6 +213,9 @@ def line(args, value, ms_per_step, dtype, data, config, roofline, prof, extra=No
         "config": config,
         "roofline": roofline,
         "kernels": kernels_of(prof),
+        "timing": "ms_per_step over the timed steps with no launch events; kernel averages "
+                  "(roofline.achieved, kernels) from the same number of steps run again with "
+                  "the library's launch events on",
     }
     if extra:
         res.update(extra)
@@ -244,7 +258,7 @@ def bench_lsd(args, torch, rs, gen, np):
     st = rs.rs_get_stats()
     assert st.device_error == 0, "device reported a bounded-wait or range error"
     passes = st.passes
-    ms, prof = timed_steps(step, args.steps, args.warmup, rs, torch)
+    ms, prof = timed_steps(step, args.steps, args.warmup, rs, torch, launch_timing=True)
     gkeys = n / (ms * 1e-3) / 1e9
     wide = bits >= 12
     # whole-call algorithmic bytes: one histogram read (wide digits: a
@@ -324,7 +338,7 @@ def bench_small(args, torch, rs, gen, np):
     step()
     torch.cuda.synchronize()
     st = rs.rs_get_stats()
-    ms, prof = timed_steps(step, args.steps, args.warmup, rs, torch)
+    ms, prof = timed_steps(step, args.steps, args.warmup, rs, torch, launch_timing=True)
     used = {rs.RS_ALGO_BTN: "btn", rs.RS_ALGO_OET: "oet", rs.RS_ALGO_LDS_RADIX: "lds_radix"}[st.algo]
     p = st.runs_p
     # one instance alone, and the device-wide LSD sort of one instance
@@ -400,7 +414,7 @@ def bench_segmented(args, torch, rs, gen, np):
     step()
     torch.cuda.synchronize()
     assert rs.rs_get_stats().device_error == 0
-    ms, prof = timed_steps(step, args.steps, args.warmup, rs, torch)
+    ms, prof = timed_steps(step, args.steps, args.warmup, rs, torch, launch_timing=True)
     # algorithmic bytes: a segment held in LDS is read and written once; a
     # larger one takes four radix-2^8 rounds through HBM
     small = lens <= 16384
@@ -471,7 +485,7 @@ def bench_learned(args, torch, rs, gen, np):
     torch.cuda.synchronize()
     st = rs.rs_get_stats()
     assert st.device_error == 0
-    ms, prof = timed_steps(step, args.steps, args.warmup, rs, torch)
+    ms, prof = timed_steps(step, args.steps, args.warmup, rs, torch, launch_timing=True)
 
     def plain():
         rs.rs_sort_kv(keys, vals, ko, vo, radix_bits=8, algo=rs.RS_ALGO_LSD, ws=ws)
@@ -536,7 +550,7 @@ def bench_blocks(args, torch, rs, gen, np):
     st = rs.rs_get_stats()
     assert st.device_error == 0, "device reported a bounded-wait or range error"
     stages = st.network_stages
-    ms, prof = timed_steps(step, args.steps, args.warmup, rs, torch)
+    ms, prof = timed_steps(step, args.steps, args.warmup, rs, torch, launch_timing=True)
     # one merge-split stage reads and writes every key of the p runs once
     N = -(-n // p)
     roof = hbm_roofline(prof, "block_merge", 2 * 4 * p * N)
@@ -703,7 +717,9 @@ def bench_crossover(args, torch, rs, gen, np):
             row["lds_radix_us"] = timed_steps(lambda: rs.rs_sort_batch_u32(keys, n, 1, out,
                                                                            algo=rs.RS_ALGO_LDS_RADIX),
                                               steps, 2, rs, torch)[0] * 1e3
-        row["lsd_wins"] = row["lsd_us"] < min(row["btn_us"], row["oet_us"])
+        # the device-wide LSD sort against the best one-array alternative
+        # (the networks, and the one-workgroup LDS radix sort where it fits)
+        row["lsd_wins"] = row["lsd_us"] < min(row["btn_us"], row["oet_us"], row.get("lds_radix_us", float("inf")))
         print("crossover n=2^%d: lsd %.1f us  btn %.1f us (p=%d)  oet %.1f us (p=%d)%s" % (
             lg, row["lsd_us"], row["btn_us"], row["btn_p"], row["oet_us"], row["oet_p"],
             ("  lds radix %.1f us" % row["lds_radix_us"]) if "lds_radix_us" in row else ""),
