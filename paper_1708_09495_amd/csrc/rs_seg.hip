@@ -103,28 +103,44 @@ __device__ void seg_large(const uint32_t* __restrict__ in, uint32_t* __restrict_
     uint32_t* wsum = tot + SG_R;                                      // NW+1
     const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
 
-    for (int i = tid; i < SG_NW * SG_R; i += SG_NT) {
-        wmask[i] = 0;
-        wcnt[i] = 0;
-    }
-    for (int i = tid; i < SG_P * SG_R; i += SG_NT) hist[i] = 0;
-    __syncthreads();
     // one read counts the digits of all four rounds (four loads in flight)
+    // into counters laid out by lane (word = round, digit, lane mod HC; the
+    // ranking buffers, not in use yet, hold them), so that lanes on one
+    // digit do not pile onto one LDS bank; the columns are summed after
+    constexpr int HC = 8;
+    static_assert((size_t)SG_P * SG_R * HC * 4 <= 53248, "the column counters fit below the histograms");
+    uint32_t* hc = reinterpret_cast<uint32_t*>(smem);
+    const uint32_t col = tid & (HC - 1);
+    for (int i = tid; i < SG_P * SG_R * HC; i += SG_NT) hc[i] = 0;
+    __syncthreads();
     uint64_t q = tid;
     for (; q + 3 * SG_NT < L; q += 4 * SG_NT) {
         const uint32_t k0 = in[q], k1 = in[q + SG_NT], k2 = in[q + 2 * SG_NT], k3 = in[q + 3 * SG_NT];
 #pragma unroll
         for (int p = 0; p < SG_P; ++p) {
-            atomicAdd(&hist[p * SG_R + ((k0 >> (8 * p)) & 255u)], 1u);
-            atomicAdd(&hist[p * SG_R + ((k1 >> (8 * p)) & 255u)], 1u);
-            atomicAdd(&hist[p * SG_R + ((k2 >> (8 * p)) & 255u)], 1u);
-            atomicAdd(&hist[p * SG_R + ((k3 >> (8 * p)) & 255u)], 1u);
+            atomicAdd(&hc[(p * SG_R + __builtin_amdgcn_ubfe(k0, 8 * p, 8)) * HC + col], 1u);
+            atomicAdd(&hc[(p * SG_R + __builtin_amdgcn_ubfe(k1, 8 * p, 8)) * HC + col], 1u);
+            atomicAdd(&hc[(p * SG_R + __builtin_amdgcn_ubfe(k2, 8 * p, 8)) * HC + col], 1u);
+            atomicAdd(&hc[(p * SG_R + __builtin_amdgcn_ubfe(k3, 8 * p, 8)) * HC + col], 1u);
         }
     }
     for (; q < L; q += SG_NT) {
         const uint32_t k = in[q];
 #pragma unroll
-        for (int p = 0; p < SG_P; ++p) atomicAdd(&hist[p * SG_R + ((k >> (8 * p)) & 255u)], 1u);
+        for (int p = 0; p < SG_P; ++p)
+            atomicAdd(&hc[(p * SG_R + __builtin_amdgcn_ubfe(k, 8 * p, 8)) * HC + col], 1u);
+    }
+    __syncthreads();
+    for (int r = tid; r < SG_P * SG_R; r += SG_NT) {
+        uint32_t c_sum = 0;
+#pragma unroll
+        for (int c = 0; c < HC; ++c) c_sum += hc[r * HC + ((c + r) & (HC - 1))];
+        hist[r] = c_sum;
+    }
+    __syncthreads();
+    for (int i = tid; i < SG_NW * SG_R; i += SG_NT) {
+        wmask[i] = 0;
+        wcnt[i] = 0;
     }
     const uint64_t mybit = 1ull << lane;
     const uint32_t* src = in;
