@@ -95,6 +95,17 @@ enum {
 };
 rs_status rs_learned_debug_fault(int kind, const uint64_t* splitters, size_t count);
 
+/* Test hook for the following LEARNED sorts in this process (not
+ * thread-safe against concurrent sorts): each sort of n keys also writes,
+ * for every input key i, its bucket from evaluating the feature, the
+ * network and the calibration directly to direct[i], and its bucket from
+ * the splitter search (the ids the two stable rounds sort by) to
+ * assigned[i].  The splitters are the smallest keys reaching each bucket,
+ * so the two agree wherever the bucket map is non-decreasing in the key.
+ * Both are DEVICE arrays of at least n uint16 that the caller owns; NULL
+ * for both turns the hook off, one NULL alone is RS_ERR_INVALID. */
+rs_status rs_learned_debug_ids(uint16_t* direct, uint16_t* assigned);
+
 #ifdef __cplusplus
 }
 #endif

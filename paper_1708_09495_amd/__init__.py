@@ -22,7 +22,8 @@ EXPORTS = ["rs_sort_u32", "rs_sort_u64", "rs_sort_kv", "rs_sort_batch_u32", "rs_
            "rs_workspace_bytes", "rs_small_capacity", "rs_status_string", "rs_get_stats",
            "rs_tune_set", "rs_tune_get", "rs_tune_run", "rs_tune_save", "rs_tune_load", "rs_profile_enable", "rs_profile_read",
            "rs_learned_set_opts", "rs_learned_get_opts", "rs_mlp_num_params", "rs_mlp_forward",
-           "rs_mlp_loss_grad", "rs_mlp_adam_step", "rs_mlp_set_weights", "rs_learned_debug_fault"]
+           "rs_mlp_loss_grad", "rs_mlp_adam_step", "rs_mlp_set_weights", "rs_learned_debug_fault",
+           "rs_learned_debug_ids"]
 
 
 class RsError(RuntimeError):
@@ -141,6 +142,8 @@ def lib():
         L.rs_mlp_set_weights.restype = i
         L.rs_learned_debug_fault.argtypes = [i, vp, sz]
         L.rs_learned_debug_fault.restype = i
+        L.rs_learned_debug_ids.argtypes = [vp, vp]
+        L.rs_learned_debug_ids.restype = i
         L.rs_profile_enable.argtypes = [i]
         L.rs_profile_read.argtypes = [ctypes.POINTER(rs_kernel_time), i]
         L.rs_profile_read.restype = i
@@ -342,6 +345,19 @@ def rs_learned_debug_fault(kind, splitters=None):
     import numpy as np
     a = np.ascontiguousarray(splitters, dtype=np.uint64)
     _call(lib().rs_learned_debug_fault(int(kind), a.ctypes.data, a.size), "rs_learned_debug_fault")
+
+
+def rs_learned_debug_ids(direct=None, assigned=None):
+    """Has the following learned sorts write every key's bucket from the
+    network directly into `direct` and from the splitter search into
+    `assigned` (device int16 tensors of at least n entries); no arguments
+    turn it off."""
+    if direct is None and assigned is None:
+        _call(lib().rs_learned_debug_ids(None, None), "rs_learned_debug_ids")
+        return
+    _check_dev(direct, 2, "direct")
+    _check_dev(assigned, 2, "assigned")
+    _call(lib().rs_learned_debug_ids(_ptr(direct), _ptr(assigned)), "rs_learned_debug_ids")
 
 
 def rs_stream_copy(src, dst, stream=None):

@@ -493,6 +493,10 @@ extern "C" rs_status rs_learned_debug_fault(int kind, const uint64_t* splitters,
     return rs::learned_inject_fault(kind, splitters, count);
 }
 
+extern "C" rs_status rs_learned_debug_ids(uint16_t* direct, uint16_t* assigned) {
+    return rs::learned_debug_ids(direct, assigned);
+}
+
 // ---- tuning table -----------------------------------------------------------
 
 namespace rs {

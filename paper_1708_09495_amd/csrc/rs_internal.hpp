@@ -204,6 +204,7 @@ rs_status mlp_adam_step(float* params, float* m1, float* m2, const float* grad, 
 // (NULL: back to training); a planted fault (RS_LEARNED_FAULT_*).
 rs_status learned_inject_weights(const float* params, size_t count);
 rs_status learned_inject_fault(int kind, const uint64_t* spl, size_t count);
+rs_status learned_debug_ids(uint16_t* direct, uint16_t* assigned);
 rs_status mlp_loss_grad(const float* params, const float* x, const float* t, size_t m, float* grad,
                         hipStream_t st);
 constexpr int MLP_NPARAM = 1153;

@@ -191,12 +191,16 @@ __device__ __forceinline__ float calibrate(float y, const float* knot) {
     return ((float)lo + fminf(fmaxf(f, 0.f), 1.f)) * (1.0f / (float)KNOTS);
 }
 
-__device__ __forceinline__ uint32_t bucket_of(const Mlp& W, const State& s, const float* knot, uint64_t k,
-                                              int use_net) {
-    const float x = feat(k, s);
+// bucket of a key from its feature x: min(NB - 1, floor(NB * calibrated y))
+__device__ __forceinline__ uint32_t bucket_of_x(const Mlp& W, const float* knot, float x, int use_net) {
     const float y = use_net ? mlp_y(W, x) : x;
     const float b = calibrate(y, knot) * (float)NB;
     return b >= (float)(NB - 1) ? NB - 1 : (b <= 0.f ? 0u : (uint32_t)b);
+}
+
+__device__ __forceinline__ uint32_t bucket_of(const Mlp& W, const State& s, const float* knot, uint64_t k,
+                                              int use_net) {
+    return bucket_of_x(W, knot, feat(k, s), use_net);
 }
 
 // ---- 1. sample, setup, targets ----------------------------------------------
@@ -523,16 +527,54 @@ __global__ __launch_bounds__(256) void k_splitters(const float* __restrict__ par
     if (j <= blo) r = 0;
     else if (j > bhi) r = ~0ull;  // no key reaches bucket j
     else {
-        uint64_t lo = S.kmin, hi = S.kmax;  // bucket(lo) < j <= bucket(hi)
+        // bucket(k) = g(feat(k)) with g non-decreasing on floats in [0, 1]:
+        // first the smallest float feature x* with g(x*) >= j, by bisection
+        // over the bit patterns of [0, 1] (ordered like the values, at most
+        // 30 network evaluations), then the smallest key whose feature
+        // reaches x*, by bisection over the keys with the feature alone.
+        // That key is the smallest with bucket(k) >= j, the same splitter a
+        // bisection over the keys with the whole bucket map finds.
+        const float xlo = feat(S.kmin, S), xhi = feat(S.kmax, S);  // g(xlo) < j <= g(xhi)
+        uint32_t blo_f = __float_as_uint(xlo), bhi_f = __float_as_uint(xhi);
+        while (bhi_f - blo_f > 1) {
+            const uint32_t mid = blo_f + (bhi_f - blo_f) / 2;
+            if (bucket_of_x(W, knot, __uint_as_float(mid), use_net) >= j) bhi_f = mid;
+            else blo_f = mid;
+        }
+        const float xs = __uint_as_float(bhi_f);
+        uint64_t lo = S.kmin, hi = S.kmax;  // feat(lo) < x* <= feat(hi)
         while (hi - lo > 1) {
             const uint64_t mid = lo + (hi - lo) / 2;
-            if (bucket_of(W, S, knot, mid, use_net) >= j) hi = mid;
+            if (feat(mid, S) >= xs) hi = mid;
             else lo = mid;
         }
         r = hi;
     }
     spl[j - 1] = r;
     if (j == 1) st->reach = bhi;
+}
+
+// Test hook: every key's bucket from the network directly (feature,
+// network, calibration; the definition the splitters invert).
+__global__ __launch_bounds__(256) void k_direct_ids(const uint64_t* __restrict__ keys, uint64_t n,
+                                                    const float* __restrict__ params,
+                                                    const State* __restrict__ st,
+                                                    const float* __restrict__ knot_g, int use_net,
+                                                    uint16_t* __restrict__ out) {
+    __shared__ Mlp W;
+    __shared__ float raw[NP];
+    __shared__ float knot[KNOTS + 1];
+    __shared__ State S;
+    for (int p = threadIdx.x; p < NP; p += blockDim.x) raw[p] = params[p];
+    for (int g = threadIdx.x; g <= KNOTS; g += blockDim.x) knot[g] = knot_g[g];
+    for (uint32_t i = threadIdx.x; i < sizeof(State) / 8; i += blockDim.x)
+        reinterpret_cast<uint64_t*>(&S)[i] = reinterpret_cast<const uint64_t*>(st)[i];
+    __syncthreads();
+    mlp_derive(raw, W, false);
+    __syncthreads();
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        out[i] = (uint16_t)bucket_of(W, S, knot, keys[i], use_net);
 }
 
 // Prefix maximum over the splitters (one workgroup of 1024 threads): makes
@@ -1380,6 +1422,8 @@ struct Inject {
     int fault = 0;  // RS_LEARNED_FAULT_*
     std::vector<float> params;
     std::vector<uint64_t> spl;
+    uint16_t* direct = nullptr;    // device: each key's bucket from the network directly
+    uint16_t* assigned = nullptr;  // device: each key's bucket from the splitters
 };
 Inject g_inject;
 
@@ -1495,6 +1539,16 @@ rs_status learned_run(const void* kin, void* kout, const void* vin, void* vout, 
                            spl, topg, st, bid0);
         prof(s, KID_LEARN_ASSIGN, 1);
         if ((rc = launch_status()) != RS_OK) return rc;
+    }
+    if (g_inject.direct) {
+        // test hook: both bucket maps of every key, for the caller to compare
+        uint64_t g = (n + 255) / 256;
+        if (g > 4096) g = 4096;
+        hipLaunchKernelGGL(k_direct_ids, dim3((unsigned)g), dim3(256), 0, s, (const uint64_t*)kin, (uint64_t)n,
+                           params, st, knot, opt.use_network, g_inject.direct);
+        if ((rc = launch_status()) != RS_OK) return rc;
+        if ((e = hipMemcpyAsync(g_inject.assigned, bid0, 2 * n, hipMemcpyDeviceToDevice, s)) != hipSuccess)
+            return hip_fail(e);
     }
     // 5. two stable rounds on the bucket id carry keys and values
     if ((rc = lsd_run(L.pass_plan, bid0, bid1, kin, kout, big, s, vb ? vin : nullptr, vb ? vout : nullptr)) !=
@@ -1634,6 +1688,13 @@ rs_status learned_inject_weights(const float* params, size_t count) {
     if (count != (size_t)NP) return RS_ERR_INVALID;
     g_inject.params.assign(params, params + NP);
     g_inject.weights = true;
+    return RS_OK;
+}
+
+rs_status learned_debug_ids(uint16_t* direct, uint16_t* assigned) {
+    if ((direct == nullptr) != (assigned == nullptr)) return RS_ERR_INVALID;
+    g_inject.direct = direct;
+    g_inject.assigned = assigned;
     return RS_OK;
 }
 

@@ -340,3 +340,41 @@ def test_planted_bucket_error_takes_the_check_fallback(rs, orc, kv):
     finally:
         rs.rs_learned_debug_fault(rs.RS_LEARNED_FAULT_NONE)
         rs.rs_learned_set_opts(**old)
+
+
+@pytest.mark.parametrize("dist,opts", [("lognormal", {}), ("zipf", {}), ("mixture", {}), ("uniform", {}),
+                                       ("mixture", dict(use_network=0)), ("lognormal", dict(feature_mode=1)),
+                                       ("mixture", dict(feature_mode=0))])
+def test_splitters_match_direct_bucket_map(rs, dist, opts):
+    """The splitter form of inference against its definition: for every
+    key, the bucket the splitter search assigns equals the bucket from
+    evaluating the feature, the network and the calibration on the key
+    itself (splitter j is the smallest key reaching bucket j, found by
+    inverting the map in feature space, then in key space).  Along the
+    sorted keys the direct map is non-decreasing (monotone network)."""
+    import gen
+    import torch
+    old = rs.rs_learned_set_opts(**opts) if opts else None
+    try:
+        n = (1 << 20) + 17
+        print("case splitters %s %s" % (dist, opts), flush=True)
+        keys = _dist(dist, n, gen.S0 + 9)
+        direct = torch.full((n,), -1, dtype=torch.int16, device="cuda")
+        assigned = torch.full((n,), -1, dtype=torch.int16, device="cuda")
+        rs.rs_learned_debug_ids(direct, assigned)
+        try:
+            ko, _, st = _learned(rs, keys)
+        finally:
+            rs.rs_learned_debug_ids()
+        assert st.fallback == 0 and st.device_error == 0
+        d = to_host(direct, np.uint16).astype(np.int64)
+        a = to_host(assigned, np.uint16).astype(np.int64)
+        bad = np.nonzero(d != a)[0]
+        assert bad.size == 0, "%d keys differ, first key %d: direct %d, splitters %d" % (
+            bad.size, keys[bad[0]], d[bad[0]], a[bad[0]])
+        order = np.argsort(keys, kind="stable")
+        assert np.all(np.diff(d[order]) >= 0)
+        assert first_mismatch(ko, np.sort(keys)) is None
+    finally:
+        if old is not None:
+            rs.rs_learned_set_opts(**old)
