@@ -293,6 +293,10 @@ typedef struct {
     double us_per_array;    /* per array (segment), `instances` in one launch;  */
                             /* LSD: one array per call                           */
     double us_single;       /* one array alone: launch latency included          */
+    double us_model;        /* rs_tune_run_model: the cost model's prediction   */
+                            /* per array (NaN where not modelled; 0 from        */
+                            /* rs_tune_run); us_per_array is NaN for a          */
+                            /* candidate it predicted but did not time          */
 } rs_tune_result;
 
 /* Autotuner, on the current device:
@@ -316,6 +320,23 @@ typedef struct {
  * least rs_workspace_bytes(RS_OP_TUNE, instances, ...)) holds the inputs. */
 int rs_tune_run(void* ws, size_t ws_bytes, int instances, void* stream, rs_tune_result* out,
                 int max);
+
+/* The same tuning with the small classes (k = 1..14) guided by a cost model
+ * of the form of the paper's T_b and T_o (Section 3; Section 4, Eqs. for
+ * BTN and OET with p processors): per array,
+ *   t(p) = c0 npad lg N (lg N + 1) / 4 + c1 S npad (lg N + 1) + c2 S p + c3,
+ * N = npad / p keys per processor, S = lg p (lg p + 1) / 2 merge-split
+ * stages for BTN and p rounds for OET.  The three constants are fitted per
+ * network (c3: a share of the launch), by least squares on relative error,
+ * to timings of the smallest,
+ * middle and largest valid p in classes 4, 7, 10 and 13; then each class
+ * times only the p the model predicts fastest and its two neighbours for
+ * each network, and the LDS radix sort, and installs the fastest timed.
+ * Candidates predicted but not timed are reported with us_per_array = NaN
+ * and their prediction in us_model.  The larger classes are tuned as by
+ * rs_tune_run.  Same arguments, workspace and return value. */
+int rs_tune_run_model(void* ws, size_t ws_bytes, int instances, void* stream, rs_tune_result* out,
+                      int max);
 
 /* ---- kernel timing (benchmarks) ---------------------------------------- */
 

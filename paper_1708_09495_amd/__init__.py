@@ -20,7 +20,7 @@ RS_OP_SORT, RS_OP_SORT_KV, RS_OP_BATCH, RS_OP_SEGMENTED, RS_OP_TUNE, RS_OP_BLOCK
 EXPORTS = ["rs_sort_u32", "rs_sort_u64", "rs_sort_kv", "rs_sort_batch_u32", "rs_sort_segmented",
            "rs_sort_blocks_u32", "rs_sort_u32_noalloc", "rs_stream_copy", "rs_blocks_set_model", "rs_blocks_get_model", "rs_blocks_default_p",
            "rs_workspace_bytes", "rs_small_capacity", "rs_status_string", "rs_get_stats",
-           "rs_tune_set", "rs_tune_get", "rs_tune_run", "rs_tune_save", "rs_tune_load", "rs_profile_enable", "rs_profile_read",
+           "rs_tune_set", "rs_tune_get", "rs_tune_run", "rs_tune_run_model", "rs_tune_save", "rs_tune_load", "rs_profile_enable", "rs_profile_read",
            "rs_learned_set_opts", "rs_learned_get_opts", "rs_mlp_num_params", "rs_mlp_forward",
            "rs_mlp_loss_grad", "rs_mlp_adam_step", "rs_mlp_set_weights", "rs_learned_debug_fault",
            "rs_learned_debug_ids"]
@@ -63,7 +63,8 @@ class rs_tune_result(ctypes.Structure):
     _fields_ = [("size_log2", ctypes.c_int32), ("algo", ctypes.c_int32), ("p", ctypes.c_int32),
                 ("radix_bits", ctypes.c_int32), ("tile_items", ctypes.c_int32),
                 ("seg_tile_items", ctypes.c_int32), ("chosen", ctypes.c_int32),
-                ("us_per_array", ctypes.c_double), ("us_single", ctypes.c_double)]
+                ("us_per_array", ctypes.c_double), ("us_single", ctypes.c_double),
+                ("us_model", ctypes.c_double)]
 
 
 class rs_learned_opts(ctypes.Structure):
@@ -121,6 +122,8 @@ def lib():
         L.rs_tune_get.restype = i
         L.rs_tune_run.argtypes = [vp, sz, i, vp, ctypes.POINTER(rs_tune_result), i]
         L.rs_tune_run.restype = i
+        L.rs_tune_run_model.argtypes = [vp, sz, i, vp, ctypes.POINTER(rs_tune_result), i]
+        L.rs_tune_run_model.restype = i
         L.rs_tune_save.argtypes = [ctypes.c_char_p]
         L.rs_tune_save.restype = i
         L.rs_tune_load.argtypes = [ctypes.c_char_p]
@@ -256,16 +259,18 @@ def rs_tune_get():
     return [tuple(getattr(arr[i], f) for f in TUNE_FIELDS) for i in range(k)]
 
 
-def rs_tune_run(instances=1024, ws=None, stream=None):
-    """Runs the autotuner on the current device; returns a list of dicts
-    (the fields of rs_tune_result)."""
+def rs_tune_run(instances=1024, ws=None, stream=None, model=False):
+    """Runs the autotuner on the current device (model=True: the small
+    classes guided by the fitted cost model, rs_tune_run_model); returns a
+    list of dicts (the fields of rs_tune_result)."""
     torch = _torch()
     need = rs_workspace_bytes(RS_OP_TUNE, instances)
     ws = _workspace(need, ws, torch.device("cuda", torch.cuda.current_device()))
     buf = (rs_tune_result * 1024)()
-    k = lib().rs_tune_run(_ptr(ws), ws.numel(), instances, _stream(stream), buf, 1024)
+    fn = lib().rs_tune_run_model if model else lib().rs_tune_run
+    k = fn(_ptr(ws), ws.numel(), instances, _stream(stream), buf, 1024)
     if k < 0:
-        raise RsError(-k, "rs_tune_run")
+        raise RsError(-k, "rs_tune_run_model" if model else "rs_tune_run")
     return [{f: getattr(buf[i], f) for f, _ in rs_tune_result._fields_} for i in range(k)]
 
 

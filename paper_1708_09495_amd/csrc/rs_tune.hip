@@ -4,6 +4,8 @@
 // the device-wide LSD sort of one array per launch (the radix side of the
 // small-n crossover the paper observes on CPUs, Section 4, Observation 6).
 #include <math.h>
+
+#include <cmath>
 #include <vector>
 
 #include "rs_internal.hpp"
@@ -60,6 +62,75 @@ struct Timer {
     }
 };
 
+// Cost model of one workgroup sorting an array of npad keys with p
+// processors holding runs of N = npad / p keys, in the form of the paper's
+// T_b and T_o (Section 3): a local sort of each run, then S merge-split
+// stages (BTN: lg p (lg p + 1) / 2; OET: p rounds), each a bitonic merge of
+// two runs and an exchange.  With many arrays in one launch the machine is
+// saturated, so an array costs the work of all p processors, plus a share
+// of the launch:
+//   t = c0 * npad lg N (lg N + 1) / 4        compare-exchanges of the local sorts
+//     + c1 * S npad (lg N + 1)               compare-exchanges of the stages
+//     + c2 * S p                             fixed cost of a processor's stage
+//     + c3                                   per array, whatever p.
+constexpr int NF = 4;
+void model_features(int algo, uint32_t npad, int p, double f[NF]) {
+    const double N = (double)npad / p, lgN = log2(N), lgp = log2((double)p);
+    const double S = algo == RS_ALGO_OET ? (double)p : lgp * (lgp + 1.0) / 2.0;
+    f[0] = (double)npad * lgN * (lgN + 1.0) / 4.0;
+    f[1] = S * (double)npad * (lgN + 1.0);
+    f[2] = S * (double)p;
+    f[3] = 1.0;
+}
+
+// Least squares for the NF constants, each row weighted by 1 / t (so the
+// fit minimises relative error).  Returns false for a singular system.
+bool model_fit(const std::vector<double>& F, const std::vector<double>& t, double c[NF]) {
+    double A[NF][NF] = {}, b[NF] = {};
+    for (size_t i = 0; i < t.size(); ++i) {
+        const double* f = &F[NF * i];
+        const double w = 1.0 / (t[i] * t[i]);
+        for (int r = 0; r < NF; ++r) {
+            b[r] += w * f[r] * t[i];
+            for (int q = 0; q < NF; ++q) A[r][q] += w * f[r] * f[q];
+        }
+    }
+    // Gaussian elimination with partial pivoting
+    for (int col = 0; col < NF; ++col) {
+        int piv = col;
+        for (int r = col + 1; r < NF; ++r)
+            if (fabs(A[r][col]) > fabs(A[piv][col])) piv = r;
+        if (fabs(A[piv][col]) < 1e-300) return false;
+        for (int q = 0; q < NF; ++q) {
+            const double tmp = A[col][q];
+            A[col][q] = A[piv][q];
+            A[piv][q] = tmp;
+        }
+        const double tb = b[col];
+        b[col] = b[piv];
+        b[piv] = tb;
+        for (int r = col + 1; r < NF; ++r) {
+            const double m = A[r][col] / A[col][col];
+            for (int q = col; q < NF; ++q) A[r][q] -= m * A[col][q];
+            b[r] -= m * b[col];
+        }
+    }
+    for (int r = NF - 1; r >= 0; --r) {
+        double v = b[r];
+        for (int q = r + 1; q < NF; ++q) v -= A[r][q] * c[q];
+        c[r] = v / A[r][r];
+    }
+    return true;
+}
+
+double model_us(int algo, uint32_t npad, int p, const double c[NF]) {
+    double f[NF];
+    model_features(algo, npad, p, f);
+    double t = 0;
+    for (int q = 0; q < NF; ++q) t += c[q] * f[q];
+    return t;
+}
+
 }  // namespace
 
 // Workspace of the tuner: the input and output arrays of instances * 16384
@@ -90,8 +161,9 @@ size_t tune_ws_bytes(int instances) {
 
 using namespace rs;
 
-extern "C" int rs_tune_run(void* ws, size_t ws_bytes, int instances, void* stream,
-                           rs_tune_result* out, int max) {
+namespace {
+int tune_impl(void* ws, size_t ws_bytes, int instances, void* stream, rs_tune_result* out, int max,
+              bool model) {
     if (instances < 1 || instances > 65536 || !out || max < 1) return -RS_ERR_INVALID;
     const size_t need = tune_ws_bytes(instances);
     if (!ws || ws_bytes < need || (reinterpret_cast<uintptr_t>(ws) % ALIGN)) return -RS_ERR_WORKSPACE;
@@ -118,7 +190,118 @@ extern "C" int rs_tune_run(void* ws, size_t ws_bytes, int instances, void* strea
         if (hipEventElapsedTime(&ms, tm.a, tm.b) != hipSuccess) return (double)NAN;
         return (double)ms / reps;
     };
-    for (int c = 1; c <= 14; ++c) {
+    // Model-guided: the constants of the cost model above are fitted, per
+    // algorithm, to timings of three p (smallest, middle, largest valid) in
+    // four classes; then every class times only the p the model predicts
+    // fastest and its two neighbours (and the LDS radix sort).
+    double coef[2][NF] = {};
+    bool fitted[2] = {false, false};
+    std::vector<double> cal_ms[2][15];  // [algo][class] timings by p index, NaN if not timed
+    if (model) {
+        constexpr int CAL[4] = {4, 7, 10, 13};
+        for (int ai = 0; ai < 2; ++ai) {
+            const int algo = ai ? RS_ALGO_OET : RS_ALGO_BTN;
+            std::vector<double> F, T;
+            for (int c : CAL) {
+                const uint32_t n = 1u << c;
+                std::vector<int> ps;
+                for (int p = 1; p <= 1024; p <<= 1)
+                    if (small_valid_p(n, p)) ps.push_back(p);
+                cal_ms[ai][c].assign(ps.size(), (double)NAN);
+                const size_t pick[3] = {0, ps.size() / 2, ps.size() - 1};
+                for (size_t i : pick) {
+                    if (!std::isnan(cal_ms[ai][c][i])) continue;
+                    const double ms =
+                        time_ms([&] { small_run(algo, in, dst, n, (size_t)instances, ps[i], st); }, 3);
+                    cal_ms[ai][c][i] = ms;
+                    double f[NF];
+                    model_features(algo, small_npad(n), ps[i], f);
+                    F.insert(F.end(), f, f + NF);
+                    T.push_back(ms * 1e3 / instances);
+                }
+            }
+            fitted[ai] = model_fit(F, T, coef[ai]);
+        }
+    }
+    for (int c = 1; c <= 14 && model; ++c) {
+        const uint32_t n = 1u << c, npad = small_npad(n);
+        double best = INFINITY;
+        int best_algo = RS_ALGO_BTN, best_p = small_default_p(RS_ALGO_BTN, n);
+        const int first = k;
+        auto record = [&](int algo, int p, double ms, double single, double pred) {
+            if (k < max) {
+                out[k] = rs_tune_result{};
+                out[k].size_log2 = c;
+                out[k].algo = algo;
+                out[k].p = p;
+                out[k].us_per_array = ms * 1e3 / instances;
+                out[k].us_single = single * 1e3;
+                out[k].us_model = pred;
+                ++k;
+            }
+            if (ms < best) {
+                best = ms;
+                best_algo = algo;
+                best_p = p;
+            }
+        };
+        {
+            const double ms = time_ms([&] { small_run(RS_ALGO_LDS_RADIX, in, dst, n, (size_t)instances, 0, st); }, 3);
+            const double single = time_ms([&] { small_run(RS_ALGO_LDS_RADIX, in, dst, n, 1, 0, st); }, 5);
+            record(RS_ALGO_LDS_RADIX, 0, ms, single, (double)NAN);
+        }
+        for (int ai = 0; ai < 2; ++ai) {
+            const int algo = ai ? RS_ALGO_OET : RS_ALGO_BTN;
+            std::vector<int> ps;
+            for (int p = 1; p <= 1024; p <<= 1)
+                if (small_valid_p(n, p)) ps.push_back(p);
+            std::vector<double> pred(ps.size());
+            size_t arg = 0;
+            for (size_t i = 0; i < ps.size(); ++i) {
+                pred[i] = fitted[ai] ? model_us(algo, npad, ps[i], coef[ai]) : 0.0;
+                if (pred[i] < pred[arg]) arg = i;
+            }
+            for (size_t i = 0; i < ps.size(); ++i) {
+                const bool timed = i + 1 >= arg && i <= arg + 1;  // the predicted best and its neighbours
+                if (!timed && fitted[ai]) {
+                    if (k < max) {
+                        out[k] = rs_tune_result{};
+                        out[k].size_log2 = c;
+                        out[k].algo = algo;
+                        out[k].p = ps[i];
+                        out[k].us_per_array = (double)NAN;
+                        out[k].us_single = (double)NAN;
+                        out[k].us_model = pred[i];
+                        ++k;
+                    }
+                    continue;
+                }
+                double ms = (c < 15 && i < cal_ms[ai][c].size()) ? cal_ms[ai][c][i] : (double)NAN;
+                if (std::isnan(ms))
+                    ms = time_ms([&] { small_run(algo, in, dst, n, (size_t)instances, ps[i], st); }, 3);
+                const double single = time_ms([&] { small_run(algo, in, dst, n, 1, ps[i], st); }, 5);
+                record(algo, ps[i], ms, single, fitted[ai] ? pred[i] : (double)NAN);
+            }
+        }
+        for (int i = first; i < k; ++i)
+            if (out[i].algo == best_algo && out[i].p == best_p && !std::isnan(out[i].us_per_array)) out[i].chosen = 1;
+        table.algo[c] = (int8_t)best_algo;
+        table.p[c] = (int16_t)(best_algo == RS_ALGO_LDS_RADIX ? 0 : best_p);
+        LsdPlan p1;
+        lsd_plan(n, 4, 0, 8, &p1);
+        const double lsd = time_ms([&] { lsd_run(p1, in, dst, nullptr, nullptr, lws, st); }, 5);
+        if (k < max) {
+            out[k] = rs_tune_result{};
+            out[k].size_log2 = c;
+            out[k].algo = RS_ALGO_LSD;
+            out[k].radix_bits = 8;
+            out[k].us_per_array = lsd * 1e3;
+            out[k].us_single = lsd * 1e3;
+            out[k].us_model = (double)NAN;
+            ++k;
+        }
+    }
+    for (int c = 1; c <= 14 && !model; ++c) {
         const uint32_t n = 1u << c;
         // the instances are packed back to back at stride n
         struct Cand {
@@ -251,4 +434,15 @@ extern "C" int rs_tune_run(void* ws, size_t ws_bytes, int instances, void* strea
     }
     if (hipStreamSynchronize(st) != hipSuccess) return -RS_ERR_HIP;
     return k;
+}
+}  // namespace
+
+extern "C" int rs_tune_run(void* ws, size_t ws_bytes, int instances, void* stream,
+                           rs_tune_result* out, int max) {
+    return tune_impl(ws, ws_bytes, instances, stream, out, max, false);
+}
+
+extern "C" int rs_tune_run_model(void* ws, size_t ws_bytes, int instances, void* stream,
+                                 rs_tune_result* out, int max) {
+    return tune_impl(ws, ws_bytes, instances, stream, out, max, true);
 }

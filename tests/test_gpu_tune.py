@@ -117,3 +117,43 @@ def test_sorts_under_the_tuned_table_match_the_oracle(rs, orc, tuned):
     out = rs.rs_sort_segmented(to_dev(keys), torch.from_numpy(off).cuda())
     assert rs.rs_get_stats().device_error == 0
     assert first_mismatch(to_host(out, np.uint32), orc.segmented(keys, off)) is None
+
+
+def test_model_guided_small_classes(rs):
+    """The small-array classes tuned by the fitted cost model (the form of
+    the paper's T_b / T_o, rs_tune_run_model) against timing every
+    candidate (rs_tune_run): about half the timings, and from 128-key
+    arrays up (where the launch no longer dominates a batch of 1,024) the
+    candidate it installs is, by the exhaustive run's own timing, within
+    15% of the fastest; the model's predictions of the candidates it timed
+    are within 35% of the measurement at the median."""
+    import math
+    old = rs.rs_tune_get()
+    try:
+        ex = rs.rs_tune_run(instances=1024)
+        mo = rs.rs_tune_run(instances=1024, model=True)
+    finally:
+        rs.rs_tune_set(old)
+    nets = (rs.RS_ALGO_BTN, rs.RS_ALGO_OET, rs.RS_ALGO_LDS_RADIX)
+    timed_ex = timed_mo = 0
+    errs = []
+    for c in range(1, 15):
+        e = [r for r in ex if r["size_log2"] == c and r["algo"] in nets]
+        m = [r for r in mo if r["size_log2"] == c and r["algo"] in nets]
+        timed_ex += len(e)
+        timed_mo += sum(1 for r in m if not math.isnan(r["us_per_array"]))
+        assert all(not math.isnan(r["us_model"]) for r in m if r["algo"] != rs.RS_ALGO_LDS_RADIX)
+        errs += [abs(r["us_model"] - r["us_per_array"]) / r["us_per_array"] for r in m
+                 if r["algo"] != rs.RS_ALGO_LDS_RADIX and not math.isnan(r["us_per_array"])]
+        pick = [r for r in m if r["chosen"]]
+        assert len(pick) == 1 and not math.isnan(pick[0]["us_per_array"])
+        best = min(r["us_per_array"] for r in e)
+        same = [r for r in e if r["algo"] == pick[0]["algo"] and r["p"] == pick[0]["p"]][0]
+        print("class %d: model installs %d/p=%d, %.4f us (exhaustive best %.4f)" %
+              (c, pick[0]["algo"], pick[0]["p"], same["us_per_array"], best), flush=True)
+        if c >= 7:
+            assert same["us_per_array"] <= 1.15 * best
+    print("timings: %d model-guided, %d exhaustive; median prediction error %.3f" %
+          (timed_mo, timed_ex, float(np.median(errs))), flush=True)
+    assert timed_mo <= 0.7 * timed_ex
+    assert float(np.median(errs)) <= 0.35
