@@ -498,6 +498,14 @@ def bench_learned(args, torch, rs, gen, np):
     # the same rounds, skipping those whose digit is the same for every key
     skip_ms, _ = timed_steps(plain_skip, max(3, args.steps // 2), 1, rs, torch)
     skipped = rs.rs_get_stats().passes_skipped
+    # the same learned path with the network off (buckets from the feature
+    # and the calibration alone): what the network costs in time
+    old_opts = rs.rs_learned_set_opts(use_network=0)
+    try:
+        nonet_ms, _ = timed_steps(step, max(3, args.steps // 2), 1, rs, torch)
+        st_nonet = rs.rs_get_stats()
+    finally:
+        rs.rs_learned_set_opts(**old_opts)
     # dominant kernel: the two stable bucket-id rounds, each reading and
     # writing the 2-byte id, the key and the payload
     roof = hbm_roofline(prof, "learn_pass", 2 * n * (2 + 8 + 8))
@@ -510,6 +518,8 @@ def bench_learned(args, torch, rs, gen, np):
                 "speedup_vs_plain": plain_ms / ms,
                 "plain_skip_gkeys": n / (skip_ms * 1e-3) / 1e9, "plain_skip_rounds_skipped": skipped,
                 "speedup_vs_plain_skip": skip_ms / ms,
+                "feature_only_gkeys": n / (nonet_ms * 1e-3) / 1e9, "network_cost_ms": ms - nonet_ms,
+                "feature_only_keys_overflowed": st_nonet.keys_overflowed,
                 "fallback": st.fallback, "buckets_overflowed": st.buckets_overflowed,
                 "keys_overflowed": st.keys_overflowed, "train_loss": st.train_loss})
     del ws
