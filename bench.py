@@ -56,6 +56,8 @@ def parse():
     ap.add_argument("--plain-sample", type=int, default=512,
                     help="segments timed one plain-radix call each (segmented workload)")
     ap.add_argument("--dist", default="zipf", choices=["zipf", "lognormal", "mixture"])
+    ap.add_argument("--feature-mode", type=int, default=-1, choices=[-1, 0, 1, 2],
+                    help="learned: the key feature (-1 automatic, 0 linear, 1 log2, 2 sample quantiles)")
     ap.add_argument("--mbsp-radix", action="store_true",
                     help="lsd: the MBSP check of the parallel radix sort (Eqs. TsG, Tp4, Tp2; Observation 7)")
     ap.add_argument("--mbsp", action="store_true",
@@ -469,6 +471,8 @@ def bench_segmented(args, torch, rs, gen, np):
 
 def bench_learned(args, torch, rs, gen, np):
     n = 1 << args.log2n
+    if args.feature_mode != -1:
+        rs.rs_learned_set_opts(feature_mode=args.feature_mode)
     host = {"zipf": gen.zipf_u64, "lognormal": gen.lognormal_u64,
             "mixture": gen.gauss_mix_u64}[args.dist](gen.S0 + 5, n)
     keys = torch.from_numpy(host.view(np.int64)).cuda()
@@ -512,7 +516,7 @@ def bench_learned(args, torch, rs, gen, np):
     res = line(args, n / (ms * 1e-3) / 1e9, ms, "u64",
                "synthetic: %s u64 keys (seed S0+5), u64 payload = original index" % args.dist,
                {"workload": "learned-CDF buckets, n=2^%d u64 keys + u64 payload, %s" % (args.log2n, args.dist),
-                "n": n, "dist": args.dist},
+                "n": n, "dist": args.dist, "feature_mode": rs.rs_learned_get_opts()["feature_mode"]},
                roof, prof,
                {"plain_lsd_gkeys": n / (plain_ms * 1e-3) / 1e9, "plain_lsd_ms": plain_ms,
                 "speedup_vs_plain": plain_ms / ms,
