@@ -1,8 +1,11 @@
 // rs_tune.hip -- the autotuner: times every small-array algorithm and every
-// valid p for each length class on the device it runs on, installs the
-// fastest per class in the tuning table, and reports every timing, including
-// the device-wide LSD sort of one array per launch (the radix side of the
-// small-n crossover the paper observes on CPUs, Section 4, Observation 6).
+// valid p for each length class on the device it runs on (or, model-guided,
+// only the p a fitted cost model in the form of the paper's T_b and T_o
+// predicts best), installs the fastest per class in the tuning table, and
+// reports every timing, including the device-wide LSD sort of one array per
+// launch (the radix side of the small-n crossover the paper observes on
+// CPUs, Section 4, Observation 6); above the small classes it picks the
+// radix and tile of single arrays and the tile of large segments.
 #include <math.h>
 
 #include <cmath>
