@@ -138,9 +138,18 @@ def test_repeat_runs_identical(rs):
     ws = torch.empty(rs.rs_workspace_bytes(rs.RS_OP_SORT, a.numel(), 4, 0, 8), dtype=torch.uint8,
                      device="cuda")
     out = torch.empty_like(a)
-    for _ in range(30):
+    for _ in range(100):
         rs.rs_sort_u32(a, out, radix_bits=8, algo=rs.RS_ALGO_LSD, ws=ws)
         assert torch.equal(out, ref)
+    assert rs.rs_get_stats().device_error == 0
+    # key-value with many equal keys: the order of equal keys (the values)
+    # must come out the same every time too
+    k = to_dev((_u32(gen.S0 + 11, 1 << 20) & np.uint32(0xFF)).astype(np.uint32))
+    v = to_dev(np.arange(1 << 20, dtype=np.uint32))
+    rk, rv = rs.rs_sort_kv(k, v, radix_bits=8, algo=rs.RS_ALGO_LSD)
+    for _ in range(100):
+        ok, ov = rs.rs_sort_kv(k, v, radix_bits=8, algo=rs.RS_ALGO_LSD)
+        assert torch.equal(ok, rk) and torch.equal(ov, rv)
     assert rs.rs_get_stats().device_error == 0
 
 
