@@ -109,6 +109,13 @@ int main(int argc, char** argv) {
     EXPECT(rs_learned_debug_fault(RS_LEARNED_FAULT_SPLITTERS, nullptr, 0) == RS_ERR_INVALID);
     EXPECT(rs_learned_debug_fault(7, nullptr, 0) == RS_ERR_INVALID);
     EXPECT(rs_learned_debug_fault(RS_LEARNED_FAULT_NONE, nullptr, 0) == RS_OK);
+    EXPECT(rs_learned_debug_ids(nullptr, (uint16_t*)b) == RS_ERR_INVALID);
+    EXPECT(rs_learned_debug_ids((uint16_t*)a, nullptr) == RS_ERR_INVALID);
+    EXPECT(rs_learned_debug_ids(nullptr, nullptr) == RS_OK);
+    rs_tune_result tr[4];
+    EXPECT(rs_tune_run_model(nullptr, 0, 0, nullptr, tr, 4) == -RS_ERR_INVALID);
+    EXPECT(rs_tune_run_model(nullptr, 0, 16, nullptr, nullptr, 4) == -RS_ERR_INVALID);
+    EXPECT(rs_tune_run_model(nullptr, 0, 16, nullptr, tr, 4) == -RS_ERR_WORKSPACE);
     rs_block_model m;
     EXPECT(rs_blocks_get_model(&m) == RS_OK);
     rs_block_model m2 = m;
