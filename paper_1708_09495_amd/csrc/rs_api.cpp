@@ -758,7 +758,7 @@ namespace {
 const char* const KNAMES[KID_COUNT_] = {
     "fill", "hist", "onesweep", "copy", "batch", "seg_plan", "seg",
     "learn_sample", "learn_train", "learn_split", "learn_assign", "learn_bucket", "learn_check",
-    "wide_count", "wide_scatter", "learn_pass", "learn_mid", "block_merge", "stream_copy"};
+    "wide_count", "wide_scatter", "learn_pass", "learn_mid", "block_merge", "stream_copy", "seg_round"};
 struct Mark {
     int kid;
     hipEvent_t b, e;

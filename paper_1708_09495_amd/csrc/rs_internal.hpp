@@ -41,6 +41,7 @@ enum KernelId {
     KID_LEARN_MID,
     KID_BLOCK_MERGE,
     KID_STREAM_COPY,
+    KID_SEG_ROUND,
     KID_COUNT_
 };
 extern bool g_prof_on;
@@ -140,13 +141,37 @@ struct SegTable {
     int8_t seg_items[64]; // large segments: keys per thread of a tile, 8 or 16 (0: 16)
 };
 constexpr int TUNE_CLASSES = 33;  // classes 0 .. 32 in rs_tune_get / rs_tune_set
+// Segments of SEG_OS_MIN .. SEG_OS_MAX - 1 keys are sorted by onesweep
+// rounds whose tiles every workgroup takes from one counter per round (the
+// device-wide round's kernel, with the look-back inside each segment);
+// shorter (and longer) ones by one workgroup each.
+constexpr uint64_t SEG_OS_MIN = 1ull << 16;
+constexpr uint64_t SEG_OS_MAX = 1ull << 30;
+struct SegOs {
+    const int64_t* off = nullptr;        // segment offsets (S + 1)
+    const uint32_t* ttile = nullptr;     // first tile of each segment (S + 1; entry S: all tiles)
+    const uint32_t* tile_seg = nullptr;  // segment of each tile
+    const uint32_t* lrank = nullptr;     // rank of each segment among the large ones (S + 1)
+    const uint32_t* hist = nullptr;      // per large segment: 4 rounds x 256 digit counts
+    uint64_t nseg = 0;                   // S
+};
 struct SegPlan {
     size_t off_status = 0, off_cnt = 0, off_order = 0, off_tmp = 0;
+    // onesweep rounds of the large segments: tile map, per-segment
+    // histograms, round counters, look-back words (4 rounds x max_tiles x 256)
+    size_t off_ttile = 0, off_lrank = 0, off_tseg = 0, off_shist = 0, off_osctr = 0, off_oslb = 0;
+    uint64_t max_tiles = 0;  // bound on the tiles of the large segments (grid of a round)
     size_t zero_bytes = 0, total = 0;
 };
 bool seg_plan(uint64_t S, int64_t total, SegPlan* p);
 rs_status seg_run(const SegPlan& p, const uint32_t* in, uint32_t* out, const int64_t* offsets,
                   uint64_t S, int64_t total, const SegTable& table, void* ws, hipStream_t st);
+
+// the four onesweep rounds of the segments of SEG_OS_MIN .. SEG_OS_MAX - 1
+// keys (in -> tmp -> out -> tmp -> out), after their plan kernels
+rs_status segos_run(const SegPlan& p, const uint32_t* in, uint32_t* out, uint32_t* tmp, const int64_t* off,
+                    uint64_t S, unsigned char* ws, hipStream_t st);
+constexpr uint64_t SEG_OS_TILE = 512 * 28;  // keys per tile of those rounds
 
 size_t tune_ws_bytes(int instances);
 

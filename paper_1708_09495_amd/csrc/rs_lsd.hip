@@ -362,13 +362,13 @@ void launch_hist_fixed(const void* kin, uint64_t n, uint32_t* gh, uint32_t* zp, 
 // a compute unit (at the tile sizes above a few spilled registers cost less
 // than half the occupancy); radix-2^11 tiles are held to two workgroups by
 // their LDS anyway.
-template <typename K, int VB, int MAXB, int ITEMS, typename LB, typename OFF, int VB2 = 0>
+template <typename K, int VB, int MAXB, int ITEMS, typename LB, typename OFF, int VB2 = 0, bool SEG = false>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MAXB <= 8 ? 4 : 1))) void k_onesweep(
     const K* __restrict__ kin0, K* __restrict__ kout0, const void* __restrict__ vin0,
     void* __restrict__ vout0, uint64_t n, int shift, int bits, uint32_t* __restrict__ tile_ctr,
     LB* __restrict__ lb, const uint32_t* __restrict__ ghist, uint32_t* __restrict__ status,
     const Route* __restrict__ route, const void* __restrict__ vin2_ = nullptr,
-    void* __restrict__ vout2_ = nullptr) {
+    void* __restrict__ vout2_ = nullptr, SegOs sg = SegOs{}) {
     using V = typename ValT<VB>::type;
     constexpr int RMAX = 1 << MAXB;
     constexpr int RLO = RMAX < 256 ? RMAX : 256;      // slots of the LDS match
@@ -450,8 +450,24 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MAXB <= 8 ? 
     // per look-back block of LBB tiles and digit: the tiles counted so far
     // (bits 26 up) and the sum of their counts (LBB * 2^16 < 2^26)
     uint32_t* __restrict__ bwsum = reinterpret_cast<uint32_t*>(lb + (size_t)gridDim.x * R);
-    const uint64_t base = (uint64_t)tile * T;
-    const uint32_t nvalid = (uint32_t)((n - base) < (uint64_t)T ? (n - base) : (uint64_t)T);
+    // SEG: the tiles of all segments in one numbering; a tile covers
+    // positions [base, base + nvalid) of its segment [seg_lo, seg_lo +
+    // seg_len), its look-back stops at the segment's first tile, and its
+    // counts are counted from the segment's start
+    uint32_t tl = tile;              // tile within its segment
+    uint64_t seg_lo = 0, seg_len = n;
+    const uint32_t* __restrict__ hist0 = ghist;  // the round's digit counts (of the segment)
+    if constexpr (SEG) {
+        if (tile >= sg.ttile[sg.nseg]) return;  // past the last tile of the large segments
+        const uint32_t s = sg.tile_seg[tile];
+        tl = tile - sg.ttile[s];
+        seg_lo = (uint64_t)sg.off[s];
+        seg_len = (uint64_t)(sg.off[s + 1] - sg.off[s]);
+        hist0 = sg.hist + (size_t)sg.lrank[s] * (4 * RMAX) + (size_t)(shift / bits) * RMAX;
+    }
+    const uint64_t base = seg_lo + (uint64_t)tl * T;
+    const uint64_t rem = seg_len - (uint64_t)tl * T;
+    const uint32_t nvalid = (uint32_t)(rem < (uint64_t)T ? rem : (uint64_t)T);
     const bool full = nvalid == (uint32_t)T;
     const K* __restrict__ tin = kin + base;
 
@@ -548,11 +564,11 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MAXB <= 8 ? 
                     for (int w = 0; w < NW; ++w) t += wcnt[w * R + d];
                 }
                 tot[d] = t;
-                if (tile != 0)
+                if (tl != 0)
                     st_agent(&lb[(size_t)tile * R + d], (LB)(((LB)FLAG_AGG << LBW<LB>::SH) | (LB)t));
                 // this tile's count joins its look-back block's sum, with one
                 // more tile counted in the word's top bits
-                atomicAdd(&bwsum[(size_t)(tile / LBB) * R + d], (1u << BW_SH) | t);
+                if constexpr (!SEG) atomicAdd(&bwsum[(size_t)(tile / LBB) * R + d], (1u << BW_SH) | t);
             }
             part[q] = t;
             s += t;
@@ -627,15 +643,15 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MAXB <= 8 ? 
     // ---- global position of each digit's first key in this tile.  Taken
     //      after the LDS reorder: by then the tiles before this one have
     //      had longer to publish, so the look-back resolves in fewer steps.
-    if (tile == 0) {
+    if (tl == 0) {
         // Tile 0 starts the chain: its exclusive prefix is the exclusive
-        // scan of the round's global histogram.
+        // scan of the round's global histogram (SEG: of its segment's).
         uint32_t part[PER];
         uint32_t s = 0;
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
             const int d = tid * PER + q;
-            part[q] = d < R ? ghist[d] : 0u;
+            part[q] = d < R ? hist0[d] : 0u;
             s += part[q];
         }
         uint32_t total;
@@ -645,8 +661,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MAXB <= 8 ? 
         for (int q = 0; q < PER; ++q) {
             const int d = tid * PER + q;
             if (d < R) {
-                st_agent(&lb[d], (LB)(((LB)FLAG_PRE << LBW<LB>::SH) | (LB)(ex + tot[d])));
-                goff[d] = (OFF)((int64_t)ex - (int64_t)loc[d]);
+                st_agent(&lb[(size_t)tile * R + d], (LB)(((LB)FLAG_PRE << LBW<LB>::SH) | (LB)(ex + tot[d])));
+                goff[d] = (OFF)((int64_t)seg_lo + (int64_t)ex - (int64_t)loc[d]);
             }
             ex += part[q];
         }
@@ -665,8 +681,10 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MAXB <= 8 ? 
             // each; then whole blocks before it, each read as its last
             // tile's word (an inclusive prefix ends the walk) and its sum
             // (used once every tile of the block has counted); block 0 only
-            // by its last tile's prefix, which holds the digit's global base
-            const int64_t bfirst = (int64_t)(tile / LBB) * LBB;
+            // by its last tile's prefix, which holds the digit's global base.
+            // SEG: tile by tile down to the segment's first tile, whose
+            // inclusive prefix ends every walk of the segment
+            const int64_t bfirst = SEG ? (int64_t)tile - (int64_t)tl : (int64_t)(tile / LBB) * LBB;
             bool done = false;
             while (!done && j >= bfirst) {
                 LB w[LBWIN];
@@ -693,6 +711,10 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MAXB <= 8 ? 
                 }
             }
             int64_t b = bfirst / LBB - 1;  // nearest block not yet consumed
+            if constexpr (SEG) {
+                if (!done) atomicOr(status, STATUS_SPIN);  // the segment's first tile was not reached
+                done = true;
+            }
             while (!done && b >= 0) {
                 LB lt[LBWIN_B];
                 uint32_t bs[LBWIN_B];
@@ -726,7 +748,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MAXB <= 8 ? 
             }
             st_agent(&lb[(size_t)tile * R + d],
                      (LB)(((LB)FLAG_PRE << LBW<LB>::SH) | (LB)(excl + tot[d])));
-            goff[d] = (OFF)((int64_t)excl - (int64_t)loc[d]);
+            goff[d] = (OFF)((int64_t)seg_lo + (int64_t)excl - (int64_t)loc[d]);
         }
     }
     __syncthreads();
@@ -746,7 +768,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MAXB <= 8 ? 
             const K key = k[q];
             const uint32_t d = (uint32_t)(key >> shift) & dmask;
             OFF o = goff[d] + (OFF)j;
-            if ((uint64_t)(UOFF)o >= n) {
+            if ((uint64_t)((int64_t)o - (int64_t)seg_lo) >= seg_len) {
                 atomicOr(status, STATUS_RANGE);
                 o = -1;
             } else {
@@ -949,6 +971,99 @@ bool lsd_plan(size_t n, int kb, int vb, int bits, LsdPlan* p, int vb2, int items
     return true;
 }
 
+// ---- segments sorted by shared onesweep rounds --------------------------------
+
+__device__ __forceinline__ bool segos_large(const int64_t* off, uint64_t s) {
+    const int64_t b = off[s], e = off[s + 1];
+    return b >= 0 && e > b && (uint64_t)(e - b) >= SEG_OS_MIN && (uint64_t)(e - b) < SEG_OS_MAX;
+}
+
+// ttile[s] = tiles of the large segments before s, lrank[s] = large segments
+// before s (entries S: the totals); one workgroup scans S in chunks.
+__global__ __launch_bounds__(1024) void k_segos_scan(const int64_t* __restrict__ off, uint64_t S,
+                                                     uint32_t* __restrict__ ttile, uint32_t* __restrict__ lrank) {
+    __shared__ uint64_t part[1024];
+    const uint32_t tid = threadIdx.x;
+    uint64_t carry = 0;  // tiles in the low word, large segments in the high word
+    for (uint64_t c0 = 0; c0 < S; c0 += 1024) {
+        const uint64_t s = c0 + tid;
+        uint64_t v = 0;
+        if (s < S && segos_large(off, s))
+            v = ((uint64_t)1 << 32) | (uint64_t)((off[s + 1] - off[s] + (int64_t)SEG_OS_TILE - 1) / (int64_t)SEG_OS_TILE);
+        part[tid] = v;
+        __syncthreads();
+        for (uint32_t o = 1; o < 1024; o <<= 1) {
+            const uint64_t w = tid >= o ? part[tid - o] : 0;
+            __syncthreads();
+            part[tid] += w;
+            __syncthreads();
+        }
+        const uint64_t excl = carry + part[tid] - v;
+        if (s < S) {
+            ttile[s] = (uint32_t)excl;
+            lrank[s] = (uint32_t)(excl >> 32);
+        }
+        carry += part[1023];
+        __syncthreads();
+    }
+    if (tid == 0) {
+        ttile[S] = (uint32_t)carry;
+        lrank[S] = (uint32_t)(carry >> 32);
+    }
+}
+
+// tile_seg[t] = s for the tiles of large segment s; then each large
+// segment's digit counts of the four rounds (one read, lane-column LDS
+// counters), and the rounds' look-back words zeroed
+__global__ __launch_bounds__(512) void k_segos_hist(const uint32_t* __restrict__ keys, const int64_t* __restrict__ off,
+                                                    uint64_t S, const uint32_t* __restrict__ ttile,
+                                                    const uint32_t* __restrict__ lrank, uint32_t* __restrict__ tile_seg,
+                                                    uint32_t* __restrict__ hist, uint32_t* __restrict__ lbz,
+                                                    uint64_t max_tiles) {
+    constexpr int HC = 8;
+    __shared__ uint32_t hc[4 * 256 * HC];
+    const uint32_t tid = threadIdx.x;
+    // round r's words: lbz[r * max_tiles * 256 ...], the first ttile[S] tiles' in use
+    const uint64_t zwords = (uint64_t)ttile[S] * 256;
+    for (int r = 0; r < 4; ++r)
+        for (uint64_t j = (uint64_t)blockIdx.x * 512 + tid; j < zwords; j += (uint64_t)gridDim.x * 512)
+            lbz[(uint64_t)r * max_tiles * 256 + j] = 0u;
+    for (uint64_t s = blockIdx.x; s < S; s += gridDim.x) {
+        if (!segos_large(off, s)) continue;
+        for (uint32_t t = ttile[s] + tid; t < ttile[s + 1]; t += 512) tile_seg[t] = (uint32_t)s;
+        const uint32_t* __restrict__ in = keys + off[s];
+        const uint64_t L = (uint64_t)(off[s + 1] - off[s]);
+        const uint32_t col = tid & (HC - 1);
+        for (int i = tid; i < 4 * 256 * HC; i += 512) hc[i] = 0;
+        __syncthreads();
+        uint64_t q = tid;
+        for (; q + 3 * 512 < L; q += 4 * 512) {
+            const uint32_t k0 = in[q], k1 = in[q + 512], k2 = in[q + 1024], k3 = in[q + 1536];
+#pragma unroll
+            for (int p = 0; p < 4; ++p) {
+                atomicAdd(&hc[(p * 256 + __builtin_amdgcn_ubfe(k0, 8 * p, 8)) * HC + col], 1u);
+                atomicAdd(&hc[(p * 256 + __builtin_amdgcn_ubfe(k1, 8 * p, 8)) * HC + col], 1u);
+                atomicAdd(&hc[(p * 256 + __builtin_amdgcn_ubfe(k2, 8 * p, 8)) * HC + col], 1u);
+                atomicAdd(&hc[(p * 256 + __builtin_amdgcn_ubfe(k3, 8 * p, 8)) * HC + col], 1u);
+            }
+        }
+        for (; q < L; q += 512) {
+            const uint32_t k = in[q];
+#pragma unroll
+            for (int p = 0; p < 4; ++p) atomicAdd(&hc[(p * 256 + __builtin_amdgcn_ubfe(k, 8 * p, 8)) * HC + col], 1u);
+        }
+        __syncthreads();
+        uint32_t* h = hist + (size_t)lrank[s] * 1024;
+        for (int r = tid; r < 1024; r += 512) {
+            uint32_t c = 0;
+#pragma unroll
+            for (int cc = 0; cc < HC; ++cc) c += hc[r * HC + ((cc + r) & (HC - 1))];
+            h[r] = c;
+        }
+        __syncthreads();
+    }
+}
+
 rs_status lsd_run(const LsdPlan& p, const void* kin, void* kout, const void* vin, void* vout,
                   void* ws_, hipStream_t st, const void* vin2, void* vout2) {
     if (p.n == 0) return RS_OK;
@@ -1042,6 +1157,50 @@ rs_status lsd_run(const LsdPlan& p, const void* kin, void* kout, const void* vin
             e = hipMemcpyAsync(vout2, tv2, p.n * p.vb2, hipMemcpyDeviceToDevice, st);
         if (e != hipSuccess) return hip_fail(e);
         prof(st, KID_COPY, 1);
+    }
+    return RS_OK;
+}
+
+
+// The segments of SEG_OS_MIN .. SEG_OS_MAX - 1 keys: tile map and
+// histograms, then four rounds of the device-wide round's kernel over all
+// their tiles at once (in -> tmp -> out -> tmp -> out), the look-back of
+// each tile inside its own segment.
+rs_status segos_run(const SegPlan& p, const uint32_t* in, uint32_t* out, uint32_t* tmp, const int64_t* off,
+                    uint64_t S, unsigned char* ws, hipStream_t st) {
+    if (S == 0 || p.max_tiles == 0) return RS_OK;
+    uint32_t* ttile = reinterpret_cast<uint32_t*>(ws + p.off_ttile);
+    uint32_t* lrank = reinterpret_cast<uint32_t*>(ws + p.off_lrank);
+    uint32_t* tseg = reinterpret_cast<uint32_t*>(ws + p.off_tseg);
+    uint32_t* hist = reinterpret_cast<uint32_t*>(ws + p.off_shist);
+    uint32_t* ctr = reinterpret_cast<uint32_t*>(ws + p.off_osctr);
+    uint32_t* lbw = reinterpret_cast<uint32_t*>(ws + p.off_oslb);
+    uint32_t* status = reinterpret_cast<uint32_t*>(ws + p.off_status);
+    prof(st, KID_SEG_PLAN, 0);
+    hipLaunchKernelGGL(k_segos_scan, dim3(1), dim3(1024), 0, st, off, S, ttile, lrank);
+    uint64_t g = S < 4096 ? S : 4096;
+    hipLaunchKernelGGL(k_segos_hist, dim3((unsigned)g), dim3(512), 0, st, in, off, S, ttile, lrank, tseg, hist, lbw,
+                       (uint64_t)p.max_tiles);
+    prof(st, KID_SEG_PLAN, 1);
+    rs_status rc = launch_status();
+    if (rc != RS_OK) return rc;
+    SegOs sg;
+    sg.off = off;
+    sg.ttile = ttile;
+    sg.tile_seg = tseg;
+    sg.lrank = lrank;
+    sg.hist = hist;
+    sg.nseg = S;
+    const uint32_t* src = in;
+    for (int r = 0; r < 4; ++r) {
+        uint32_t* dst = (r & 1) ? out : tmp;
+        prof(st, KID_SEG_ROUND, 0);
+        hipLaunchKernelGGL((k_onesweep<uint32_t, 0, 8, 28, uint32_t, int64_t, 0, true>), dim3((unsigned)p.max_tiles),
+                           dim3(NT), 0, st, src, dst, nullptr, nullptr, (uint64_t)0, 8 * r, 8, ctr + r,
+                           lbw + (size_t)r * p.max_tiles * 256, nullptr, status, nullptr, nullptr, nullptr, sg);
+        prof(st, KID_SEG_ROUND, 1);
+        if ((rc = launch_status()) != RS_OK) return rc;
+        src = dst;
     }
     return RS_OK;
 }

@@ -303,6 +303,7 @@ __attribute__((amdgpu_waves_per_eu(4))) __global__ __launch_bounds__(SG_NT) void
             if (threadIdx.x == 0) atomicOr(status, STATUS_RANGE);
             continue;
         }
+        if (L >= SEG_OS_MIN && L < SEG_OS_MAX) continue;  // sorted by the shared onesweep rounds
         if (L == 1) {
             if (threadIdx.x == 0) out[b] = in[b];
             continue;
@@ -332,11 +333,31 @@ bool seg_plan(uint64_t S, int64_t total, SegPlan* p) {
     off += ALIGN;
     q.off_cnt = off;
     off += align_up(sizeof(uint32_t) * (2 * NCLASS + 1));
+    q.off_osctr = off;  // the four rounds' tile counters
+    off += align_up(sizeof(uint32_t) * 4);
     q.zero_bytes = off - q.off_status;
     q.off_order = off;
     off += align_up(sizeof(uint32_t) * (S ? S : 1));
     q.off_tmp = off;
     off += align_up(sizeof(uint32_t) * (size_t)(total ? total : 1));
+    // the large segments' onesweep rounds: at most total / T + S tiles (a
+    // segment's last tile is partial) and total / SEG_OS_MIN segments
+    if ((uint64_t)total >= SEG_OS_MIN) {
+        const uint64_t mt = (uint64_t)total / SEG_OS_TILE + S;
+        const uint64_t nl = (uint64_t)total / SEG_OS_MIN < S ? (uint64_t)total / SEG_OS_MIN : S;
+        if (mt >= (1ull << 31)) return false;
+        q.max_tiles = mt;
+        q.off_ttile = off;
+        off += align_up(sizeof(uint32_t) * (size_t)(S + 1));
+        q.off_lrank = off;
+        off += align_up(sizeof(uint32_t) * (size_t)(S + 1));
+        q.off_tseg = off;
+        off += align_up(sizeof(uint32_t) * (size_t)mt);
+        q.off_shist = off;
+        off += align_up(sizeof(uint32_t) * 1024 * (size_t)(nl ? nl : 1));
+        q.off_oslb = off;
+        off += align_up(sizeof(uint32_t) * 256 * 4 * (size_t)mt);
+    }
     q.total = off;
     *p = q;
     return true;
@@ -378,7 +399,8 @@ rs_status seg_run(const SegPlan& p, const uint32_t* in, uint32_t* out, const int
     hipLaunchKernelGGL(k_seg_sort, dim3((unsigned)grid), dim3(SG_NT), 0, st, in, out, tmp, offsets, S,
                        total, order, qctr, table, status);
     prof(st, KID_SEG, 1);
-    return launch_status();
+    if ((rc = launch_status()) != RS_OK) return rc;
+    return segos_run(p, in, out, tmp, offsets, S, ws, st);
 }
 
 }  // namespace rs
