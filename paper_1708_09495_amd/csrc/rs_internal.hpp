@@ -147,20 +147,26 @@ constexpr int TUNE_CLASSES = 33;  // classes 0 .. 32 in rs_tune_get / rs_tune_se
 // shorter (and longer) ones by one workgroup each.
 constexpr uint64_t SEG_OS_MIN = 1ull << 16;
 constexpr uint64_t SEG_OS_MAX = 1ull << 30;
+struct SegTile {          // one tile of the large segments' rounds (32 bytes)
+    int64_t lo;           // first position of its segment
+    int64_t len;          // keys of its segment (0: no tile, the workgroup leaves)
+    uint32_t tl;          // tile within the segment
+    uint32_t rank;        // the segment among the large ones (its histograms)
+    uint32_t bb;          // look-back block of the segment's first tile
+    uint32_t pad;
+};
 struct SegOs {
-    const int64_t* off = nullptr;        // segment offsets (S + 1)
-    const uint32_t* ttile = nullptr;     // first tile of each segment (S + 1; entry S: all tiles)
-    const uint32_t* tile_seg = nullptr;  // segment of each tile
-    const uint32_t* lrank = nullptr;     // rank of each segment among the large ones (S + 1)
+    const SegTile* td = nullptr;         // per tile of the round's numbering (max_tiles)
     const uint32_t* hist = nullptr;      // per large segment: 4 rounds x 256 digit counts
-    uint64_t nseg = 0;                   // S
 };
 struct SegPlan {
     size_t off_status = 0, off_cnt = 0, off_order = 0, off_tmp = 0;
     // onesweep rounds of the large segments: tile map, per-segment
     // histograms, round counters, look-back words (4 rounds x max_tiles x 256)
-    size_t off_ttile = 0, off_lrank = 0, off_tseg = 0, off_shist = 0, off_osctr = 0, off_oslb = 0;
-    uint64_t max_tiles = 0;  // bound on the tiles of the large segments (grid of a round)
+    size_t off_ttile = 0, off_lrank = 0, off_tdesc = 0, off_shist = 0, off_osctr = 0, off_oslb = 0;
+    uint64_t max_tiles = 0;   // bound on the tiles of the large segments (grid of a round)
+    uint64_t max_blocks = 0;  // bound on their look-back blocks of 16 tiles
+    size_t off_bbase = 0;
     size_t zero_bytes = 0, total = 0;
 };
 bool seg_plan(uint64_t S, int64_t total, SegPlan* p);

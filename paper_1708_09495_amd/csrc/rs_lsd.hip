@@ -398,7 +398,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MAXB <= 8 ? 
 
     __shared__ __align__(16) unsigned char u_raw[UB];
     __shared__ __align__(16) unsigned char v_raw[SEPV ? VALB : 16];
-    __shared__ OFF goff[RMAX];        // global destination of slot 0 of each digit
+    __shared__ OFF goff[RMAX];        // destination of slot 0 of each digit (SEG: from the segment's start)
     __shared__ uint32_t tot[RMAX];    // this tile's count per digit
     __shared__ uint32_t loc[RMAX];    // first LDS slot of each digit
     __shared__ uint32_t wsum[NW + 1];
@@ -455,15 +455,17 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MAXB <= 8 ? 
     // seg_len), its look-back stops at the segment's first tile, and its
     // counts are counted from the segment's start
     uint32_t tl = tile;              // tile within its segment
+    uint32_t blk0 = 0;               // look-back block of the segment's first tile
     uint64_t seg_lo = 0, seg_len = n;
     const uint32_t* __restrict__ hist0 = ghist;  // the round's digit counts (of the segment)
     if constexpr (SEG) {
-        if (tile >= sg.ttile[sg.nseg]) return;  // past the last tile of the large segments
-        const uint32_t s = sg.tile_seg[tile];
-        tl = tile - sg.ttile[s];
-        seg_lo = (uint64_t)sg.off[s];
-        seg_len = (uint64_t)(sg.off[s + 1] - sg.off[s]);
-        hist0 = sg.hist + (size_t)sg.lrank[s] * (4 * RMAX) + (size_t)(shift / bits) * RMAX;
+        const SegTile dsc = sg.td[tile];
+        if (dsc.len == 0) return;  // past the last tile of the large segments
+        tl = dsc.tl;
+        blk0 = dsc.bb;
+        seg_lo = (uint64_t)dsc.lo;
+        seg_len = (uint64_t)dsc.len;
+        hist0 = sg.hist + (size_t)dsc.rank * (4 * RMAX) + (size_t)(shift / bits) * RMAX;
     }
     const uint64_t base = seg_lo + (uint64_t)tl * T;
     const uint64_t rem = seg_len - (uint64_t)tl * T;
@@ -568,7 +570,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MAXB <= 8 ? 
                     st_agent(&lb[(size_t)tile * R + d], (LB)(((LB)FLAG_AGG << LBW<LB>::SH) | (LB)t));
                 // this tile's count joins its look-back block's sum, with one
                 // more tile counted in the word's top bits
-                if constexpr (!SEG) atomicAdd(&bwsum[(size_t)(tile / LBB) * R + d], (1u << BW_SH) | t);
+                atomicAdd(&bwsum[(size_t)(blk0 + tl / LBB) * R + d], (1u << BW_SH) | t);
             }
             part[q] = t;
             s += t;
@@ -662,7 +664,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MAXB <= 8 ? 
             const int d = tid * PER + q;
             if (d < R) {
                 st_agent(&lb[(size_t)tile * R + d], (LB)(((LB)FLAG_PRE << LBW<LB>::SH) | (LB)(ex + tot[d])));
-                goff[d] = (OFF)((int64_t)seg_lo + (int64_t)ex - (int64_t)loc[d]);
+                goff[d] = (OFF)((int64_t)ex - (int64_t)loc[d]);
             }
             ex += part[q];
         }
@@ -675,16 +677,18 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MAXB <= 8 ? 
         // waited for and re-read; no tile is ever skipped.
         for (int d = tid; d < R; d += NT) {
             LB excl = 0;
-            int64_t j = (int64_t)tile - 1;  // nearest predecessor not yet consumed
+            int32_t j = (int32_t)tile - 1;  // nearest predecessor not yet consumed (tile ids < 2^31)
             uint32_t spins = 0;
             // first the tiles of this tile's own look-back block, one word
             // each; then whole blocks before it, each read as its last
             // tile's word (an inclusive prefix ends the walk) and its sum
             // (used once every tile of the block has counted); block 0 only
             // by its last tile's prefix, which holds the digit's global base.
-            // SEG: tile by tile down to the segment's first tile, whose
-            // inclusive prefix ends every walk of the segment
-            const int64_t bfirst = SEG ? (int64_t)tile - (int64_t)tl : (int64_t)(tile / LBB) * LBB;
+            // SEG: the blocks are counted from the segment's first tile
+            // (t0), their sums from its block blk0, and the walk ends inside
+            // the segment
+            const int32_t t0 = (int32_t)(tile - tl);
+            const int32_t bfirst = t0 + (int32_t)(tl / LBB) * LBB;
             bool done = false;
             while (!done && j >= bfirst) {
                 LB w[LBWIN];
@@ -710,19 +714,15 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MAXB <= 8 ? 
                     __builtin_amdgcn_s_sleep(1);
                 }
             }
-            int64_t b = bfirst / LBB - 1;  // nearest block not yet consumed
-            if constexpr (SEG) {
-                if (!done) atomicOr(status, STATUS_SPIN);  // the segment's first tile was not reached
-                done = true;
-            }
+            int32_t b = (int32_t)(tl / LBB) - 1;  // nearest block not yet consumed
             while (!done && b >= 0) {
                 LB lt[LBWIN_B];
                 uint32_t bs[LBWIN_B];
 #pragma unroll
                 for (int q = 0; q < LBWIN_B; ++q) {
                     const bool in = b - q >= 0;
-                    lt[q] = in ? ld_agent(&lb[(size_t)((b - q) * LBB + LBB - 1) * R + d]) : (LB)0;
-                    bs[q] = (in && b - q > 0) ? ld_agent(&bwsum[(size_t)(b - q) * R + d]) : 0u;
+                    lt[q] = in ? ld_agent(&lb[(size_t)(t0 + (b - q) * LBB + LBB - 1) * R + d]) : (LB)0;
+                    bs[q] = (in && b - q > 0) ? ld_agent(&bwsum[(size_t)(blk0 + b - q) * R + d]) : 0u;
                 }
                 int used = 0;
 #pragma unroll
@@ -748,7 +748,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MAXB <= 8 ? 
             }
             st_agent(&lb[(size_t)tile * R + d],
                      (LB)(((LB)FLAG_PRE << LBW<LB>::SH) | (LB)(excl + tot[d])));
-            goff[d] = (OFF)((int64_t)seg_lo + (int64_t)excl - (int64_t)loc[d]);
+            goff[d] = (OFF)((int64_t)excl - (int64_t)loc[d]);
         }
     }
     __syncthreads();
@@ -768,12 +768,12 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MAXB <= 8 ? 
             const K key = k[q];
             const uint32_t d = (uint32_t)(key >> shift) & dmask;
             OFF o = goff[d] + (OFF)j;
-            if ((uint64_t)((int64_t)o - (int64_t)seg_lo) >= seg_len) {
+            if ((uint64_t)(UOFF)o >= seg_len) {
                 atomicOr(status, STATUS_RANGE);
                 o = -1;
             } else {
-                kout[(UOFF)o] = key;
-                if constexpr (VEARLY) vout[(UOFF)o] = v[q];
+                kout[seg_lo + (UOFF)o] = key;
+                if constexpr (VEARLY) vout[seg_lo + (UOFF)o] = v[q];
             }
             if constexpr ((VB != 0 && !VEARLY) || VB2 != 0) dst[q] = o;
         }
@@ -788,7 +788,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MAXB <= 8 ? 
 #pragma unroll
         for (int q = 0; q < ITEMS; ++q) {
             const uint32_t j = q * NT + tid;
-            if ((full || j < nvalid) && dst[q] >= 0) vout[(UOFF)dst[q]] = svals[j];
+            if ((full || j < nvalid) && dst[q] >= 0) vout[seg_lo + (UOFF)dst[q]] = svals[j];
         }
     }
     if constexpr (VB2 != 0) {
@@ -810,7 +810,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MAXB <= 8 ? 
 #pragma unroll
         for (int q = 0; q < ITEMS; ++q) {
             const uint32_t j = q * NT + tid;
-            if ((full || j < nvalid) && dst[q] >= 0) v2out[(UOFF)dst[q]] = sv2[j];
+            if ((full || j < nvalid) && dst[q] >= 0) v2out[seg_lo + (UOFF)dst[q]] = sv2[j];
         }
     }
 }
@@ -981,59 +981,109 @@ __device__ __forceinline__ bool segos_large(const int64_t* off, uint64_t s) {
 // ttile[s] = tiles of the large segments before s, lrank[s] = large segments
 // before s (entries S: the totals); one workgroup scans S in chunks.
 __global__ __launch_bounds__(1024) void k_segos_scan(const int64_t* __restrict__ off, uint64_t S,
-                                                     uint32_t* __restrict__ ttile, uint32_t* __restrict__ lrank) {
-    __shared__ uint64_t part[1024];
+                                                     uint32_t* __restrict__ ttile, uint32_t* __restrict__ lrank,
+                                                     uint32_t* __restrict__ bbase) {
+    __shared__ uint64_t part[1024], partb[1024];
     const uint32_t tid = threadIdx.x;
-    uint64_t carry = 0;  // tiles in the low word, large segments in the high word
+    uint64_t carry = 0, carryb = 0;  // tiles in the low word, large segments in the high word; blocks
     for (uint64_t c0 = 0; c0 < S; c0 += 1024) {
         const uint64_t s = c0 + tid;
-        uint64_t v = 0;
-        if (s < S && segos_large(off, s))
-            v = ((uint64_t)1 << 32) | (uint64_t)((off[s + 1] - off[s] + (int64_t)SEG_OS_TILE - 1) / (int64_t)SEG_OS_TILE);
+        uint64_t v = 0, vb = 0;
+        if (s < S && segos_large(off, s)) {
+            const uint64_t t = (uint64_t)((off[s + 1] - off[s] + (int64_t)SEG_OS_TILE - 1) / (int64_t)SEG_OS_TILE);
+            v = ((uint64_t)1 << 32) | t;
+            vb = (t + LBB - 1) / LBB;
+        }
         part[tid] = v;
+        partb[tid] = vb;
         __syncthreads();
         for (uint32_t o = 1; o < 1024; o <<= 1) {
             const uint64_t w = tid >= o ? part[tid - o] : 0;
+            const uint64_t wb = tid >= o ? partb[tid - o] : 0;
             __syncthreads();
             part[tid] += w;
+            partb[tid] += wb;
             __syncthreads();
         }
         const uint64_t excl = carry + part[tid] - v;
         if (s < S) {
             ttile[s] = (uint32_t)excl;
             lrank[s] = (uint32_t)(excl >> 32);
+            bbase[s] = (uint32_t)(carryb + partb[tid] - vb);
         }
         carry += part[1023];
+        carryb += partb[1023];
         __syncthreads();
     }
     if (tid == 0) {
         ttile[S] = (uint32_t)carry;
         lrank[S] = (uint32_t)(carry >> 32);
+        bbase[S] = (uint32_t)carryb;
     }
 }
 
-// tile_seg[t] = s for the tiles of large segment s; then each large
-// segment's digit counts of the four rounds (one read, lane-column LDS
-// counters), and the rounds' look-back words zeroed
-__global__ __launch_bounds__(512) void k_segos_hist(const uint32_t* __restrict__ keys, const int64_t* __restrict__ off,
-                                                    uint64_t S, const uint32_t* __restrict__ ttile,
-                                                    const uint32_t* __restrict__ lrank, uint32_t* __restrict__ tile_seg,
+// The last s in [0, S) with idx[s] <= t, for a non-decreasing idx: with
+// idx an exclusive scan of per-segment counts, the segment that holds item
+// t of the concatenated numbering (segments with no items are skipped over,
+// as the next one starts at the same value).
+__device__ __forceinline__ uint64_t segos_find(const uint32_t* __restrict__ idx, uint64_t S, uint32_t t) {
+    uint64_t lo = 0, hi = S;  // idx[lo] <= t < idx[hi] (idx[S] > t)
+    while (hi - lo > 1) {
+        const uint64_t m = (lo + hi) >> 1;
+        if (idx[m] <= t) lo = m;
+        else hi = m;
+    }
+    return lo;
+}
+
+// Tile descriptors (unused tiles of the round's grid get length 0), the
+// rounds' look-back words and the per-segment histograms zeroed.
+__global__ __launch_bounds__(256) void k_segos_desc(const int64_t* __restrict__ off, uint64_t S,
+                                                    const uint32_t* __restrict__ ttile,
+                                                    const uint32_t* __restrict__ lrank,
+                                                    const uint32_t* __restrict__ bbase, SegTile* __restrict__ td,
                                                     uint32_t* __restrict__ hist, uint32_t* __restrict__ lbz,
-                                                    uint64_t max_tiles) {
+                                                    uint64_t max_tiles, uint64_t max_blocks) {
+    const uint64_t i0 = (uint64_t)blockIdx.x * 256 + threadIdx.x, step = (uint64_t)gridDim.x * 256;
+    // round r's words: lbz[r * (max_tiles + max_blocks) * 256 ...], the
+    // first ttile[S] tiles' in use, then from max_tiles the first bbase[S]
+    // blocks' sums
+    const uint64_t zt = (uint64_t)ttile[S] * 256, zb = (uint64_t)bbase[S] * 256;
+    for (int r = 0; r < 4; ++r) {
+        uint32_t* lr = lbz + (uint64_t)r * (max_tiles + max_blocks) * 256;
+        for (uint64_t j = i0; j < zt; j += step) lr[j] = 0u;
+        for (uint64_t j = i0; j < zb; j += step) lr[max_tiles * 256 + j] = 0u;
+    }
+    const uint64_t zh = (uint64_t)lrank[S] * 1024;
+    for (uint64_t j = i0; j < zh; j += step) hist[j] = 0u;
+    const uint32_t used = ttile[S];
+    for (uint64_t t = i0; t < max_tiles; t += step) {
+        if (t >= used) {
+            td[t] = SegTile{0, 0, 0, 0, 0, 0};
+            continue;
+        }
+        const uint64_t s = segos_find(ttile, S, (uint32_t)t);
+        td[t] = SegTile{off[s], off[s + 1] - off[s], (uint32_t)t - ttile[s], lrank[s], bbase[s], 0};
+    }
+}
+
+// Per-segment digit counts of the four rounds: one workgroup per look-back
+// block (LBB tiles of one segment) counts its keys in lane-column LDS
+// counters and adds the non-zero counts to its segment's histogram.
+__global__ __launch_bounds__(512) void k_segos_hist(const uint32_t* __restrict__ keys, const int64_t* __restrict__ off,
+                                                    uint64_t S, const uint32_t* __restrict__ lrank,
+                                                    const uint32_t* __restrict__ bbase, uint32_t* __restrict__ hist) {
     constexpr int HC = 8;
+    constexpr uint64_t BK = (uint64_t)LBB * SEG_OS_TILE;  // keys per block
     __shared__ uint32_t hc[4 * 256 * HC];
-    const uint32_t tid = threadIdx.x;
-    // round r's words: lbz[r * max_tiles * 256 ...], the first ttile[S] tiles' in use
-    const uint64_t zwords = (uint64_t)ttile[S] * 256;
-    for (int r = 0; r < 4; ++r)
-        for (uint64_t j = (uint64_t)blockIdx.x * 512 + tid; j < zwords; j += (uint64_t)gridDim.x * 512)
-            lbz[(uint64_t)r * max_tiles * 256 + j] = 0u;
-    for (uint64_t s = blockIdx.x; s < S; s += gridDim.x) {
-        if (!segos_large(off, s)) continue;
-        for (uint32_t t = ttile[s] + tid; t < ttile[s + 1]; t += 512) tile_seg[t] = (uint32_t)s;
-        const uint32_t* __restrict__ in = keys + off[s];
-        const uint64_t L = (uint64_t)(off[s + 1] - off[s]);
-        const uint32_t col = tid & (HC - 1);
+    const uint32_t tid = threadIdx.x, col = tid & (HC - 1);
+    const uint32_t nb = bbase[S];
+    for (uint32_t b = blockIdx.x; b < nb; b += gridDim.x) {
+        const uint64_t s = segos_find(bbase, S, b);
+        const uint64_t lo = (uint64_t)off[s] + (uint64_t)(b - bbase[s]) * BK;
+        const uint64_t e = (uint64_t)off[s + 1];
+        const uint64_t L = e - lo < BK ? e - lo : BK;
+        const uint32_t* __restrict__ in = keys + lo;
         for (int i = tid; i < 4 * 256 * HC; i += 512) hc[i] = 0;
         __syncthreads();
         uint64_t q = tid;
@@ -1058,7 +1108,7 @@ __global__ __launch_bounds__(512) void k_segos_hist(const uint32_t* __restrict__
             uint32_t c = 0;
 #pragma unroll
             for (int cc = 0; cc < HC; ++cc) c += hc[r * HC + ((cc + r) & (HC - 1))];
-            h[r] = c;
+            if (c) atomicAdd(&h[r], c);
         }
         __syncthreads();
     }
@@ -1171,33 +1221,37 @@ rs_status segos_run(const SegPlan& p, const uint32_t* in, uint32_t* out, uint32_
     if (S == 0 || p.max_tiles == 0) return RS_OK;
     uint32_t* ttile = reinterpret_cast<uint32_t*>(ws + p.off_ttile);
     uint32_t* lrank = reinterpret_cast<uint32_t*>(ws + p.off_lrank);
-    uint32_t* tseg = reinterpret_cast<uint32_t*>(ws + p.off_tseg);
+    uint32_t* bbase = reinterpret_cast<uint32_t*>(ws + p.off_bbase);
+    SegTile* td = reinterpret_cast<SegTile*>(ws + p.off_tdesc);
     uint32_t* hist = reinterpret_cast<uint32_t*>(ws + p.off_shist);
     uint32_t* ctr = reinterpret_cast<uint32_t*>(ws + p.off_osctr);
     uint32_t* lbw = reinterpret_cast<uint32_t*>(ws + p.off_oslb);
     uint32_t* status = reinterpret_cast<uint32_t*>(ws + p.off_status);
     prof(st, KID_SEG_PLAN, 0);
-    hipLaunchKernelGGL(k_segos_scan, dim3(1), dim3(1024), 0, st, off, S, ttile, lrank);
-    uint64_t g = S < 4096 ? S : 4096;
-    hipLaunchKernelGGL(k_segos_hist, dim3((unsigned)g), dim3(512), 0, st, in, off, S, ttile, lrank, tseg, hist, lbw,
-                       (uint64_t)p.max_tiles);
+    hipLaunchKernelGGL(k_segos_scan, dim3(1), dim3(1024), 0, st, off, S, ttile, lrank, bbase);
+    {
+        const uint64_t zw = (uint64_t)(p.max_tiles + p.max_blocks) * 256;
+        uint64_t g = (zw + 255) / 256;
+        if (g > 4096) g = 4096;
+        hipLaunchKernelGGL(k_segos_desc, dim3((unsigned)g), dim3(256), 0, st, off, S, ttile, lrank, bbase, td, hist,
+                           lbw, (uint64_t)p.max_tiles, (uint64_t)p.max_blocks);
+        g = p.max_blocks < 4096 ? p.max_blocks : 4096;
+        hipLaunchKernelGGL(k_segos_hist, dim3((unsigned)g), dim3(512), 0, st, in, off, S, lrank, bbase, hist);
+    }
     prof(st, KID_SEG_PLAN, 1);
     rs_status rc = launch_status();
     if (rc != RS_OK) return rc;
     SegOs sg;
-    sg.off = off;
-    sg.ttile = ttile;
-    sg.tile_seg = tseg;
-    sg.lrank = lrank;
+    sg.td = td;
     sg.hist = hist;
-    sg.nseg = S;
     const uint32_t* src = in;
     for (int r = 0; r < 4; ++r) {
         uint32_t* dst = (r & 1) ? out : tmp;
         prof(st, KID_SEG_ROUND, 0);
-        hipLaunchKernelGGL((k_onesweep<uint32_t, 0, 8, 28, uint32_t, int64_t, 0, true>), dim3((unsigned)p.max_tiles),
+        hipLaunchKernelGGL((k_onesweep<uint32_t, 0, 8, 28, uint32_t, int32_t, 0, true>), dim3((unsigned)p.max_tiles),
                            dim3(NT), 0, st, src, dst, nullptr, nullptr, (uint64_t)0, 8 * r, 8, ctr + r,
-                           lbw + (size_t)r * p.max_tiles * 256, nullptr, status, nullptr, nullptr, nullptr, sg);
+                           lbw + (size_t)r * (p.max_tiles + p.max_blocks) * 256, nullptr, status, nullptr, nullptr,
+                           nullptr, sg);
         prof(st, KID_SEG_ROUND, 1);
         if ((rc = launch_status()) != RS_OK) return rc;
         src = dst;

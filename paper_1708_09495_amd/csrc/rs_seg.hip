@@ -347,16 +347,19 @@ bool seg_plan(uint64_t S, int64_t total, SegPlan* p) {
         const uint64_t nl = (uint64_t)total / SEG_OS_MIN < S ? (uint64_t)total / SEG_OS_MIN : S;
         if (mt >= (1ull << 31)) return false;
         q.max_tiles = mt;
+        q.max_blocks = mt / 16 + S;
+        q.off_bbase = off;
+        off += align_up(sizeof(uint32_t) * (size_t)(S + 1));
         q.off_ttile = off;
         off += align_up(sizeof(uint32_t) * (size_t)(S + 1));
         q.off_lrank = off;
         off += align_up(sizeof(uint32_t) * (size_t)(S + 1));
-        q.off_tseg = off;
-        off += align_up(sizeof(uint32_t) * (size_t)mt);
+        q.off_tdesc = off;
+        off += align_up(sizeof(SegTile) * (size_t)mt);
         q.off_shist = off;
         off += align_up(sizeof(uint32_t) * 1024 * (size_t)(nl ? nl : 1));
-        q.off_oslb = off;
-        off += align_up(sizeof(uint32_t) * 256 * 4 * (size_t)mt);
+        q.off_oslb = off;  // per round: the tiles' words, then the blocks' sums
+        off += align_up(sizeof(uint32_t) * 256 * 4 * (size_t)(mt + q.max_blocks));
     }
     q.total = off;
     *p = q;
