@@ -418,10 +418,13 @@ def bench_segmented(args, torch, rs, gen, np):
     assert rs.rs_get_stats().device_error == 0
     ms, prof = timed_steps(step, args.steps, args.warmup, rs, torch, launch_timing=True)
     # algorithmic bytes: a segment held in LDS is read and written once; a
-    # larger one takes four radix-2^8 rounds through HBM
+    # larger one takes four radix-2^8 rounds through HBM.  Segments of 2^16
+    # keys and more share the device-wide rounds ("seg_round", four launches
+    # a step, each reading and writing their keys once), which dominate.
     small = lens <= 16384
+    shared = lens >= 65536
     alg = 8 * int(lens[small].sum()) + 32 * int(lens[~small].sum())
-    roof = hbm_roofline(prof, "seg", alg)
+    roof = hbm_roofline(prof, "seg_round", 8 * int(lens[shared].sum()))
     # one plain LSD call per array, on a seeded sample of the segments
     rng = np.random.default_rng(int(gen.S0 + 4))
     pick = rng.choice(S, size=min(args.plain_sample, S), replace=False)
@@ -442,8 +445,10 @@ def bench_segmented(args, torch, rs, gen, np):
     res = line(args, total / (ms * 1e-3) / 1e9, ms, "u32",
                "synthetic: %d segments, lengths log-uniform in [16, 2^20) (seed S0+4), "
                "SplitMix64 uniform u32 keys (seed S0+4)" % S,
-               {"workload": "batched segmented sort, %d segments, %d keys, one persistent launch"
-                            % (S, total), "segments": S, "total_keys": total},
+               {"workload": "batched segmented sort, %d segments, %d keys: one persistent launch for "
+                            "segments below 2^16 keys, four shared radix-2^8 rounds for the longer ones"
+                            % (S, total), "segments": S, "total_keys": total,
+                "keys_in_shared_rounds": int(lens[shared].sum())},
                roof, prof,
                {"hbm_gbs": alg / (ms * 1e-3) / 1e9,
                 "plain_per_array_gkeys": total / plain_s / 1e9,

@@ -238,7 +238,8 @@ rs_status rs_sort_u32_noalloc(const uint32_t* in, uint32_t* out, size_t n, int r
  *                   rounds at radix <= 2^8: 8, 16 or 28 (0: by size, 16
  *                   below 2^23 keys);
  *   seg_tile_items  keys per thread of the tiles that sort a segment of the
- *                   class longer than one workgroup's capacity: 8 or 16
+ *                   class longer than one workgroup's capacity and shorter
+ *                   than 2^16 keys (or of 2^30 keys and more): 8 or 16
  *                   (0: 16).
  * The choices change the workspace a call needs: rs_workspace_bytes reads
  * the same table, so size the workspace after the table is set. */
@@ -309,10 +310,12 @@ typedef struct {
  *     tiles and at radix 2^11; the fastest is installed as the class's radix and
  *     tile if it beats the default (radix 2^8, 16-key tiles below 2^23
  *     keys, 28 above) by at least 3%, else the default;
- *   - every class k = 15 .. 20 with at least 512 segments of 2^k keys in
- *     instances * 16384 keys: the segmented sort of those segments with 8-
- *     and 16-key-per-thread tiles; 8 is installed if at least 3% faster,
- *     else 16 (classes with fewer segments keep their entry).
+ *   - classes k = 15 and 16, with at least 512 segments of 2^k keys (2^16 - 1
+ *     in class 16) in instances * 16384 keys: the segmented sort of those
+ *     segments with 8- and 16-key-per-thread tiles; 8 is installed if at
+ *     least 3% faster, else 16 (classes with fewer segments keep their
+ *     entry).  Segments of 2^16 .. 2^30 - 1 keys are sorted by the shared
+ *     device-wide rounds, which have no tile choice.
  * Each candidate is timed twice, interleaved with the others, and keeps its
  * faster time.
  * Writes at most `max` results to `out` (host) and returns how many, or

@@ -166,6 +166,7 @@ struct SegPlan {
     size_t off_ttile = 0, off_lrank = 0, off_tdesc = 0, off_shist = 0, off_osctr = 0, off_oslb = 0;
     uint64_t max_tiles = 0;   // bound on the tiles of the large segments (grid of a round)
     uint64_t max_blocks = 0;  // bound on their look-back blocks of 16 tiles
+    uint64_t max_large = 0;   // bound on their number (histograms held)
     size_t off_bbase = 0;
     size_t zero_bytes = 0, total = 0;
 };
@@ -176,7 +177,7 @@ rs_status seg_run(const SegPlan& p, const uint32_t* in, uint32_t* out, const int
 // the four onesweep rounds of the segments of SEG_OS_MIN .. SEG_OS_MAX - 1
 // keys (in -> tmp -> out -> tmp -> out), after their plan kernels
 rs_status segos_run(const SegPlan& p, const uint32_t* in, uint32_t* out, uint32_t* tmp, const int64_t* off,
-                    uint64_t S, unsigned char* ws, hipStream_t st);
+                    uint64_t S, int64_t total, unsigned char* ws, hipStream_t st);
 constexpr uint64_t SEG_OS_TILE = 512 * 28;  // keys per tile of those rounds
 
 size_t tune_ws_bytes(int instances);

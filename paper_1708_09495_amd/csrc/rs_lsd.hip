@@ -973,52 +973,64 @@ bool lsd_plan(size_t n, int kb, int vb, int bits, LsdPlan* p, int vb2, int items
 
 // ---- segments sorted by shared onesweep rounds --------------------------------
 
-__device__ __forceinline__ bool segos_large(const int64_t* off, uint64_t s) {
+// a valid segment of SEG_OS_MIN .. SEG_OS_MAX - 1 keys inside [0, total)
+__device__ __forceinline__ bool segos_large(const int64_t* off, uint64_t s, int64_t total) {
     const int64_t b = off[s], e = off[s + 1];
-    return b >= 0 && e > b && (uint64_t)(e - b) >= SEG_OS_MIN && (uint64_t)(e - b) < SEG_OS_MAX;
+    return b >= 0 && e > b && e <= total && (uint64_t)(e - b) >= SEG_OS_MIN && (uint64_t)(e - b) < SEG_OS_MAX;
 }
 
 // ttile[s] = tiles of the large segments before s, lrank[s] = large segments
-// before s (entries S: the totals); one workgroup scans S in chunks.
-__global__ __launch_bounds__(1024) void k_segos_scan(const int64_t* __restrict__ off, uint64_t S,
+// before s, bbase[s] = their look-back blocks before s (entries S: the
+// totals); one workgroup scans S in chunks.  Offsets that overlap (invalid:
+// reported by the classification) can add up to more than the plan holds:
+// then the range error is raised and the totals are set to zero, so that
+// no later kernel of the rounds touches a segment.
+__global__ __launch_bounds__(1024) void k_segos_scan(const int64_t* __restrict__ off, uint64_t S, int64_t total,
                                                      uint32_t* __restrict__ ttile, uint32_t* __restrict__ lrank,
-                                                     uint32_t* __restrict__ bbase) {
-    __shared__ uint64_t part[1024], partb[1024];
+                                                     uint32_t* __restrict__ bbase, uint64_t max_tiles,
+                                                     uint64_t max_blocks, uint64_t max_large,
+                                                     uint32_t* __restrict__ status) {
+    __shared__ uint64_t part[1024], partb[1024], partl[1024];
     const uint32_t tid = threadIdx.x;
-    uint64_t carry = 0, carryb = 0;  // tiles in the low word, large segments in the high word; blocks
+    uint64_t carry = 0, carryb = 0, carryl = 0;  // tiles, look-back blocks, large segments
     for (uint64_t c0 = 0; c0 < S; c0 += 1024) {
         const uint64_t s = c0 + tid;
-        uint64_t v = 0, vb = 0;
-        if (s < S && segos_large(off, s)) {
-            const uint64_t t = (uint64_t)((off[s + 1] - off[s] + (int64_t)SEG_OS_TILE - 1) / (int64_t)SEG_OS_TILE);
-            v = ((uint64_t)1 << 32) | t;
-            vb = (t + LBB - 1) / LBB;
+        uint64_t v = 0, vb = 0, vl = 0;
+        if (s < S && segos_large(off, s, total)) {
+            v = (uint64_t)((off[s + 1] - off[s] + (int64_t)SEG_OS_TILE - 1) / (int64_t)SEG_OS_TILE);
+            vb = (v + LBB - 1) / LBB;
+            vl = 1;
         }
         part[tid] = v;
         partb[tid] = vb;
+        partl[tid] = vl;
         __syncthreads();
         for (uint32_t o = 1; o < 1024; o <<= 1) {
             const uint64_t w = tid >= o ? part[tid - o] : 0;
             const uint64_t wb = tid >= o ? partb[tid - o] : 0;
+            const uint64_t wl = tid >= o ? partl[tid - o] : 0;
             __syncthreads();
             part[tid] += w;
             partb[tid] += wb;
+            partl[tid] += wl;
             __syncthreads();
         }
-        const uint64_t excl = carry + part[tid] - v;
         if (s < S) {
-            ttile[s] = (uint32_t)excl;
-            lrank[s] = (uint32_t)(excl >> 32);
+            ttile[s] = (uint32_t)(carry + part[tid] - v);
             bbase[s] = (uint32_t)(carryb + partb[tid] - vb);
+            lrank[s] = (uint32_t)(carryl + partl[tid] - vl);
         }
         carry += part[1023];
         carryb += partb[1023];
+        carryl += partl[1023];
         __syncthreads();
     }
     if (tid == 0) {
-        ttile[S] = (uint32_t)carry;
-        lrank[S] = (uint32_t)(carry >> 32);
-        bbase[S] = (uint32_t)carryb;
+        const bool fits = carry <= max_tiles && carryb <= max_blocks && carryl <= max_large;
+        if (!fits) atomicOr(status, STATUS_RANGE);
+        ttile[S] = fits ? (uint32_t)carry : 0u;
+        lrank[S] = fits ? (uint32_t)carryl : 0u;
+        bbase[S] = fits ? (uint32_t)carryb : 0u;
     }
 }
 
@@ -1217,7 +1229,7 @@ rs_status lsd_run(const LsdPlan& p, const void* kin, void* kout, const void* vin
 // their tiles at once (in -> tmp -> out -> tmp -> out), the look-back of
 // each tile inside its own segment.
 rs_status segos_run(const SegPlan& p, const uint32_t* in, uint32_t* out, uint32_t* tmp, const int64_t* off,
-                    uint64_t S, unsigned char* ws, hipStream_t st) {
+                    uint64_t S, int64_t total, unsigned char* ws, hipStream_t st) {
     if (S == 0 || p.max_tiles == 0) return RS_OK;
     uint32_t* ttile = reinterpret_cast<uint32_t*>(ws + p.off_ttile);
     uint32_t* lrank = reinterpret_cast<uint32_t*>(ws + p.off_lrank);
@@ -1228,7 +1240,8 @@ rs_status segos_run(const SegPlan& p, const uint32_t* in, uint32_t* out, uint32_
     uint32_t* lbw = reinterpret_cast<uint32_t*>(ws + p.off_oslb);
     uint32_t* status = reinterpret_cast<uint32_t*>(ws + p.off_status);
     prof(st, KID_SEG_PLAN, 0);
-    hipLaunchKernelGGL(k_segos_scan, dim3(1), dim3(1024), 0, st, off, S, ttile, lrank, bbase);
+    hipLaunchKernelGGL(k_segos_scan, dim3(1), dim3(1024), 0, st, off, S, total, ttile, lrank, bbase,
+                       (uint64_t)p.max_tiles, (uint64_t)p.max_blocks, (uint64_t)p.max_large, status);
     {
         const uint64_t zw = (uint64_t)(p.max_tiles + p.max_blocks) * 256;
         uint64_t g = (zw + 255) / 256;

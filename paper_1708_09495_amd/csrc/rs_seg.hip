@@ -34,8 +34,10 @@ constexpr int SG_P = 4;                       // rounds for 32-bit keys
 constexpr int NCLASS = 64;
 constexpr int SMEM = 16896 * 4;               // BTN/OET: p*(N+1) words for n_pad <= 16384
 
+// Length class k of the tuning table: lengths in (2^(k-1), 2^k], 0 for one
+// key (and for the empty and invalid segments, which are skipped).
 __device__ __forceinline__ int len_class(int64_t L) {
-    return L <= 0 ? 0 : 64 - __clzll((unsigned long long)L);
+    return L <= 1 ? 0 : 64 - __clzll((unsigned long long)(L - 1));
 }
 
 __global__ void k_seg_classify(const int64_t* __restrict__ off, uint64_t S, int64_t total,
@@ -348,6 +350,7 @@ bool seg_plan(uint64_t S, int64_t total, SegPlan* p) {
         if (mt >= (1ull << 31)) return false;
         q.max_tiles = mt;
         q.max_blocks = mt / 16 + S;
+        q.max_large = nl;
         q.off_bbase = off;
         off += align_up(sizeof(uint32_t) * (size_t)(S + 1));
         q.off_ttile = off;
@@ -403,7 +406,7 @@ rs_status seg_run(const SegPlan& p, const uint32_t* in, uint32_t* out, const int
                        total, order, qctr, table, status);
     prof(st, KID_SEG, 1);
     if ((rc = launch_status()) != RS_OK) return rc;
-    return segos_run(p, in, out, tmp, offsets, S, ws, st);
+    return segos_run(p, in, out, tmp, offsets, S, total, ws, st);
 }
 
 }  // namespace rs

@@ -74,6 +74,15 @@ def test_invalid_offsets_reported(rs):
     off = torch.tensor([0, 50, 40, 100], dtype=torch.int64, device="cuda")   # decreasing
     rs.rs_sort_segmented(keys, off)
     assert rs.rs_get_stats().device_error & 2
+    # segments long enough for the shared device-wide rounds: one that ends
+    # past the keys, and two valid ones that overlap (around an invalid one)
+    # by more tiles than the rounds' tables hold; both are reported, and no
+    # kernel touches memory outside the keys and the workspace
+    n = (1 << 17) + 1000
+    keys = torch.zeros(n, dtype=torch.int32, device="cuda")
+    for o in ([0, n + 4096], [0, 1 << 17, 0, n]):
+        rs.rs_sort_segmented(keys, torch.tensor(o, dtype=torch.int64, device="cuda"))
+        assert rs.rs_get_stats().device_error & 2, o
 
 
 def test_tuning_table_round_trip(rs, orc):
