@@ -636,12 +636,14 @@ def mbsp_check(args, torch, rs, keys, n, p, name, ms, stages, prof):
                          device="cuda")
         other_ms, _ = timed_steps(lambda: rs.rs_sort_blocks_u32(keys, out, algo=algo, p=p, ws=ws), 2, 1, rs, torch)
         del ws, out
-    # the serial sort: one workgroup sorts all n keys (one segment)
+    # the serial sort: one workgroup sorts all n keys (one segment, never
+    # the device-wide rounds: algo LSD)
     off = torch.tensor([0, n], dtype=torch.int64, device="cuda")
     out = torch.empty_like(keys)
-    ws = torch.empty(rs.rs_workspace_bytes(rs.RS_OP_SEGMENTED, n, 4, 0, 0, rs.RS_ALGO_AUTO, 1), dtype=torch.uint8,
+    ws = torch.empty(rs.rs_workspace_bytes(rs.RS_OP_SEGMENTED, n, 4, 0, 0, rs.RS_ALGO_LSD, 1), dtype=torch.uint8,
                      device="cuda")
-    serial_ms, _ = timed_steps(lambda: rs.rs_sort_segmented(keys, off, out, ws=ws), 1, 1, rs, torch)
+    serial_ms, _ = timed_steps(lambda: rs.rs_sort_segmented(keys, off, out, algo=rs.RS_ALGO_LSD, ws=ws), 1, 1,
+                               rs, torch)
     del ws, out
     btn_ms = ms if name == "btn" else other_ms
     oet_ms = ms if name == "oet" else other_ms
@@ -671,9 +673,10 @@ def mbsp_radix_check(args, torch, rs, keys, n, bits, ms):
     p = 2 * cus
     off = torch.tensor([0, n], dtype=torch.int64, device="cuda")
     out = torch.empty_like(keys)
-    ws = torch.empty(rs.rs_workspace_bytes(rs.RS_OP_SEGMENTED, n, 4, 0, 0, rs.RS_ALGO_AUTO, 1), dtype=torch.uint8,
+    ws = torch.empty(rs.rs_workspace_bytes(rs.RS_OP_SEGMENTED, n, 4, 0, 0, rs.RS_ALGO_LSD, 1), dtype=torch.uint8,
                      device="cuda")
-    serial_ms, _ = timed_steps(lambda: rs.rs_sort_segmented(keys, off, out, ws=ws), 1, 1, rs, torch)
+    serial_ms, _ = timed_steps(lambda: rs.rs_sort_segmented(keys, off, out, algo=rs.RS_ALGO_LSD, ws=ws), 1, 1,
+                               rs, torch)
     del ws
     G = serial_ms * 1e-3 / (68 * n)
     res = {"p": p, "G_ps": G * 1e12, "serial_one_workgroup_ms": serial_ms}

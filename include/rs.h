@@ -123,10 +123,21 @@ rs_status rs_sort_batch_u32(const uint32_t* in, uint32_t* out, size_t n, size_t 
  * (offsets: DEVICE array of num_segments+1 non-decreasing int64,
  * offsets[0] = 0, offsets[num_segments] = total_n; empty segments allowed;
  * no segment may exceed 2^32 - 1 keys).  Each segment is sorted
- * independently, all in one persistent launch; segments that fit one
- * workgroup's LDS are sorted there (BTN/OET/LDS radix per the tuning
- * table), larger ones by radix-2^b rounds.  algo: AUTO (tuned), BTN, OET or
- * LDS_RADIX forces the small-segment algorithm.  `in == out` is allowed. */
+ * independently (Section 3's radix-2^8 count-sort rounds, or a network of
+ * Section 2 in LDS).  One persistent launch sorts the segments of fewer
+ * than 2^16 keys (or 2^30 and more), each by one workgroup: those that fit
+ * its LDS there (BTN/OET/LDS radix per the tuning table), longer ones by
+ * its own radix-2^8 rounds.  The segments of 2^16 .. 2^30 - 1 keys are
+ * sorted together by four device-wide radix-2^8 rounds over all their
+ * tiles, each tile's prefix taken inside its own segment.
+ * algo: AUTO (tuned); BTN, OET or LDS_RADIX force the small-segment
+ * algorithm; LSD keeps the tuned small-segment algorithm and sorts every
+ * longer segment by one workgroup's rounds, never by the shared rounds
+ * (the schedule of the paper's model, one processor per segment; its
+ * workspace is smaller).  Invalid offsets (decreasing, negative, past
+ * total_n, or overlapping segments) raise the range error in the status
+ * word and leave the segments concerned unsorted; nothing outside `in`,
+ * `out` and the workspace is touched.  `in == out` is allowed. */
 rs_status rs_sort_segmented(const uint32_t* in, uint32_t* out, const int64_t* offsets,
                             size_t num_segments, int64_t total_n, rs_algo algo, void* ws,
                             size_t ws_bytes, void* stream);

@@ -316,10 +316,10 @@ rs_status rs_sort_segmented(const uint32_t* in, uint32_t* out, const int64_t* of
     if (total_n > 0 && in != out && overlaps(in, (size_t)total_n * 4, out, (size_t)total_n * 4))
         return RS_ERR_INVALID;
     if (algo != RS_ALGO_AUTO && algo != RS_ALGO_BTN && algo != RS_ALGO_OET &&
-        algo != RS_ALGO_LDS_RADIX)
+        algo != RS_ALGO_LDS_RADIX && algo != RS_ALGO_LSD)
         return RS_ERR_UNSUPPORTED;
     SegPlan p;
-    if (!seg_plan(num_segments, total_n, &p)) return RS_ERR_UNSUPPORTED;
+    if (!seg_plan(num_segments, total_n, &p, algo != RS_ALGO_LSD)) return RS_ERR_UNSUPPORTED;
     begin_call(algo);
     g_call.stats.radix_bits = 8;
     g_call.stats.passes = 4;
@@ -327,7 +327,7 @@ rs_status rs_sort_segmented(const uint32_t* in, uint32_t* out, const int64_t* of
     rs_status rc = check_ws(ws, ws_bytes, p.total);
     if (rc != RS_OK) return rc;
     SegTable t = tune_table();
-    if (algo != RS_ALGO_AUTO)
+    if (algo != RS_ALGO_AUTO && algo != RS_ALGO_LSD)
         for (int c = 0; c < 64; ++c) {
             t.algo[c] = (int8_t)algo;
             const int npad = c < 15 ? (1 << c) : 16384;
@@ -384,7 +384,7 @@ size_t rs_workspace_bytes(int op, size_t n, int key_bytes, int val_bytes, int ra
     }
     if (op == RS_OP_SEGMENTED) {
         SegPlan p;
-        if ((int64_t)n < 0 || !seg_plan(num_segments, (int64_t)n, &p)) return 0;
+        if ((int64_t)n < 0 || !seg_plan(num_segments, (int64_t)n, &p, algo != RS_ALGO_LSD)) return 0;
         return p.total;
     }
     return 0;

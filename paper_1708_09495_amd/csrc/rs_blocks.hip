@@ -201,7 +201,8 @@ bool block_plan(size_t n, int algo, uint32_t p, BlockPlan* bp) {
     q.N = (n + p - 1) / p;
     if ((uint64_t)p * q.N >= (1ull << 32)) return false;  // 32-bit positions
     q.nch = (uint32_t)((2 * q.N + MS_C - 1) / MS_C);
-    if (!seg_plan(p, (int64_t)n, &q.seg)) return false;
+    // one workgroup per run: the local sort of the paper's processors
+    if (!seg_plan(p, (int64_t)n, &q.seg, false)) return false;
     size_t off = 0;
     q.off_seg = off;
     off += align_up(q.seg.total);

@@ -169,8 +169,11 @@ struct SegPlan {
     uint64_t max_large = 0;   // bound on their number (histograms held)
     size_t off_bbase = 0;
     size_t zero_bytes = 0, total = 0;
+    bool shared = true;       // segments of SEG_OS_MIN .. SEG_OS_MAX - 1 keys share device-wide rounds
 };
-bool seg_plan(uint64_t S, int64_t total, SegPlan* p);
+// shared = false: every segment is sorted by one workgroup (the tables of
+// the shared rounds are not allocated)
+bool seg_plan(uint64_t S, int64_t total, SegPlan* p, bool shared = true);
 rs_status seg_run(const SegPlan& p, const uint32_t* in, uint32_t* out, const int64_t* offsets,
                   uint64_t S, int64_t total, const SegTable& table, void* ws, hipStream_t st);
 

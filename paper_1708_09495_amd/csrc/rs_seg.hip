@@ -288,7 +288,7 @@ __attribute__((amdgpu_waves_per_eu(4))) __global__ __launch_bounds__(SG_NT) void
                                                     const int64_t* __restrict__ off, uint64_t S,
                                                     int64_t total, const uint32_t* __restrict__ order,
                                                     uint32_t* __restrict__ qctr, SegTable table,
-                                                    uint32_t* __restrict__ status) {
+                                                    uint32_t* __restrict__ status, bool shared) {
     __shared__ __align__(16) unsigned char smem[SMEM];
     __shared__ uint32_t s_item;
     while (true) {
@@ -305,7 +305,7 @@ __attribute__((amdgpu_waves_per_eu(4))) __global__ __launch_bounds__(SG_NT) void
             if (threadIdx.x == 0) atomicOr(status, STATUS_RANGE);
             continue;
         }
-        if (L >= SEG_OS_MIN && L < SEG_OS_MAX) continue;  // sorted by the shared onesweep rounds
+        if (shared && L >= SEG_OS_MIN && L < SEG_OS_MAX) continue;  // sorted by the shared onesweep rounds
         if (L == 1) {
             if (threadIdx.x == 0) out[b] = in[b];
             continue;
@@ -327,7 +327,7 @@ __attribute__((amdgpu_waves_per_eu(4))) __global__ __launch_bounds__(SG_NT) void
 
 // ---- host side -------------------------------------------------------------------
 
-bool seg_plan(uint64_t S, int64_t total, SegPlan* p) {
+bool seg_plan(uint64_t S, int64_t total, SegPlan* p, bool shared) {
     if (total < 0 || S > 0x7FFFFFFFull) return false;
     SegPlan q;
     size_t off = 0;
@@ -344,7 +344,8 @@ bool seg_plan(uint64_t S, int64_t total, SegPlan* p) {
     off += align_up(sizeof(uint32_t) * (size_t)(total ? total : 1));
     // the large segments' onesweep rounds: at most total / T + S tiles (a
     // segment's last tile is partial) and total / SEG_OS_MIN segments
-    if ((uint64_t)total >= SEG_OS_MIN) {
+    q.shared = shared;
+    if (shared && (uint64_t)total >= SEG_OS_MIN) {
         const uint64_t mt = (uint64_t)total / SEG_OS_TILE + S;
         const uint64_t nl = (uint64_t)total / SEG_OS_MIN < S ? (uint64_t)total / SEG_OS_MIN : S;
         if (mt >= (1ull << 31)) return false;
@@ -403,9 +404,10 @@ rs_status seg_run(const SegPlan& p, const uint32_t* in, uint32_t* out, const int
     if (grid > S) grid = S;
     prof(st, KID_SEG, 0);
     hipLaunchKernelGGL(k_seg_sort, dim3((unsigned)grid), dim3(SG_NT), 0, st, in, out, tmp, offsets, S,
-                       total, order, qctr, table, status);
+                       total, order, qctr, table, status, p.shared);
     prof(st, KID_SEG, 1);
     if ((rc = launch_status()) != RS_OK) return rc;
+    if (!p.shared) return RS_OK;
     return segos_run(p, in, out, tmp, offsets, S, total, ws, st);
 }
 

@@ -35,7 +35,7 @@ MIXED = [0, 1, 2, 3, 15, 16, 17, 63, 64, 65, 100, 255, 256, 1000, 4095, 4096, 81
          16384, 16385, 20000, 40000, 65_535, 65_536, 71_680, 71_681, 100_000, 262_144, 0, 1]
 
 
-@pytest.mark.parametrize("algo", ["AUTO", "BTN", "OET", "LDS_RADIX"])
+@pytest.mark.parametrize("algo", ["AUTO", "BTN", "OET", "LDS_RADIX", "LSD"])
 def test_mixed_lengths(rs, orc, algo):
     import gen
     lens = np.array(MIXED, dtype=np.int64)
@@ -66,6 +66,26 @@ def test_in_place_and_single_segment(rs, orc):
         keys = gen.uniform_u32(gen.S0 + 40, int(off[-1]))
         out = _run(rs, keys, off, inplace=True)
         assert first_mismatch(out, orc.segmented(keys, off)) is None, lens
+
+
+def test_shared_rounds_only_without_lsd(rs, orc):
+    # AUTO sorts a segment of 2^17 keys by the four shared device-wide
+    # rounds; LSD by one workgroup's own rounds (no shared round launched)
+    import gen, torch
+    n = (1 << 17) + 3
+    keys = gen.uniform_u32(gen.S0 + 41, n)
+    off = np.array([0, n], dtype=np.int64)
+    ref = orc.segmented(keys, off)
+    for algo, rounds in ((rs.RS_ALGO_AUTO, 4), (rs.RS_ALGO_LSD, 0)):
+        rs.rs_profile_read()
+        rs.rs_profile_enable(True)
+        out = _run(rs, keys, off, algo)
+        torch.cuda.synchronize()
+        rs.rs_profile_enable(False)
+        prof = rs.rs_profile_read()
+        assert first_mismatch(out, ref) is None, algo
+        assert rs.rs_get_stats().device_error == 0
+        assert prof.get("seg_round", (0, 0.0))[0] == rounds, (algo, prof)
 
 
 def test_invalid_offsets_reported(rs):
