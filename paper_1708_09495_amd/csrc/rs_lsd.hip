@@ -374,10 +374,11 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MAXB <= 8 ? 
     constexpr int RLO = RMAX < 256 ? RMAX : 256;      // slots of the LDS match
     constexpr int T = NT * ITEMS;
     constexpr int PER = (RMAX + NT - 1) / NT;  // digits per thread in the digit scans
-    // Radix <= 2^8: keys are ranked in groups of 32 lanes (half a wave), and
-    // a digit's slot holds the group's 32-lane match mask in its low word and
-    // the group's running count of the digit in its high word.  Wider radices
-    // rank whole waves, with 16-bit counters beside the 64-lane masks.
+    // Radix <= 2^8: keys are ranked in groups of RANK_GL lanes, and a
+    // digit's slot holds the group's match mask in its low half and the
+    // group's running count of the digit in its high half (a 32-bit slot for
+    // 16-lane groups).  Wider radices rank whole waves, with 16-bit counters
+    // beside the 64-lane masks.
     constexpr bool HALF = MAXB <= 8;
     constexpr int GL = HALF ? RANK_GL : WAVE;  // lanes per ranking group
     constexpr int NG = NT / GL;                // ranking groups per workgroup
