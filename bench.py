@@ -418,11 +418,11 @@ def bench_segmented(args, torch, rs, gen, np):
     assert rs.rs_get_stats().device_error == 0
     ms, prof = timed_steps(step, args.steps, args.warmup, rs, torch, launch_timing=True)
     # algorithmic bytes: a segment held in LDS is read and written once; a
-    # larger one takes four radix-2^8 rounds through HBM.  Segments of 2^16
-    # keys and more share the device-wide rounds ("seg_round", four launches
-    # a step, each reading and writing their keys once), which dominate.
+    # larger one takes four radix-2^8 rounds through HBM: the device-wide
+    # rounds all of them share ("seg_round", four launches a step, each
+    # reading and writing their keys once), which dominate.
     small = lens <= 16384
-    shared = lens >= 65536
+    shared = ~small
     alg = 8 * int(lens[small].sum()) + 32 * int(lens[~small].sum())
     roof = hbm_roofline(prof, "seg_round", 8 * int(lens[shared].sum()))
     # one plain LSD call per array, on a seeded sample of the segments
@@ -446,7 +446,8 @@ def bench_segmented(args, torch, rs, gen, np):
                "synthetic: %d segments, lengths log-uniform in [16, 2^20) (seed S0+4), "
                "SplitMix64 uniform u32 keys (seed S0+4)" % S,
                {"workload": "batched segmented sort, %d segments, %d keys: one persistent launch for "
-                            "segments below 2^16 keys, four shared radix-2^8 rounds for the longer ones"
+                            "segments of at most 16,384 keys (in LDS), four shared radix-2^8 rounds for the "
+                            "longer ones"
                             % (S, total), "segments": S, "total_keys": total,
                 "keys_in_shared_rounds": int(lens[shared].sum())},
                roof, prof,

@@ -124,12 +124,12 @@ rs_status rs_sort_batch_u32(const uint32_t* in, uint32_t* out, size_t n, size_t 
  * offsets[0] = 0, offsets[num_segments] = total_n; empty segments allowed;
  * no segment may exceed 2^32 - 1 keys).  Each segment is sorted
  * independently (Section 3's radix-2^8 count-sort rounds, or a network of
- * Section 2 in LDS).  One persistent launch sorts the segments of fewer
- * than 2^16 keys (or 2^30 and more), each by one workgroup: those that fit
- * its LDS there (BTN/OET/LDS radix per the tuning table), longer ones by
- * its own radix-2^8 rounds.  The segments of 2^16 .. 2^30 - 1 keys are
- * sorted together by four device-wide radix-2^8 rounds over all their
- * tiles, each tile's prefix taken inside its own segment.
+ * Section 2 in LDS).  One persistent launch sorts the segments of at most
+ * 16,384 keys, each in one workgroup's LDS (BTN/OET/LDS radix per the
+ * tuning table), and those of 2^30 keys and more by one workgroup's own
+ * radix-2^8 rounds.  The segments of 16,385 .. 2^30 - 1 keys are sorted
+ * together by four device-wide radix-2^8 rounds over all their tiles, each
+ * tile's prefix taken inside its own segment.
  * algo: AUTO (tuned); BTN, OET or LDS_RADIX force the small-segment
  * algorithm; LSD keeps the tuned small-segment algorithm and sorts every
  * longer segment by one workgroup's rounds, never by the shared rounds
@@ -248,10 +248,10 @@ rs_status rs_sort_u32_noalloc(const uint32_t* in, uint32_t* out, size_t n, int r
  *   tile_items      keys per thread of the tiles of uint32 keys-only LSD
  *                   rounds at radix <= 2^8: 8, 16 or 28 (0: by size, 16
  *                   below 2^23 keys);
- *   seg_tile_items  keys per thread of the tiles that sort a segment of the
- *                   class longer than one workgroup's capacity and shorter
- *                   than 2^16 keys (or of 2^30 keys and more): 8 or 16
- *                   (0: 16).
+ *   seg_tile_items  keys per thread of the tiles with which one workgroup
+ *                   sorts a segment of the class longer than its LDS
+ *                   capacity (RS_ALGO_LSD segments, the block networks'
+ *                   runs, segments of 2^30 keys and more): 8 or 16 (0: 16).
  * The choices change the workspace a call needs: rs_workspace_bytes reads
  * the same table, so size the workspace after the table is set. */
 typedef struct {
@@ -321,12 +321,12 @@ typedef struct {
  *     tiles and at radix 2^11; the fastest is installed as the class's radix and
  *     tile if it beats the default (radix 2^8, 16-key tiles below 2^23
  *     keys, 28 above) by at least 3%, else the default;
- *   - classes k = 15 and 16, with at least 512 segments of 2^k keys (2^16 - 1
- *     in class 16) in instances * 16384 keys: the segmented sort of those
- *     segments with 8- and 16-key-per-thread tiles; 8 is installed if at
- *     least 3% faster, else 16 (classes with fewer segments keep their
- *     entry).  Segments of 2^16 .. 2^30 - 1 keys are sorted by the shared
- *     device-wide rounds, which have no tile choice.
+ *   - every class k = 15 .. 20 with at least 512 segments of 2^k keys in
+ *     instances * 16384 keys: those segments sorted one workgroup each (as
+ *     RS_ALGO_LSD sorts them) with 8- and 16-key-per-thread tiles; 8 is
+ *     installed if at least 3% faster, else 16 (classes with fewer segments
+ *     keep their entry).  The shared device-wide rounds, which sort such
+ *     segments under RS_ALGO_AUTO, have no tile choice.
  * Each candidate is timed twice, interleaved with the others, and keeps its
  * faster time.
  * Writes at most `max` results to `out` (host) and returns how many, or

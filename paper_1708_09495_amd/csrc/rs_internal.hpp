@@ -141,11 +141,12 @@ struct SegTable {
     int8_t seg_items[64]; // large segments: keys per thread of a tile, 8 or 16 (0: 16)
 };
 constexpr int TUNE_CLASSES = 33;  // classes 0 .. 32 in rs_tune_get / rs_tune_set
-// Segments of SEG_OS_MIN .. SEG_OS_MAX - 1 keys are sorted by onesweep
-// rounds whose tiles every workgroup takes from one counter per round (the
-// device-wide round's kernel, with the look-back inside each segment);
-// shorter (and longer) ones by one workgroup each.
-constexpr uint64_t SEG_OS_MIN = 1ull << 16;
+// Segments of SEG_OS_MIN .. SEG_OS_MAX - 1 keys (every segment too long for
+// one workgroup's LDS) are sorted by onesweep rounds whose tiles every
+// workgroup takes from one counter per round (the device-wide round's
+// kernel, with the look-back inside each segment); shorter (and longer)
+// ones by one workgroup each.
+constexpr uint64_t SEG_OS_MIN = (uint64_t)SEG_SMALL_MAX + 1;
 constexpr uint64_t SEG_OS_MAX = 1ull << 30;
 struct SegTile {          // one tile of the large segments' rounds (32 bytes)
     int64_t lo;           // first position of its segment
@@ -157,6 +158,7 @@ struct SegTile {          // one tile of the large segments' rounds (32 bytes)
 };
 struct SegOs {
     const SegTile* td = nullptr;         // per tile of the round's numbering (max_tiles)
+    const uint32_t* used = nullptr;      // tiles in use: workgroups numbered from here leave at once
     const uint32_t* hist = nullptr;      // per large segment: 4 rounds x 256 digit counts
 };
 struct SegPlan {

@@ -442,6 +442,11 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MAXB <= 8 ? 
     const uint32_t dmask = (uint32_t)R - 1;
     const uint32_t lomask = (1u << lob) - 1;
 
+    // SEG: the grid covers a bound on the tiles; the workgroups numbered
+    // past the tiles in use take no tile id (exactly as many workgroups as
+    // tiles take one, so every tile id is taken)
+    if constexpr (SEG)
+        if (blockIdx.x >= *sg.used) return;
     if (tid == 0) s_tile = atomicAdd(tile_ctr, 1u);
     if constexpr (!HALF)
         for (int i = tid; i < NW * R; i += NT) wcnt[i] = 0;
@@ -1257,6 +1262,7 @@ rs_status segos_run(const SegPlan& p, const uint32_t* in, uint32_t* out, uint32_
     if (rc != RS_OK) return rc;
     SegOs sg;
     sg.td = td;
+    sg.used = ttile + S;
     sg.hist = hist;
     const uint32_t* src = in;
     for (int r = 0; r < 4; ++r) {

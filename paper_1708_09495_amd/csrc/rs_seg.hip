@@ -342,15 +342,16 @@ bool seg_plan(uint64_t S, int64_t total, SegPlan* p, bool shared) {
     off += align_up(sizeof(uint32_t) * (S ? S : 1));
     q.off_tmp = off;
     off += align_up(sizeof(uint32_t) * (size_t)(total ? total : 1));
-    // the large segments' onesweep rounds: at most total / T + S tiles (a
-    // segment's last tile is partial) and total / SEG_OS_MIN segments
+    // the large segments' onesweep rounds: at most nl = min(S, total /
+    // SEG_OS_MIN) such segments, so at most total / T + nl tiles (a
+    // segment's last tile is partial) and tiles / 16 + nl look-back blocks
     q.shared = shared;
     if (shared && (uint64_t)total >= SEG_OS_MIN) {
-        const uint64_t mt = (uint64_t)total / SEG_OS_TILE + S;
         const uint64_t nl = (uint64_t)total / SEG_OS_MIN < S ? (uint64_t)total / SEG_OS_MIN : S;
+        const uint64_t mt = (uint64_t)total / SEG_OS_TILE + nl;
         if (mt >= (1ull << 31)) return false;
         q.max_tiles = mt;
-        q.max_blocks = mt / 16 + S;
+        q.max_blocks = mt / 16 + nl;
         q.max_large = nl;
         q.off_bbase = off;
         off += align_up(sizeof(uint32_t) * (size_t)(S + 1));

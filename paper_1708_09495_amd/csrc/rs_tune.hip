@@ -35,9 +35,10 @@ __global__ void k_even_offsets(int64_t* __restrict__ off, uint64_t S, uint64_t L
 }
 
 constexpr int TUNE_LSD_MAX = 24;  // largest class of the single-array LSD timings
-// largest class of the segment timings: longer segments (up to 2^30 - 1
-// keys) are sorted by the shared device-wide rounds, which have no tile choice
-constexpr int TUNE_SEG_MAX = 16;
+// largest class of the segment timings (the tile of the one-workgroup
+// rounds: RS_ALGO_LSD segments, the block networks' runs, segments of 2^30
+// keys and more; the shared device-wide rounds have no tile choice)
+constexpr int TUNE_SEG_MAX = 20;
 // A segment class is timed only with enough segments to occupy every
 // workgroup slot of the persistent launch at once (its throughput, not the
 // latency of a few segments, decides the batched workload).
@@ -407,12 +408,12 @@ int tune_impl(void* ws, size_t ws_bytes, int instances, void* stream, rs_tune_re
         table.radix[c] = (int8_t)LSD_CANDS[pick].bits;
         table.items[c] = (int8_t)LSD_CANDS[pick].items;
         if (c > TUNE_SEG_MAX) continue;
-        // S segments of the class's longest length the one-workgroup rounds
-        // sort (2^c keys, 2^16 - 1 in class 16), as one batch with each tile
-        const uint64_t S = N >> c, sl = n < SEG_OS_MIN ? n : SEG_OS_MIN - 1;
+        // S segments of 2^c keys, each sorted by one workgroup's rounds (no
+        // shared rounds), as one batch with each tile size
+        const uint64_t S = N >> c;
         SegPlan sp;
-        if (S < TUNE_SEG_MIN_COUNT || !seg_plan(S, (int64_t)(S * sl), &sp)) continue;
-        hipLaunchKernelGGL(k_even_offsets, dim3(64), dim3(256), 0, st, off, S, sl);
+        if (S < TUNE_SEG_MIN_COUNT || !seg_plan(S, (int64_t)(S * n), &sp, false)) continue;
+        hipLaunchKernelGGL(k_even_offsets, dim3(64), dim3(256), 0, st, off, S, n);
         if (hipGetLastError() != hipSuccess) return -RS_ERR_HIP;
         constexpr int SEG_CANDS[2] = {16, 8};  // the default first
         double stt[2] = {INFINITY, INFINITY};
@@ -421,7 +422,7 @@ int tune_impl(void* ws, size_t ws_bytes, int instances, void* stream, rs_tune_re
                 SegTable t2 = table;
                 t2.seg_items[c] = (int8_t)SEG_CANDS[q];
                 const double ms =
-                    time_ms([&] { seg_run(sp, in, dst, off, S, (int64_t)(S * sl), t2, lws, st); }, 3);
+                    time_ms([&] { seg_run(sp, in, dst, off, S, (int64_t)(S * n), t2, lws, st); }, 3);
                 stt[q] = ms < stt[q] ? ms : stt[q];
             }
         const int spick = stt[1] < stt[0] * (1.0 - TUNE_MARGIN) ? 1 : 0;
