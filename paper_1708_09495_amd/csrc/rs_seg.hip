@@ -1,8 +1,8 @@
-// rs_seg.hip -- batched segmented sort in one persistent launch (an
-// extension beyond the paper: many independent arrays of uneven length).
+// rs_seg.hip -- batched segmented sort (an extension beyond the paper: many
+// independent arrays of uneven length).
 //
 // Plan (three small kernels, all on the device):
-//   classify  each segment's length class = bit length of its length;
+//   classify  each segment's length class (lengths in (2^(c-1), 2^c]);
 //   scan      class cursors, largest class first;
 //   scatter   segment ids into a queue ordered by decreasing class, so the
 //             longest segments start first (longest-processing-time order).
@@ -10,7 +10,10 @@
 // until the queue is empty and sorts that segment by itself:
 //   length <= 16384  in LDS, with BTN, OET or the LDS radix sort as the
 //                    tuning table says for the length class;
-//   longer           the radix-2^8 count-sort rounds of Section 3 run by the
+//   longer           with the shared rounds (the default), only segments of
+//                    2^30 keys and more; without them (RS_ALGO_LSD, the
+//                    block networks' runs) every such segment: the
+//                    radix-2^8 count-sort rounds of Section 3 run by the
 //                    one workgroup: one read counts all four rounds' digits,
 //                    then each round walks the segment's tiles IN ORDER,
 //                    ranking each tile stably in LDS and writing each digit's
@@ -18,7 +21,9 @@
 //                    offsets stay in LDS, so no tile waits on another
 //                    workgroup.
 // Segments are independent, so workgroups never wait on each other and every
-// workgroup leaves once the queue is exhausted.
+// workgroup leaves once the queue is exhausted.  The segments of 16,385 ..
+// 2^30 - 1 keys are then sorted together by the device-wide round's kernel
+// over all their tiles (segos_run, in rs_lsd.hip).
 #include "rs_internal.hpp"
 #include "rs_small_dev.h"
 
