@@ -60,6 +60,21 @@ def test_host_side_queries(lib):
     assert lib.rs_status_string(3) == b"workspace missing, too small or misaligned"
 
 
+def test_segmented_workspace_grows_with_keys_not_segments(lib):
+    # the shared rounds' tables (look-back words and block sums, tile
+    # descriptors, per-segment histograms) are bounded by the keys: at most
+    # n / 16,385 segments can be long enough to use them
+    lib.rs_workspace_bytes.restype = ctypes.c_size_t
+    lib.rs_workspace_bytes.argtypes = [ctypes.c_int, ctypes.c_size_t, ctypes.c_int, ctypes.c_int,
+                                       ctypes.c_int, ctypes.c_int, ctypes.c_size_t]
+    n = 1 << 24
+    few = lib.rs_workspace_bytes(3, n, 4, 0, 0, 0, 64)
+    many = lib.rs_workspace_bytes(3, n, 4, 0, 0, 0, 1 << 20)
+    assert 4 * n < few < many < 8 * n + 32 * (1 << 20)
+    # RS_ALGO_LSD (one workgroup per segment) needs none of those tables
+    assert lib.rs_workspace_bytes(3, n, 4, 0, 0, 1, 1 << 20) < many
+
+
 def test_argument_errors_return_before_device_work(lib):
     vp = ctypes.c_void_p
     lib.rs_sort_u32.argtypes = [vp, vp, ctypes.c_size_t, ctypes.c_int, ctypes.c_int, vp,
