@@ -50,6 +50,13 @@ int main(int argc, char** argv) {
     EXPECT(rs_sort_u32_noalloc((uint32_t*)a, (uint32_t*)a, (1u << 22) + 1, 8, RS_ALGO_LSD, nullptr) ==
            RS_ERR_UNSUPPORTED);
     EXPECT(rs_stream_copy(a, (char*)a + 8, 64, nullptr) == RS_ERR_INVALID);
+    EXPECT(rs_sort_segmented((uint32_t*)a, (uint32_t*)b, (int64_t*)a, 3, -1, RS_ALGO_AUTO, nullptr, 0, nullptr) ==
+           RS_ERR_INVALID);
+    EXPECT(rs_sort_segmented((uint32_t*)a, (uint32_t*)b, (int64_t*)a, 3, 10, RS_ALGO_LEARNED, nullptr, 0, nullptr) ==
+           RS_ERR_UNSUPPORTED);
+    // the shared rounds' tables grow with the keys, not with the segment count
+    EXPECT(rs_workspace_bytes(RS_OP_SEGMENTED, (size_t)1 << 24, 4, 0, 0, RS_ALGO_AUTO, (size_t)1 << 20) <
+           ((size_t)8 << 24) + ((size_t)32 << 20));
     // workspace sizes over many shapes: non-zero, 256-byte multiples, growing with n
     for (int op = 0; op <= 5; ++op)
         for (int kb = 4; kb <= 8; kb += 4)
