@@ -117,3 +117,36 @@ def test_largest_kv_plan(rs):
     assert bool(seen.all())
     del k, v, ko, vo, seen
     torch.cuda.empty_cache()
+
+
+def test_largest_segments(rs):
+    """Segmented sort at the edge of the shared device-wide rounds: a segment
+    of 2^30 - 1 keys (the longest they take: look-back words and
+    destinations counted from the segment's start fit 30 and 31 bits), a
+    short one, and one of 2^30 + 5 keys (sorted by one workgroup's own
+    rounds, with 64-bit loop bounds).  Per segment: sorted, the same
+    multiset, and sampled ranks."""
+    import gen
+    import torch
+    lens = [(1 << 30) - 1, 7, (1 << 30) + 5]
+    off = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    n = int(off[-1])
+    print("case max segments n=%d lens=%s" % (n, lens), flush=True)
+    a = torch.empty(n, dtype=torch.int32, device="cuda")
+    gen.uniform_u32_dev(gen.S0 + 43, a)
+    out = rs.rs_sort_segmented(a, torch.from_numpy(off).cuda())
+    assert rs.rs_get_stats().device_error == 0
+    rng = np.random.default_rng(43)
+    for s in range(len(lens)):
+        b, e = int(off[s]), int(off[s + 1])
+        sa, so = a[b:e], out[b:e]
+        assert _sorted(so), s
+        ha, s1a, s2a = _fingerprint(sa, 32)
+        ho, s1o, s2o = _fingerprint(so, 32)
+        assert torch.equal(ha, ho) and s1a == s1o and s2a == s2o, s
+        L = e - b
+        for q in [0, L - 1] + [int(x) for x in rng.integers(0, L, 3)]:
+            lt, le = _rank_bounds(sa, _u(so[q:q + 1])[0])
+            assert lt <= q < le, (s, q)
+    del a, out
+    torch.cuda.empty_cache()
