@@ -996,40 +996,30 @@ __global__ __launch_bounds__(1024) void k_segos_scan(const int64_t* __restrict__
                                                      uint32_t* __restrict__ bbase, uint64_t max_tiles,
                                                      uint64_t max_blocks, uint64_t max_large,
                                                      uint32_t* __restrict__ status) {
-    __shared__ uint64_t part[1024], partb[1024], partl[1024];
+    __shared__ uint32_t wsum[1024 / WAVE + 1];
     const uint32_t tid = threadIdx.x;
     uint64_t carry = 0, carryb = 0, carryl = 0;  // tiles, look-back blocks, large segments
     for (uint64_t c0 = 0; c0 < S; c0 += 1024) {
         const uint64_t s = c0 + tid;
-        uint64_t v = 0, vb = 0, vl = 0;
+        // per segment at most 2^30 / SEG_OS_TILE tiles: a chunk's sums fit 32 bits
+        uint32_t v = 0, vb = 0, vl = 0;
         if (s < S && segos_large(off, s, total)) {
-            v = (uint64_t)((off[s + 1] - off[s] + (int64_t)SEG_OS_TILE - 1) / (int64_t)SEG_OS_TILE);
+            v = (uint32_t)((off[s + 1] - off[s] + (int64_t)SEG_OS_TILE - 1) / (int64_t)SEG_OS_TILE);
             vb = (v + LBB - 1) / LBB;
             vl = 1;
         }
-        part[tid] = v;
-        partb[tid] = vb;
-        partl[tid] = vl;
-        __syncthreads();
-        for (uint32_t o = 1; o < 1024; o <<= 1) {
-            const uint64_t w = tid >= o ? part[tid - o] : 0;
-            const uint64_t wb = tid >= o ? partb[tid - o] : 0;
-            const uint64_t wl = tid >= o ? partl[tid - o] : 0;
-            __syncthreads();
-            part[tid] += w;
-            partb[tid] += wb;
-            partl[tid] += wl;
-            __syncthreads();
-        }
+        uint32_t tt, tb, tl;
+        const uint32_t et = block_excl_scan<1024>(v, wsum, &tt);
+        const uint32_t eb = block_excl_scan<1024>(vb, wsum, &tb);
+        const uint32_t el = block_excl_scan<1024>(vl, wsum, &tl);
         if (s < S) {
-            ttile[s] = (uint32_t)(carry + part[tid] - v);
-            bbase[s] = (uint32_t)(carryb + partb[tid] - vb);
-            lrank[s] = (uint32_t)(carryl + partl[tid] - vl);
+            ttile[s] = (uint32_t)(carry + et);
+            bbase[s] = (uint32_t)(carryb + eb);
+            lrank[s] = (uint32_t)(carryl + el);
         }
-        carry += part[1023];
-        carryb += partb[1023];
-        carryl += partl[1023];
-        __syncthreads();
+        carry += tt;
+        carryb += tb;
+        carryl += tl;
     }
     if (tid == 0) {
         const bool fits = carry <= max_tiles && carryb <= max_blocks && carryl <= max_large;

@@ -45,15 +45,23 @@ __device__ __forceinline__ int len_class(int64_t L) {
     return L <= 1 ? 0 : 64 - __clzll((unsigned long long)(L - 1));
 }
 
+// Per-class segment counts: each workgroup counts its segments in LDS and
+// adds one word per class to the global counts.
 __global__ void k_seg_classify(const int64_t* __restrict__ off, uint64_t S, int64_t total,
                                uint32_t* __restrict__ cnt, uint32_t* __restrict__ status) {
+    __shared__ uint32_t lc[NCLASS];
+    for (uint32_t i = threadIdx.x; i < NCLASS; i += blockDim.x) lc[i] = 0;
+    __syncthreads();
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; s < S; s += stride) {
         const int64_t b = off[s], e = off[s + 1];
         if (b < 0 || e < b || e > total || (s == 0 && b != 0)) atomicOr(status, STATUS_RANGE);
         const int c = (b < 0 || e < b || e > total) ? 0 : len_class(e - b);
-        atomicAdd(&cnt[c], 1u);
+        atomicAdd(&lc[c], 1u);
     }
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < NCLASS; i += blockDim.x)
+        if (lc[i]) atomicAdd(&cnt[i], lc[i]);
 }
 
 // One workgroup of NCLASS threads: cursor[c] = number of segments in classes
@@ -68,14 +76,32 @@ __global__ void k_seg_scan(const uint32_t* __restrict__ cnt, uint32_t* __restric
     }
 }
 
+// Segment ids into the queue, by class: per chunk of the workgroup's
+// segments, LDS ranks within each class and one global reservation per class.
 __global__ void k_seg_scatter(const int64_t* __restrict__ off, uint64_t S, int64_t total,
                               uint32_t* __restrict__ cursor, uint32_t* __restrict__ order) {
+    __shared__ uint32_t lc[NCLASS], lbase[NCLASS];
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; s < S; s += stride) {
-        const int64_t b = off[s], e = off[s + 1];
-        const int c = (b < 0 || e < b || e > total) ? 0 : len_class(e - b);
-        const uint32_t pos = atomicAdd(&cursor[c], 1u);
-        if (pos < S) order[pos] = (uint32_t)s;
+    for (uint64_t c0 = (uint64_t)blockIdx.x * blockDim.x; c0 < S; c0 += stride) {
+        for (uint32_t i = threadIdx.x; i < NCLASS; i += blockDim.x) lc[i] = 0;
+        __syncthreads();
+        const uint64_t s = c0 + threadIdx.x;
+        int c = 0;
+        uint32_t r = 0;
+        if (s < S) {
+            const int64_t b = off[s], e = off[s + 1];
+            c = (b < 0 || e < b || e > total) ? 0 : len_class(e - b);
+            r = atomicAdd(&lc[c], 1u);
+        }
+        __syncthreads();
+        for (uint32_t i = threadIdx.x; i < NCLASS; i += blockDim.x)
+            if (lc[i]) lbase[i] = atomicAdd(&cursor[i], lc[i]);
+        __syncthreads();
+        if (s < S) {
+            const uint32_t pos = lbase[c] + r;
+            if (pos < S) order[pos] = (uint32_t)s;
+        }
+        __syncthreads();
     }
 }
 
