@@ -417,12 +417,13 @@ def bench_segmented(args, torch, rs, gen, np):
     torch.cuda.synchronize()
     assert rs.rs_get_stats().device_error == 0
     ms, prof = timed_steps(step, args.steps, args.warmup, rs, torch, launch_timing=True)
-    # algorithmic bytes: a segment held in LDS is read and written once; a
-    # larger one takes four radix-2^8 rounds through HBM: the device-wide
-    # rounds all of them share ("seg_round", four launches a step, each
-    # reading and writing their keys once), which dominate.
-    small = lens <= 16384
-    shared = ~small
+    # algorithmic bytes: a segment sorted in LDS is read and written once;
+    # the others take four radix-2^8 rounds through HBM, the device-wide
+    # rounds shared by the segments of 10,241 .. 14,336 and 16,385 .. 2^30 -
+    # 1 keys ("seg_round", four launches a step, each reading and writing
+    # their keys once), which dominate.
+    shared = ((lens >= 10241) & (lens <= 14336)) | ((lens > 16384) & (lens < (1 << 30)))
+    small = ~shared & (lens <= 16384)
     alg = 8 * int(lens[small].sum()) + 32 * int(lens[~small].sum())
     roof = hbm_roofline(prof, "seg_round", 8 * int(lens[shared].sum()))
     # one plain LSD call per array, on a seeded sample of the segments
@@ -445,9 +446,9 @@ def bench_segmented(args, torch, rs, gen, np):
     res = line(args, total / (ms * 1e-3) / 1e9, ms, "u32",
                "synthetic: %d segments, lengths log-uniform in [16, 2^20) (seed S0+4), "
                "SplitMix64 uniform u32 keys (seed S0+4)" % S,
-               {"workload": "batched segmented sort, %d segments, %d keys: one persistent launch for "
-                            "segments of at most 16,384 keys (in LDS), four shared radix-2^8 rounds for the "
-                            "longer ones"
+               {"workload": "batched segmented sort, %d segments, %d keys: four shared radix-2^8 rounds "
+                            "for the segments of 10,241 .. 14,336 and 16,385 .. 2^30 - 1 keys, one persistent "
+                            "launch (in LDS) for the others"
                             % (S, total), "segments": S, "total_keys": total,
                 "keys_in_shared_rounds": int(lens[shared].sum())},
                roof, prof,

@@ -124,12 +124,13 @@ rs_status rs_sort_batch_u32(const uint32_t* in, uint32_t* out, size_t n, size_t 
  * offsets[0] = 0, offsets[num_segments] = total_n; empty segments allowed;
  * no segment may exceed 2^32 - 1 keys).  Each segment is sorted
  * independently (Section 3's radix-2^8 count-sort rounds, or a network of
- * Section 2 in LDS).  One persistent launch sorts the segments of at most
- * 16,384 keys, each in one workgroup's LDS (BTN/OET/LDS radix per the
- * tuning table), and those of 2^30 keys and more by one workgroup's own
- * radix-2^8 rounds.  The segments of 16,385 .. 2^30 - 1 keys are sorted
- * together by four device-wide radix-2^8 rounds over all their tiles, each
- * tile's prefix taken inside its own segment.
+ * Section 2 in LDS).  The segments of 10,241 .. 14,336 keys (one tile of
+ * those rounds, at least 71% full) and of 16,385 .. 2^30 - 1 keys are
+ * sorted together by four device-wide radix-2^8 rounds over all their
+ * tiles of 14,336 keys, each tile's prefix taken inside its own segment.
+ * One persistent launch sorts the others, each by one workgroup: in its
+ * LDS up to 16,384 keys (BTN/OET/LDS radix per the tuning table), by its
+ * own radix-2^8 rounds from 2^30 keys.
  * algo: AUTO (tuned); BTN, OET or LDS_RADIX force the small-segment
  * algorithm; LSD keeps the tuned small-segment algorithm and sorts every
  * longer segment by one workgroup's rounds, never by the shared rounds

@@ -141,13 +141,21 @@ struct SegTable {
     int8_t seg_items[64]; // large segments: keys per thread of a tile, 8 or 16 (0: 16)
 };
 constexpr int TUNE_CLASSES = 33;  // classes 0 .. 32 in rs_tune_get / rs_tune_set
-// Segments of SEG_OS_MIN .. SEG_OS_MAX - 1 keys (every segment too long for
-// one workgroup's LDS) are sorted by onesweep rounds whose tiles every
-// workgroup takes from one counter per round (the device-wide round's
-// kernel, with the look-back inside each segment); shorter (and longer)
-// ones by one workgroup each.
-constexpr uint64_t SEG_OS_MIN = (uint64_t)SEG_SMALL_MAX + 1;
+// Segments that fill their tiles well are sorted by onesweep rounds whose
+// tiles every workgroup takes from one counter per round (the device-wide
+// round's kernel, with the look-back inside each segment): every segment
+// too long for one workgroup's LDS, up to SEG_OS_MAX - 1 keys, and those
+// that fill one tile at least 71% (SEG_OS_MIN .. SEG_OS_TILE keys; a tile
+// costs about the same whatever it holds, and below that fill, or with a
+// second tile at most 2,048 keys long, one workgroup's LDS sort is faster).
+// The others are sorted by one workgroup each.
+constexpr uint64_t SEG_OS_MIN = 10241;
 constexpr uint64_t SEG_OS_MAX = 1ull << 30;
+constexpr uint64_t SEG_OS_TILE = 512 * 28;  // keys per tile of those rounds
+constexpr bool seg_shared_len(uint64_t L) {
+    return (L >= SEG_OS_MIN && L <= SEG_OS_TILE) || (L > SEG_SMALL_MAX && L < SEG_OS_MAX);
+}
+static_assert(SEG_OS_MIN <= SEG_OS_TILE && SEG_OS_TILE <= SEG_SMALL_MAX, "one tile, then the LDS capacity");
 struct SegTile {          // one tile of the large segments' rounds (32 bytes)
     int64_t lo;           // first position of its segment
     int64_t len;          // keys of its segment (0: no tile, the workgroup leaves)
@@ -171,7 +179,7 @@ struct SegPlan {
     uint64_t max_large = 0;   // bound on their number (histograms held)
     size_t off_bbase = 0;
     size_t zero_bytes = 0, total = 0;
-    bool shared = true;       // segments of SEG_OS_MIN .. SEG_OS_MAX - 1 keys share device-wide rounds
+    bool shared = true;       // segments of the lengths seg_shared_len takes share device-wide rounds
 };
 // shared = false: every segment is sorted by one workgroup (the tables of
 // the shared rounds are not allocated)
@@ -179,11 +187,10 @@ bool seg_plan(uint64_t S, int64_t total, SegPlan* p, bool shared = true);
 rs_status seg_run(const SegPlan& p, const uint32_t* in, uint32_t* out, const int64_t* offsets,
                   uint64_t S, int64_t total, const SegTable& table, void* ws, hipStream_t st);
 
-// the four onesweep rounds of the segments of SEG_OS_MIN .. SEG_OS_MAX - 1
-// keys (in -> tmp -> out -> tmp -> out), after their plan kernels
+// the four onesweep rounds of the segments seg_shared_len takes (in -> tmp
+// -> out -> tmp -> out), after their plan kernels
 rs_status segos_run(const SegPlan& p, const uint32_t* in, uint32_t* out, uint32_t* tmp, const int64_t* off,
                     uint64_t S, int64_t total, unsigned char* ws, hipStream_t st);
-constexpr uint64_t SEG_OS_TILE = 512 * 28;  // keys per tile of those rounds
 
 size_t tune_ws_bytes(int instances);
 

@@ -979,10 +979,10 @@ bool lsd_plan(size_t n, int kb, int vb, int bits, LsdPlan* p, int vb2, int items
 
 // ---- segments sorted by shared onesweep rounds --------------------------------
 
-// a valid segment of SEG_OS_MIN .. SEG_OS_MAX - 1 keys inside [0, total)
+// a valid segment inside [0, total) of a length the shared rounds take
 __device__ __forceinline__ bool segos_large(const int64_t* off, uint64_t s, int64_t total) {
     const int64_t b = off[s], e = off[s + 1];
-    return b >= 0 && e > b && e <= total && (uint64_t)(e - b) >= SEG_OS_MIN && (uint64_t)(e - b) < SEG_OS_MAX;
+    return b >= 0 && e > b && e <= total && seg_shared_len((uint64_t)(e - b));
 }
 
 // ttile[s] = tiles of the large segments before s, lrank[s] = large segments
@@ -1220,7 +1220,7 @@ rs_status lsd_run(const LsdPlan& p, const void* kin, void* kout, const void* vin
 }
 
 
-// The segments of SEG_OS_MIN .. SEG_OS_MAX - 1 keys: tile map and
+// The segments of the lengths seg_shared_len takes: tile map and
 // histograms, then four rounds of the device-wide round's kernel over all
 // their tiles at once (in -> tmp -> out -> tmp -> out), the look-back of
 // each tile inside its own segment.

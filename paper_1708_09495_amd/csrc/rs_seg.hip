@@ -7,7 +7,9 @@
 //   scatter   segment ids into a queue ordered by decreasing class, so the
 //             longest segments start first (longest-processing-time order).
 // Sort (one persistent kernel): every workgroup pops the next queue entry
-// until the queue is empty and sorts that segment by itself:
+// until the queue is empty and sorts that segment by itself, unless the
+// shared rounds take it (the default, seg_shared_len: 10,241 .. 14,336 keys
+// and 16,385 .. 2^30 - 1 keys):
 //   length <= 16384  in LDS, with BTN, OET or the LDS radix sort as the
 //                    tuning table says for the length class;
 //   longer           with the shared rounds (the default), only segments of
@@ -21,8 +23,8 @@
 //                    offsets stay in LDS, so no tile waits on another
 //                    workgroup.
 // Segments are independent, so workgroups never wait on each other and every
-// workgroup leaves once the queue is exhausted.  The segments of 16,385 ..
-// 2^30 - 1 keys are then sorted together by the device-wide round's kernel
+// workgroup leaves once the queue is exhausted.  The segments the shared
+// rounds take are then sorted together by the device-wide round's kernel
 // over all their tiles (segos_run, in rs_lsd.hip).
 #include "rs_internal.hpp"
 #include "rs_small_dev.h"
@@ -336,7 +338,7 @@ __attribute__((amdgpu_waves_per_eu(4))) __global__ __launch_bounds__(SG_NT) void
             if (threadIdx.x == 0) atomicOr(status, STATUS_RANGE);
             continue;
         }
-        if (shared && L >= SEG_OS_MIN && L < SEG_OS_MAX) continue;  // sorted by the shared onesweep rounds
+        if (shared && seg_shared_len(L)) continue;  // sorted by the shared onesweep rounds
         if (L == 1) {
             if (threadIdx.x == 0) out[b] = in[b];
             continue;

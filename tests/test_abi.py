@@ -63,7 +63,7 @@ def test_host_side_queries(lib):
 def test_segmented_workspace_grows_with_keys_not_segments(lib):
     # the shared rounds' tables (look-back words and block sums, tile
     # descriptors, per-segment histograms) are bounded by the keys: at most
-    # n / 16,385 segments can be long enough to use them
+    # n / 10,241 segments can be long enough to use them
     lib.rs_workspace_bytes.restype = ctypes.c_size_t
     lib.rs_workspace_bytes.argtypes = [ctypes.c_int, ctypes.c_size_t, ctypes.c_int, ctypes.c_int,
                                        ctypes.c_int, ctypes.c_int, ctypes.c_size_t]

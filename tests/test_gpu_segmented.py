@@ -28,11 +28,13 @@ def _run(rs, keys, off, algo=0, inplace=False):
     return to_host(res, np.uint32)
 
 
-# (above 16,384 keys a segment is sorted by the onesweep rounds shared by
-# all workgroups, in tiles of 14,336 keys: 16,384 / 16,385 and whole /
-# ragged tile counts sit on either side of those edges)
-MIXED = [0, 1, 2, 3, 15, 16, 17, 63, 64, 65, 100, 255, 256, 1000, 4095, 4096, 8192, 8193, 16383,
-         16384, 16385, 20000, 40000, 65_535, 65_536, 71_680, 71_681, 100_000, 262_144, 0, 1]
+# (segments of 10,241 .. 14,336 keys and above 16,384 keys are sorted by the
+# onesweep rounds shared by all workgroups, in tiles of 14,336 keys: the
+# lengths on either side of 10,240 / 10,241, 14,336 / 14,337 and 16,384 /
+# 16,385, and whole / ragged tile counts, sit on either side of those edges)
+MIXED = [0, 1, 2, 3, 15, 16, 17, 63, 64, 65, 100, 255, 256, 1000, 4095, 4096, 8192, 8193, 10_240,
+         10_241, 14_336, 14_337, 16383, 16384, 16385, 20000, 40000, 65_535, 65_536, 71_680, 71_681,
+         100_000, 262_144, 0, 1]
 
 
 @pytest.mark.parametrize("algo", ["AUTO", "BTN", "OET", "LDS_RADIX", "LSD"])
