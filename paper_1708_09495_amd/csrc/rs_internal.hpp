@@ -156,6 +156,10 @@ constexpr bool seg_shared_len(uint64_t L) {
     return (L >= SEG_OS_MIN && L <= SEG_OS_TILE) || (L > SEG_SMALL_MAX && L < SEG_OS_MAX);
 }
 static_assert(SEG_OS_MIN <= SEG_OS_TILE && SEG_OS_TILE <= SEG_SMALL_MAX, "one tile, then the LDS capacity");
+static_assert(!seg_shared_len(10240) && seg_shared_len(10241) && seg_shared_len(14336) && !seg_shared_len(14337) &&
+                  !seg_shared_len(16384) && seg_shared_len(16385) && seg_shared_len((1ull << 30) - 1) &&
+                  !seg_shared_len(1ull << 30),
+              "the lengths the shared rounds take");
 struct SegTile {          // one tile of the large segments' rounds (32 bytes)
     int64_t lo;           // first position of its segment
     int64_t len;          // keys of its segment (0: no tile, the workgroup leaves)
