@@ -54,6 +54,12 @@ inline void prof(hipStream_t st, int kid, int phase) {
 }
 
 // ---- LSD radix sort (count-sort rounds, Section 3) -----------------------
+// Tile order across XCDs (see LsdPlan::nx): consecutive tiles per XCD, and
+// the per-round counters (one per XCD) kept CTR_STRIDE words apart.
+constexpr uint32_t XCD_CHUNK = 16;
+constexpr uint32_t CTR_STRIDE = 8;
+// The XCD count the tile order uses on the current device (0: one counter).
+uint32_t xcd_order_count();
 struct LsdPlan {
     size_t n = 0;
     int kb = 4, vb = 0;      // key / value bytes (kb = 2: 16-bit digit keys)
@@ -63,6 +69,13 @@ struct LsdPlan {
     int R = 256;             // 2^b
     int tile = 0;            // keys per workgroup tile
     size_t tiles = 0;
+    // Tile order across XCDs: nx = 0, tiles in the order workgroups arrive
+    // at one counter; nx > 0, chunks of XCD_CHUNK consecutive tiles per XCD
+    // (chunk k on XCD k mod nx), each XCD's workgroups taking its chunks'
+    // tiles in order from a counter of its own.  grid: workgroups launched
+    // (tiles, or nx > 0: padded to whole rounds of nx chunks).
+    uint32_t nx = 0;
+    size_t grid = 0;
     bool lb64 = false;       // 64-bit look-back words (n >= 2^30)
     size_t lb_words = 0;     // look-back words per pass (tiles * R)
     // workspace layout (byte offsets)
@@ -170,7 +183,8 @@ struct SegTile {          // one tile of the large segments' rounds (32 bytes)
 };
 struct SegOs {
     const SegTile* td = nullptr;         // per tile of the round's numbering (max_tiles)
-    const uint32_t* used = nullptr;      // tiles in use: workgroups numbered from here leave at once
+    const uint32_t* used = nullptr;      // tiles in use (the surplus workgroups leave at once)
+    uint32_t max_tiles = 0;              // tiles the look-back words are laid out for (the block sums follow)
     const uint32_t* hist = nullptr;      // per large segment: 4 rounds x 256 digit counts
 };
 struct SegPlan {

@@ -24,6 +24,8 @@
 // The paper's count exchange (2prg) is the look-back table: R words per
 // tile.  Per round HBM traffic is one read and one write of the keys (and
 // values); the histogram read is paid once for all rounds.
+#include <atomic>
+#include <cstdlib>
 #include <type_traits>
 
 #include "rs_dev.h"
@@ -368,7 +370,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MAXB <= 8 ? 
     void* __restrict__ vout0, uint64_t n, int shift, int bits, uint32_t* __restrict__ tile_ctr,
     LB* __restrict__ lb, const uint32_t* __restrict__ ghist, uint32_t* __restrict__ status,
     const Route* __restrict__ route, const void* __restrict__ vin2_ = nullptr,
-    void* __restrict__ vout2_ = nullptr, SegOs sg = SegOs{}) {
+    void* __restrict__ vout2_ = nullptr, SegOs sg = SegOs{}, uint32_t nx = 0) {
     using V = typename ValT<VB>::type;
     constexpr int RMAX = 1 << MAXB;
     constexpr int RLO = RMAX < 256 ? RMAX : 256;      // slots of the LDS match
@@ -442,20 +444,55 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MAXB <= 8 ? 
     const uint32_t dmask = (uint32_t)R - 1;
     const uint32_t lomask = (1u << lob) - 1;
 
+    // the XCD this workgroup runs on (the XCD order only; segment mode keeps
+    // the single counter: the order's extra registers spill there and cost
+    // more than the order saves)
+    uint32_t xcd = 0;
+    if constexpr (!SEG) {
+        if (nx) {
+            uint32_t xcc;
+            asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(xcc));
+            xcd = (xcc & 0xFu) % nx;
+        }
+    }
     // SEG: the grid covers a bound on the tiles; the workgroups numbered
     // past the tiles in use take no tile id (exactly as many workgroups as
     // tiles take one, so every tile id is taken)
     if constexpr (SEG)
         if (blockIdx.x >= *sg.used) return;
-    if (tid == 0) s_tile = atomicAdd(tile_ctr, 1u);
+    // Tile id.  Every tile a workgroup waits for in the look-back has a
+    // smaller id, and is already held by a running workgroup or will be
+    // taken by the next workgroup to start where it belongs:
+    //   nx = 0: ids in the order workgroups reach one counter;
+    //   nx > 0: chunks of XCD_CHUNK consecutive tiles per XCD, chunk k on XCD
+    //   k mod nx, each XCD's workgroups taking its tiles in order from the
+    //   XCD's own counter.  The hardware hands workgroup b to XCD b mod nx,
+    //   so each XCD runs exactly as many workgroups as its chunks hold tiles
+    //   (the grid covers whole rounds of nx chunks; tiles past the last key
+    //   end at once), and neighbouring tiles, whose digit runs share cache
+    //   lines at their ends, run on one XCD and write through one L2.
+    if (tid == 0) {
+        uint32_t t;
+        if (!SEG && nx) {
+            const uint32_t i = atomicAdd(tile_ctr + xcd, 1u);
+            t = ((i / XCD_CHUNK) * nx + xcd) * XCD_CHUNK + i % XCD_CHUNK;
+        } else {
+            t = atomicAdd(tile_ctr, 1u);
+        }
+        s_tile = t;
+    }
     if constexpr (!HALF)
         for (int i = tid; i < NW * R; i += NT) wcnt[i] = 0;
     for (int i = tid; i < (int)(MSKB / 8); i += NT) wmask[i] = 0;
     __syncthreads();
     const uint32_t tile = s_tile;
+    if constexpr (!SEG)
+        if ((uint64_t)tile * T >= n) return;  // past the last key (the XCD order's whole rounds)
     // per look-back block of LBB tiles and digit: the tiles counted so far
     // (bits 26 up) and the sum of their counts (LBB * 2^16 < 2^26)
-    uint32_t* __restrict__ bwsum = reinterpret_cast<uint32_t*>(lb + (size_t)gridDim.x * R);
+    // (after the tiles' words: n / T tiles, or in segment mode the bound)
+    const size_t ntl = SEG ? (size_t)sg.max_tiles : (size_t)((n + T - 1) / T);
+    uint32_t* __restrict__ bwsum = reinterpret_cast<uint32_t*>(lb + ntl * R);
     // SEG: the tiles of all segments in one numbering; a tile covers
     // positions [base, base + nvalid) of its segment [seg_lo, seg_lo +
     // seg_len), its look-back stops at the segment's first tile, and its
@@ -825,14 +862,14 @@ template <typename K, int VB, int MAXB, int ITEMS, typename LB, typename OFF, in
 hipError_t launch_pass(const LsdPlan& p, const void* src, void* dst, const void* vsrc, void* vdst,
                        int pass, unsigned char* ws, hipStream_t st, const Route* route,
                        const void* v2src = nullptr, void* v2dst = nullptr) {
-    uint32_t* ctr = reinterpret_cast<uint32_t*>(ws + p.off_ctr) + pass;
+    uint32_t* ctr = reinterpret_cast<uint32_t*>(ws + p.off_ctr) + (size_t)pass * CTR_STRIDE;
     LB* lb = reinterpret_cast<LB*>(ws + p.off_lb) + (size_t)pass * p.lb_words;
     const uint32_t* gh = reinterpret_cast<const uint32_t*>(ws + p.off_hist) + (size_t)pass * p.R;
     uint32_t* status = reinterpret_cast<uint32_t*>(ws + p.off_status);
     prof(st, p.kid_scatter, 0);
-    hipLaunchKernelGGL((k_onesweep<K, VB, MAXB, ITEMS, LB, OFF, VB2>), dim3((unsigned)p.tiles), dim3(NT),
+    hipLaunchKernelGGL((k_onesweep<K, VB, MAXB, ITEMS, LB, OFF, VB2>), dim3((unsigned)p.grid), dim3(NT),
                        0, st, (const K*)src, (K*)dst, vsrc, vdst, (uint64_t)p.n, pass * p.bits, p.bits,
-                       ctr, lb, gh, status, route, v2src, v2dst);
+                       ctr, lb, gh, status, route, v2src, v2dst, SegOs{}, p.nx);
     prof(st, p.kid_scatter, 1);
     return hipGetLastError();
 }
@@ -923,6 +960,32 @@ rs_status stream_copy(const void* in, void* out, size_t bytes, hipStream_t st) {
     return launch_status();
 }
 
+// The XCD order needs the hardware to hand workgroup b to XCD b mod nx, which
+// MI355X does with its 256 compute units in 8 XCDs (one partition); on any
+// other shape the rounds keep the single counter.  RS_XCD_ORDER=0 turns the
+// XCD order off.  Cached per device.
+uint32_t xcd_order_count() {
+    static std::atomic<int> cache[64];  // 0: not asked yet, else count + 1
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    int c = cache[dev].load(std::memory_order_relaxed);
+    if (c == 0) {
+        int cus = 0;
+        const char* e = getenv("RS_XCD_ORDER");
+        const bool off = e && e[0] == '0';
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+            (void)hipGetLastError();
+            cus = 0;
+        }
+        c = (!off && cus == 256) ? 8 + 1 : 1;
+        cache[dev].store(c, std::memory_order_relaxed);
+    }
+    return (uint32_t)(c - 1);
+}
+
 bool lsd_plan(size_t n, int kb, int vb, int bits, LsdPlan* p, int vb2, int items) {
     if ((kb != 4 && kb != 8) || (vb != 0 && vb != 4 && vb != 8) || bits < 1 || bits > 11) {
         // the only other shape: 16-bit digit keys, radix 2^8, 8-byte payload(s)
@@ -948,6 +1011,11 @@ bool lsd_plan(size_t n, int kb, int vb, int bits, LsdPlan* p, int vb2, int items
                    : (two_tiles && n < LSD_SMALL_N)           ? LSD_ITEMS_SMALL
                                                               : lsd_items(kb, vb, bits <= 8 ? 8 : 11));
     q.tiles = n ? (n + q.tile - 1) / q.tile : 0;
+    q.nx = xcd_order_count();
+    {
+        const size_t round = (size_t)q.nx * XCD_CHUNK;
+        q.grid = q.nx ? (q.tiles + round - 1) / round * round : q.tiles;
+    }
     q.lb64 = n >= (1ull << 30);
     // per round: the tiles' look-back words, then one 32-bit block sum per
     // look-back block of LBB tiles and digit
@@ -960,7 +1028,7 @@ bool lsd_plan(size_t n, int kb, int vb, int bits, LsdPlan* p, int vb2, int items
     q.off_status = off;
     off += ALIGN;
     q.off_ctr = off;
-    off += align_up(sizeof(uint32_t) * q.passes);
+    off += align_up(sizeof(uint32_t) * CTR_STRIDE * q.passes);
     q.off_hist = off;
     off += align_up(sizeof(uint32_t) * (size_t)q.passes * q.R);
     q.zero_bytes = off - q.off_status;
@@ -1253,15 +1321,17 @@ rs_status segos_run(const SegPlan& p, const uint32_t* in, uint32_t* out, uint32_
     SegOs sg;
     sg.td = td;
     sg.used = ttile + S;
+    sg.max_tiles = (uint32_t)p.max_tiles;
     sg.hist = hist;
+    const uint64_t grid = p.max_tiles;
     const uint32_t* src = in;
     for (int r = 0; r < 4; ++r) {
         uint32_t* dst = (r & 1) ? out : tmp;
         prof(st, KID_SEG_ROUND, 0);
-        hipLaunchKernelGGL((k_onesweep<uint32_t, 0, 8, 28, uint32_t, int32_t, 0, true>), dim3((unsigned)p.max_tiles),
-                           dim3(NT), 0, st, src, dst, nullptr, nullptr, (uint64_t)0, 8 * r, 8, ctr + r,
+        hipLaunchKernelGGL((k_onesweep<uint32_t, 0, 8, 28, uint32_t, int32_t, 0, true>), dim3((unsigned)grid),
+                           dim3(NT), 0, st, src, dst, nullptr, nullptr, (uint64_t)0, 8 * r, 8, ctr + (size_t)r * CTR_STRIDE,
                            lbw + (size_t)r * (p.max_tiles + p.max_blocks) * 256, nullptr, status, nullptr, nullptr,
-                           nullptr, sg);
+                           nullptr, sg, 0u);
         prof(st, KID_SEG_ROUND, 1);
         if ((rc = launch_status()) != RS_OK) return rc;
         src = dst;

@@ -368,8 +368,8 @@ bool seg_plan(uint64_t S, int64_t total, SegPlan* p, bool shared) {
     off += ALIGN;
     q.off_cnt = off;
     off += align_up(sizeof(uint32_t) * (2 * NCLASS + 1));
-    q.off_osctr = off;  // the four rounds' tile counters
-    off += align_up(sizeof(uint32_t) * 4);
+    q.off_osctr = off;  // the four rounds' tile counters (CTR_STRIDE apart: one per XCD)
+    off += align_up(sizeof(uint32_t) * 4 * CTR_STRIDE);
     q.zero_bytes = off - q.off_status;
     q.off_order = off;
     off += align_up(sizeof(uint32_t) * (S ? S : 1));
