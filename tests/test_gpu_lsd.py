@@ -279,3 +279,42 @@ def test_unaligned_views(rs, orc, kdt, offset):
         out = to_host(sort(view, radix_bits=8, algo=rs.RS_ALGO_LSD), kdt)
         assert rs.rs_get_stats().device_error == 0
         _check(out, orc.lsd(a[offset:], 8), "unaligned offset=%d n=%d" % (offset, n))
+
+
+_SINGLE_COUNTER = r"""
+import sys
+sys.path.insert(0, sys.argv[1])
+import numpy as np, torch
+import paper_1708_09495_amd as rs, gen, oracle
+n = (1 << 23) + 1237
+keys = gen.uniform_u32(gen.S0 + 44, n)
+out = rs.rs_sort_u32(torch.from_numpy(keys.view(np.int32)).cuda(), algo=rs.RS_ALGO_LSD)
+kv = gen.uniform_u32(gen.S0 + 45, 1 << 20)
+vals = np.arange(1 << 20, dtype=np.uint32)
+ko, vo = rs.rs_sort_kv(torch.from_numpy(kv.view(np.int32)).cuda(), torch.from_numpy(vals.view(np.int32)).cuda(),
+                       algo=rs.RS_ALGO_LSD)
+ok = np.array_equal(out.cpu().numpy().view(np.uint32), oracle.lsd(keys, 8))
+rk, rv = oracle.lsd(kv, 8, vals=vals)
+ok = ok and np.array_equal(ko.cpu().numpy().view(np.uint32), rk) and np.array_equal(vo.cpu().numpy().view(np.uint32), rv)
+ok = ok and rs.rs_get_stats().device_error == 0
+print("single-counter order matches the oracle" if ok else "MISMATCH", flush=True)
+sys.exit(0 if ok else 1)
+"""
+
+
+def test_single_counter_tile_order():
+    """The rounds' other tile order (one arrival counter, on parts that are
+    not 256 compute units in 8 XCDs, or with RS_XCD_ORDER=0), which the
+    process-wide setting keeps from the rest of this run: a child process
+    with RS_XCD_ORDER=0 sorts keys and key-value pairs, bit-exact against
+    the oracle."""
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    env = dict(os.environ, RS_XCD_ORDER="0")
+    print("case single-counter tile order (child process)", flush=True)
+    r = subprocess.run([sys.executable, "-c", _SINGLE_COUNTER, root], env=env, capture_output=True, text=True,
+                       timeout=240)
+    print(r.stdout[-2000:], r.stderr[-2000:])
+    assert r.returncode == 0
