@@ -27,6 +27,13 @@
  *     RS_ERR_INVALID.  Other overlaps are not allowed.
  *   - n = 0 is valid and enqueues nothing.
  *   - The library never aborts the process.
+ *   - The radix rounds take their tiles in an XCD-aware order (chunks of 16
+ *     neighbouring tiles per XCD, so that the cache lines neighbouring
+ *     tiles' outputs share meet in one L2) on devices of 256 compute units
+ *     in 8 XCDs, where the hardware hands workgroup b to XCD b mod 8; the
+ *     environment variable RS_XCD_ORDER=0 (read once per device and
+ *     process) keeps the order in which workgroups reach one counter.
+ *     Results are the same either way.
  */
 #ifndef RS_H
 #define RS_H
