@@ -211,7 +211,9 @@ const char* rs_status_string(rs_status s);
 
 /* Copies the calling thread's stats of its most recent call.  If that call
  * enqueued device work whose outcome the stats report (device_error, the
- * learned path's overflow counts), this synchronises that call's stream. */
+ * learned path's overflow counts), this synchronises that call's stream and
+ * reads them from that call's workspace, which must therefore still be
+ * allocated and not reused by other work. */
 rs_status rs_get_stats(rs_stats* out);
 
 /* ---- sorting without allocation ------------------------------------------ */

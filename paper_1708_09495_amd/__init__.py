@@ -9,6 +9,7 @@ from __future__ import annotations
 
 import ctypes
 import os
+import threading
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "librs.so")
@@ -179,9 +180,19 @@ def _check_dev(t, bytes_, what):
         raise ValueError("%s must be a contiguous CUDA tensor of %d-byte elements" % (what, bytes_))
 
 
+# rs_get_stats reads the device status word in the most recent call's
+# workspace: a workspace this binding allocates for a call is kept (per
+# thread) until the thread's next call, so that the stats stay readable
+# whatever is allocated in between.
+_tls = threading.local()
+
+
 def _workspace(need, ws, device):
     if ws is None:
         ws = _torch().empty(max(int(need), 1), dtype=_torch().uint8, device=device)
+        _tls.ws = ws
+    else:
+        _tls.ws = None
     return ws
 
 

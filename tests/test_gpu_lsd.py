@@ -318,3 +318,22 @@ def test_single_counter_tile_order():
                        timeout=240)
     print(r.stdout[-2000:], r.stderr[-2000:])
     assert r.returncode == 0
+
+
+def test_stats_survive_later_allocations(rs):
+    """rs_get_stats reads the status word in the last call's workspace: a
+    workspace the binding allocated itself stays alive until the thread's
+    next call, so allocations in between (which the caching allocator would
+    serve from freed memory) do not change what the stats report."""
+    import gen
+    import torch
+    for n, sort in ((8_389_383, lambda t: rs.rs_sort_u32(t, algo=rs.RS_ALGO_LSD)),
+                    (8_389_383, lambda t: rs.rs_sort_blocks_u32(t, algo=rs.RS_ALGO_BTN, p=64))):
+        t = torch.empty(n, dtype=torch.int32, device="cuda")
+        gen.uniform_u32_dev(gen.S0 + 46, t)
+        out = sort(t)
+        junk = [torch.full((m,), -1, dtype=torch.int32, device="cuda") for m in (n // 4, n // 2, n, 2 * n)]
+        torch.cuda.synchronize()
+        assert rs.rs_get_stats().device_error == 0
+        assert bool(torch.equal(torch.sort(t.to(torch.int64) & 0xFFFFFFFF).values, out.to(torch.int64) & 0xFFFFFFFF))
+        del t, out, junk
