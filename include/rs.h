@@ -175,7 +175,7 @@ rs_status rs_sort_blocks_u32(const uint32_t* in, uint32_t* out, size_t n, rs_alg
  * the paper's 68 G, one workgroup's radix sort of its run; unlike the
  * paper's 4 (n/p) g, a merge-split stage runs on every compute unit, so it
  * costs per key of the whole array.  The defaults are one MI355X's
- * calibration (local 3.74 ns, stage 1.88 ps per key + 28 us, 512 resident
+ * calibration (local 3.74 ns, stage 1.67 ps per key + 17.2 us, 512 resident
  * workgroups); `bench.py --workload blocks --mbsp` measures G and g. */
 typedef struct {
     double local_ns_per_key;   /* > 0                                        */

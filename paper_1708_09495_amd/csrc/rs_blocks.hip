@@ -22,8 +22,11 @@
 namespace rs {
 namespace {
 
-constexpr int MS_NT = 256;
-constexpr int MS_ITEMS = 16;
+// 8 outputs per thread: a shorter merge per thread after its co-rank search
+// (measured at 2^27 keys: 0.243 ms a stage against 0.285 with 256 x 16 and
+// 0.318 with 1,024 x 4)
+constexpr int MS_NT = 512;
+constexpr int MS_ITEMS = 8;
 constexpr uint32_t MS_C = MS_NT * MS_ITEMS;  // outputs per merge workgroup
 
 struct Stage {
@@ -157,9 +160,10 @@ uint32_t log2u(uint32_t p) {
 // ToG, a processor read as a workgroup).  Defaults: the calibration on one
 // MI355X by the BTN runs themselves -- a run's radix sort costs 68 G per key
 // with G = 55 ps (stable for runs of 2^19 to 2^23 keys), and a merge-split
-// stage, spread over the whole device, 1.88 ps per key of the array plus
-// 28 us (fitted on 2^23, 2^25 and 2^27 keys); 512 workgroups resident.
-static rs_block_model g_block_model = {3.74, 1.88, 28.0, 512};
+// stage, spread over the whole device, 1.67 ps per key of the array plus
+// 17.2 us (a least-squares fit, relative error, of the BTN and OET stage
+// times at 2^23, 2^25 and 2^27 keys); 512 workgroups resident.
+static rs_block_model g_block_model = {3.74, 1.67, 17.2, 512};
 
 const rs_block_model& block_model() { return g_block_model; }
 void block_model_set(const rs_block_model& m) { g_block_model = m; }

@@ -176,7 +176,7 @@ def test_block_model_default_p(lib):
     dflt = _Model()
     assert lib.rs_blocks_get_model(ctypes.byref(dflt)) == 0
     assert (dflt.local_ns_per_key, dflt.stage_ps_per_key, dflt.stage_fixed_us, dflt.resident_runs) == \
-        (3.74, 1.88, 28.0, 512)
+        (3.74, 1.67, 17.2, 512)
     BTN, OET = 2, 3
     try:
         models = [dflt, _Model(10.0, 0.5, 5.0, 64), _Model(1.0, 20.0, 100.0, 4096)]
