@@ -1011,7 +1011,9 @@ bool lsd_plan(size_t n, int kb, int vb, int bits, LsdPlan* p, int vb2, int items
                    : (two_tiles && n < LSD_SMALL_N)           ? LSD_ITEMS_SMALL
                                                               : lsd_items(kb, vb, bits <= 8 ? 8 : 11));
     q.tiles = n ? (n + q.tile - 1) / q.tile : 0;
-    q.nx = xcd_order_count();
+    // the XCD order once every XCD gets at least 8 chunks: with fewer tiles
+    // the chunks would crowd onto the first XCDs (32 tiles: two of eight)
+    q.nx = q.tiles >= (size_t)8 * XCD_CHUNK * 8 ? xcd_order_count() : 0;
     {
         const size_t round = (size_t)q.nx * XCD_CHUNK;
         q.grid = q.nx ? (q.tiles + round - 1) / round * round : q.tiles;

@@ -286,7 +286,7 @@ import sys
 sys.path.insert(0, sys.argv[1])
 import numpy as np, torch
 import paper_1708_09495_amd as rs, gen, oracle
-n = (1 << 23) + 1237
+n = (1 << 24) + 1237  # 1,171 tiles: the XCD order would be on
 keys = gen.uniform_u32(gen.S0 + 44, n)
 out = rs.rs_sort_u32(torch.from_numpy(keys.view(np.int32)).cuda(), algo=rs.RS_ALGO_LSD)
 kv = gen.uniform_u32(gen.S0 + 45, 1 << 20)
