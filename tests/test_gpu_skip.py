@@ -62,6 +62,25 @@ def test_keys(rs, orc, n):
                 _check(to_host(t, a.dtype), a, "%s: input untouched" % name)
 
 
+def test_keys_at_xcd_order_sizes(rs, orc):
+    """Skipped rounds where the rounds take their tiles in the XCD-aware
+    order (from 1,024 tiles: 2^24 + 3 keys are 1,171 tiles of uint32 keys
+    and 1,821 of uint64): skips at the start, the middle and the top, and
+    an odd count of rounds run, against the oracle."""
+    n = (1 << 24) + 3
+    rng = np.random.default_rng(47)
+    cases = _cases(rng, n)
+    for name in ("u64_below_2p32", "u32_fixed_top", "u32_fixed_mid", "u32_fixed_low"):
+        a = cases[name]
+        print("case skip keys %s n=%d" % (name, n), flush=True)
+        f = rs.rs_sort_u32 if a.dtype == np.uint32 else rs.rs_sort_u64
+        out = f(to_dev(a), algo=rs.RS_ALGO_AUTO)
+        st = rs.rs_get_stats()
+        assert st.device_error == 0
+        _check(to_host(out, a.dtype), orc.lsd(a, 8), "%s n=%d" % (name, n))
+        assert st.passes_skipped == _single_bin_rounds(orc, a, 8), name
+
+
 @pytest.mark.parametrize("bits", [8, 11])
 def test_kv(rs, orc, bits):
     rng = np.random.default_rng(43 + bits)
